@@ -1,0 +1,200 @@
+/*
+ * qilbm.h -- C ABI of a gfx950 (AMD Instinct MI355X) implementation of the
+ * quasi-incompressible phase-field lattice Boltzmann model of Yang & Guo,
+ * "A lattice Boltzmann method for binary fluids based on mass-conserved
+ * quasi-incompressible phase-field theory" (Sec. III, the two coupled LBEs).
+ *
+ * One coupled time step advances, on a D2Q9 lattice (dx = dt = 1):
+ *   - the order-parameter LBE for g_i, whose moment phi = sum_i g_i obeys the
+ *     Cahn-Hilliard equation with mobility lambda (Sec. III, g-LBE and its
+ *     equilibrium H_i + w_i phi s_i(u) and source G_i);
+ *   - the flow LBE for f_i, whose moments give the velocity u and the
+ *     hydrodynamic pressure p (Sec. III, f-LBE with equilibrium
+ *     w_i [p + c_s^2 rho s_i(u)] and source F_i carrying the force
+ *     F = -phi grad mu + F_b and the divergence source
+ *     -gamma div(lambda grad mu) of the quasi-incompressible model, Sec. II);
+ *   - isotropic central finite differences (gradient, Laplacian) of phi,
+ *     mu and p; mu = dpsi/dphi - kappa lap phi with the double-well psi
+ *     (Sec. II).
+ *
+ * Conventions
+ *   Lattice: nx columns (x, always periodic) by ny rows (y); node (x, y) has
+ *     linear index y*nx + x. A population set is [9][ny][nx] (direction
+ *     major), directions c_0 = (0,0), c_1..4 = (1,0),(0,1),(-1,0),(0,-1),
+ *     c_5..8 = (1,1),(-1,1),(-1,-1),(1,-1).
+ *   Order parameter: phi_A = 1 (fluid A), phi_B = 0 (fluid B).
+ *   Coefficients derived by the library: beta = 12 sigma / W and
+ *     kappa = 3 sigma W / 2 (from the interface-width and surface-tension
+ *     relations of Sec. II), lambda = M, alpha = M / (c_s^2 (tau_g - 1/2))
+ *     (Sec. III), gamma = (rho_A/rho_B - 1) (Sec. II with phi_B = 0).
+ *   Boundaries: LBM_BC_PERIODIC (both axes) or LBM_BC_WALLS_Y (half-way
+ *     bounce-back walls below row 0 and above row ny-1; stencils mirror the
+ *     boundary row into the ghost row).
+ *   Memory: every pointer marked _dev is device memory owned by the caller.
+ *     The library never allocates or frees device memory; all state lives
+ *     in the caller's workspace. The library owns only the host context.
+ *   Streams: every call enqueues its work on the context's HIP stream and
+ *     returns without synchronising, except lbm_mass (host output) and
+ *     lbm_adjoint_init (host output), which synchronise that stream.
+ *   Errors: every function returns an lbm_status; arguments are validated
+ *     before any device work, and nothing is enqueued when validation fails.
+ *     Kernel-launch failures return LBM_EDEVICE. No exception or abort
+ *     crosses the ABI.
+ *   Threads: a context is bound to one stream and is not thread-safe.
+ */
+#ifndef QILBM_H
+#define QILBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* invalid argument (checked on the host)            */
+  LBM_ENOMEM = -2,     /* workspace too small, host allocation failed       */
+  LBM_EDEVICE = -3,    /* HIP error while enqueueing or synchronising       */
+  LBM_EDIVERGED = -4,  /* non-finite total returned by lbm_mass             */
+  LBM_ESTATE = -5      /* call not valid in the context's current state     */
+} lbm_status;
+
+typedef enum {
+  LBM_FP64 = 0,        /* populations stored and computed in binary64       */
+  LBM_FP32 = 1,        /* populations stored and computed in binary32       */
+  LBM_FP16_STORE = 2   /* f_0..8 and g_1..8 stored as binary16 scaled by a
+                          power of two per direction, g_0 as binary32;
+                          arithmetic in binary32                            */
+} lbm_precision;
+
+typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_WALLS_Y = 1 } lbm_bc;
+
+/* lbm_params.flags */
+#define LBM_FLAG_NO_GAMMA 1u  /* drop the gamma (quasi-incompressible) terms
+                                 from F_i and p: the same LBE in the form of
+                                 an incompressible model, for ablations    */
+#define LBM_FLAG_UNFUSED  2u  /* run the step as four separate kernels that
+                                 materialise phi, mu and p (same results up
+                                 to rounding; used for cross-checks)        */
+
+typedef struct {
+  int32_t nx, ny;         /* lattice size; nx >= 3, ny >= 3                  */
+  double rho_A, rho_B;    /* densities of fluid A (phi = 1) and B (phi = 0) */
+  double sigma;           /* surface tension, > 0                            */
+  double W;               /* interface width in lattice units, > 0          */
+  double M;               /* mobility lambda of the Cahn-Hilliard eq., > 0  */
+  double tau_f, tau_g;    /* relaxation times, > 1/2                         */
+  double gx, gy;          /* gravity: body force F_b = (rho - rho_ref)(gx, gy) */
+  double rho_ref;         /* reference density of the body force           */
+  int32_t bc;             /* lbm_bc                                          */
+  int32_t precision;      /* lbm_precision                                   */
+  uint32_t flags;         /* LBM_FLAG_*                                      */
+} lbm_params;
+
+typedef struct lbm_ctx lbm_ctx;
+
+/* Bytes of device workspace lbm_init needs for these parameters (0 when
+ * the parameters are invalid). The workspace holds two population buffers
+ * in the storage precision, the phi/mu/p scratch fields and the reduction
+ * partials. */
+size_t lbm_workspace_bytes(const lbm_params* params);
+
+/* Derived coefficients (beta, kappa, lambda, alpha, gamma, d rho/d phi) of
+ * Sec. II-III for these parameters, into out[6] (host memory). */
+lbm_status lbm_coefficients(const lbm_params* params, double out[6]);
+
+/* Creates a context at t = 0 from the initial order parameter phi0_dev
+ * (FP64, [ny][nx], device). The initial pre-collision state has u = 0 and
+ * p = 0, hence f_i = f_i^eq = 0, and g_i = H_i(phi0, mu0) with
+ * mu0 = mu(phi0) (Sec. III equilibria), so that sum_i g_i = phi0.
+ * workspace_dev: caller-owned, at least lbm_workspace_bytes(params) bytes,
+ * 256-byte aligned, kept alive until lbm_destroy. stream: a hipStream_t
+ * (NULL = default stream). On success *out receives the context. */
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* params,
+                    void* workspace_dev, size_t workspace_bytes,
+                    const double* phi0_dev, void* stream);
+
+/* Advances nsteps >= 0 coupled time steps (Sec. III: moments, chemical
+ * potential, force, velocity, pressure, both BGK collisions with their
+ * source terms, streaming). Asynchronous. */
+lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
+
+/* Macroscopic fields at the current time t (Sec. III moments): phi, rho,
+ * u = (ux, uy), p and mu, each FP64 [ny][nx] device arrays; any pointer
+ * may be NULL to skip that field. Asynchronous. */
+lbm_status lbm_moments(lbm_ctx* ctx, double* phi_dev, double* rho_dev,
+                       double* ux_dev, double* uy_dev, double* p_dev,
+                       double* mu_dev);
+
+/* Lattice totals at time t into out[4] (host): sum phi, sum rho,
+ * sum rho ux, sum rho uy, accumulated in FP64 in a fixed order (run-to-run
+ * bitwise reproducible). Synchronises the stream. Returns LBM_EDIVERGED
+ * when a total is not finite (out is still written). The mass of the
+ * quasi-incompressible model is conserved exactly by the scheme (Sec. II,
+ * local mass conservation), so sum phi and sum rho are invariants. */
+lbm_status lbm_mass(lbm_ctx* ctx, double out[4]);
+
+/* Current pre-collision populations in canonical FP64 layout,
+ * f_dev and g_dev each [9][ny][nx] (device). Asynchronous. */
+lbm_status lbm_get_state(lbm_ctx* ctx, double* f_dev, double* g_dev);
+
+/* Replaces the current pre-collision populations (canonical FP64 layout);
+ * values are rounded to the storage precision. Keeps the time counter. */
+lbm_status lbm_set_state(lbm_ctx* ctx, const double* f_dev, const double* g_dev);
+
+/* Raw snapshot of the internal state buffer in the storage precision
+ * (lbm_state_bytes bytes): exact save/restore for checkpointing.
+ * lbm_load_raw also sets the time counter to t. Asynchronous. */
+size_t lbm_state_bytes(const lbm_ctx* ctx);
+lbm_status lbm_save_raw(lbm_ctx* ctx, void* dst_dev);
+lbm_status lbm_load_raw(lbm_ctx* ctx, const void* src_dev, int64_t t);
+
+/* Time counter (number of steps taken since lbm_init). */
+int64_t lbm_time(const lbm_ctx* ctx);
+
+/* Rebinds the context to another HIP stream. */
+lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
+
+/* ---------------------------------------------------------------- adjoint
+ * Reverse-mode derivative of a loss L(phi_K) of the final order parameter
+ * with respect to sigma, M and the initial phi0 (not in the paper: a
+ * hand-written transpose of every stage of the step above). The caller
+ * drives checkpoint-and-recompute: it restores forward states with
+ * lbm_load_raw / lbm_step and hands each forward state s_t to
+ * lbm_adjoint_step in decreasing t. Parameter cotangents accumulate in FP64.
+ *
+ * lbm_adjoint_workspace_bytes: device bytes for the adjoint (two adjoint
+ *   population sets, forward/adjoint scratch fields, FP64 partials).
+ * lbm_adjoint_begin: binds the adjoint workspace and seeds the cotangent of
+ *   the state at the final time: gbar_i = dL/dphi_K (all i), fbar = 0;
+ *   clears the sigma/M accumulators. dL_dphi_dev: FP64 [ny][nx].
+ * lbm_adjoint_step: given the raw forward state s_t (layout of
+ *   lbm_save_raw, storage precision of the context) replaces the cotangent
+ *   of s_{t+1} by that of s_t = (d s_{t+1} / d s_t)^T applied to it, and
+ *   adds (d s_{t+1} / d sigma)^T and (d s_{t+1} / d M)^T to the
+ *   accumulators. Asynchronous.
+ * lbm_adjoint_init: pulls the cotangent of s_0 back through the initial
+ *   state map phi0 -> (f = 0, g = H_i(phi0, mu0)): writes dL/dphi0 (FP64
+ *   [ny][nx], device) and out[2] = (dL/dsigma, dL/dM) totals (host).
+ *   Synchronises the stream.
+ */
+size_t lbm_adjoint_workspace_bytes(const lbm_params* params);
+lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* adj_workspace_dev,
+                             size_t adj_workspace_bytes,
+                             const double* dL_dphi_dev);
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state_dev);
+lbm_status lbm_adjoint_init(lbm_ctx* ctx, double* dL_dphi0_dev, double out[2]);
+
+/* Frees the host context (never the caller's device memory). NULL is a no-op. */
+void lbm_destroy(lbm_ctx* ctx);
+
+/* Static description of a status code. */
+const char* lbm_strerror(lbm_status status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* QILBM_H */
