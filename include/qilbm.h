@@ -157,6 +157,14 @@ int64_t lbm_time(const lbm_ctx* ctx);
 /* Rebinds the context to another HIP stream. */
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 
+/* Launch shape of the fused step kernel: rows per workgroup segment
+ * (0 = automatic, about 2048 workgroups). Results do not depend on it. */
+lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t seg_rows);
+
+/* Current fused launch shape into out[4] (host): strips of 256 columns,
+ * segments per strip, rows per segment, threads per workgroup. */
+lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
+
 /* ---------------------------------------------------------------- adjoint
  * Reverse-mode derivative of a loss L(phi_K) of the final order parameter
  * with respect to sigma, M and the initial phi0 (not in the paper: a
@@ -176,16 +184,33 @@ lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
  *   adds (d s_{t+1} / d sigma)^T and (d s_{t+1} / d M)^T to the
  *   accumulators. Asynchronous.
  * lbm_adjoint_init: pulls the cotangent of s_0 back through the initial
- *   state map phi0 -> (f = 0, g = H_i(phi0, mu0)): writes dL/dphi0 (FP64
+ *   state map phi0 -> (f = 0, g = H_i(phi0, mu0)) given the same phi0_dev
+ *   (FP64 [ny][nx], device) that lbm_init received: writes dL/dphi0 (FP64
  *   [ny][nx], device) and out[2] = (dL/dsigma, dL/dM) totals (host).
  *   Synchronises the stream.
+ * The adjoint arithmetic runs in the compute type (FP64 for LBM_FP64,
+ * FP32 otherwise); the parameter sums are FP64 and run-to-run reproducible.
+ * lbm_adjoint_step and lbm_adjoint_init return LBM_ESTATE before
+ * lbm_adjoint_begin.
  */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* params);
 lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* adj_workspace_dev,
                              size_t adj_workspace_bytes,
                              const double* dL_dphi_dev);
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state_dev);
-lbm_status lbm_adjoint_init(lbm_ctx* ctx, double* dL_dphi0_dev, double out[2]);
+lbm_status lbm_adjoint_init(lbm_ctx* ctx, const double* phi0_dev, double* dL_dphi0_dev,
+                            double out[2]);
+
+/* Direct access to the adjoint state, for callers with a general state
+ * cotangent and for per-step checks. lbm_adjoint_set replaces the current
+ * cotangent of the pre-collision state by (fbar, gbar) (canonical FP64
+ * [9][ny][nx] each, device) and clears the parameter accumulators.
+ * lbm_adjoint_get copies the current cotangent out (same layout) and writes
+ * out[2] = (dL/dsigma, dL/dM) accumulated by the adjoint steps so far
+ * (without the initial-state map); synchronises the stream. Both return
+ * LBM_ESTATE before lbm_adjoint_begin. */
+lbm_status lbm_adjoint_set(lbm_ctx* ctx, const double* fbar_dev, const double* gbar_dev);
+lbm_status lbm_adjoint_get(lbm_ctx* ctx, double* fbar_dev, double* gbar_dev, double out[2]);
 
 /* Frees the host context (never the caller's device memory). NULL is a no-op. */
 void lbm_destroy(lbm_ctx* ctx);

@@ -1,0 +1,723 @@
+// Adjoint of one coupled step of the quasi-incompressible phase-field LBE
+// (reverse mode; not part of the paper, which defines only the forward
+// scheme of Sec. III). Each kernel is the transpose of one forward stage,
+// taken in reverse order:
+//
+//   forward                                  adjoint
+//   phi, S, j  <- populations                 gbar_i += phibar, fbar_i += Sbar + c_i.jbar
+//   mu <- phi (bulk + lap)                    phibar += mubar bulk'(phi) + lap^T(-kappa mubar)
+//   grad rho, grad mu, D <- stencils          grad^T, lap^T of their cotangents
+//   F, u, p <- node values                    node-local transposes
+//   grad p <- p                               pbar += grad^T(gradp_bar)
+//   collision (BGK + F_i, G_i)                node-local Jacobian transpose
+//   streaming (pull, bounce-back)             gather from the neighbour it fed
+//
+// The adjoint populations are kept in the canonical pre-collision layout
+// ([18][ny][nx], compute type); the forward state s_t is recomputed by the
+// caller and handed in raw (pull layout). Cotangents of beta, kappa, lambda,
+// alpha are summed in FP64 in a fixed block order (run-to-run reproducible)
+// and turned into dL/dsigma and dL/dM at the end (beta, kappa are
+// proportional to sigma at fixed W; lambda = M and alpha = M/(c_s^2 (tau_g - 1/2))).
+#include <math.h>
+
+#include "../../include/qilbm.h"
+#include "qilbm_adjoint.hpp"
+#include "qilbm_internal.hpp"
+
+namespace qilbm {
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+template <typename T>
+struct AF {
+  T* base;
+  int64_t Ns;
+  __device__ __forceinline__ T* operator[](int k) const { return base + (int64_t)k * Ns; }
+};
+
+// ------------------------------------------------ transposed stencils
+// grad psi(y) = 3 sum_i w_i c_i psi(nb(y, c_i)) and
+// lap psi(y) = 6 sum_i w_i (psi(nb(y, c_i)) - psi(y)), with nb the periodic
+// or mirrored neighbour. Their transposes, evaluated as gathers: node x
+// collects from every (y, i) with nb(y, c_i) = x. Off the walls that is
+// y = x - c_i; on a wall row the mirrored ghost adds y = x - (c_ix, 0) for
+// the directions pointing into the wall.
+template <typename T, int I>
+__device__ __forceinline__ void gt_term(const T* vx, const T* vy, const T* ws, int x, int y,
+                                        const Geom& g, T& gacc, T& lacc) {
+  constexpr int cx = CXS(I), cy = CYS(I);
+  const T w3 = T(3.0 * WGT(I)), w6 = T(6.0 * WGT(I));
+  int ys = y - cy;
+  bool ok = true;
+  if (ys < 0 || ys >= g.ny) {
+    if (g.walls) ok = false;
+    else ys = ys < 0 ? ys + g.ny : ys - g.ny;
+  }
+  if (ok) {
+    const int64_t n = (int64_t)ys * g.nx + wrap_x(x - cx, g.nx);
+    if (vx) gacc += w3 * (T(cx) * vx[n] + T(cy) * vy[n]);
+    if (ws) lacc += w6 * ws[n];
+  }
+  if (g.walls && ((cy == -1 && y == 0) || (cy == 1 && y == g.ny - 1))) {
+    const int64_t n = (int64_t)y * g.nx + wrap_x(x - cx, g.nx);
+    if (vx) gacc += w3 * (T(cx) * vx[n] + T(cy) * vy[n]);
+    if (ws) lacc += w6 * ws[n];
+  }
+}
+
+// Returns grad^T(vx, vy)(x) + lap^T(ws)(x); either input may be null.
+template <typename T>
+__device__ __forceinline__ T stencil_T(const T* vx, const T* vy, const T* ws, int x, int y,
+                                       const Geom& g) {
+  T gacc = T(0), lacc = T(0);
+  gt_term<T, 1>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 2>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 3>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 4>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 5>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 6>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 7>(vx, vy, ws, x, y, g, gacc, lacc);
+  gt_term<T, 8>(vx, vy, ws, x, y, g, gacc, lacc);
+  if (ws) lacc -= T(10.0 / 3.0) * ws[(int64_t)y * g.nx + x];
+  return gacc + lacc;
+}
+
+// ----------------------------------------------- block partial accumulation
+// Each block adds its FP64 partial to its own slot: the order of additions
+// is fixed by the launch shape, so the totals are reproducible.
+__device__ __forceinline__ double wsum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+__device__ __forceinline__ void block_add(double v, int slot, double* acc_part) {
+  __shared__ double red[4];
+  v = wsum(v);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) acc_part[4 * blockIdx.x + slot] += (red[0] + red[1]) + (red[2] + red[3]);
+  __syncthreads();
+}
+
+// ----------------------------------------------------------------- kernels
+__global__ __launch_bounds__(256) void k_fill_zero(double* p, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    p[i] = 0.0;
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_seed(const double* __restrict__ dphi, T* __restrict__ hat,
+                                                  Geom g) {
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const T v = T(dphi[n]);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      hat[(int64_t)i * g.Ns + n] = T(0);
+      hat[(int64_t)(9 + i) * g.Ns + n] = v;
+    }
+  }
+}
+
+// Cotangent of the post-collision population i at x: the pre-collision
+// population it becomes at t+1 is i at x + c_i, or opp(i) at x itself when
+// x + c_i lies beyond a wall.
+template <typename T, int I>
+__device__ __forceinline__ T post_hat(const T* hat, int koff, int x, int y, const Geom& g) {
+  constexpr int cx = CXS(I), cy = CYS(I);
+  int yd = y + cy;
+  if (yd < 0 || yd >= g.ny) {
+    if (g.walls) return hat[(int64_t)(koff + OPP(I)) * g.Ns + (int64_t)y * g.nx + x];
+    yd = yd < 0 ? yd + g.ny : yd - g.ny;
+  }
+  return hat[(int64_t)(koff + I) * g.Ns + (int64_t)yd * g.nx + wrap_x(x + cx, g.nx)];
+}
+
+template <typename T, int I = 0>
+__device__ __forceinline__ void post_hat9(const T* hat, int koff, int x, int y, const Geom& g,
+                                          T v[9]) {
+  if constexpr (I < 9) {
+    v[I] = post_hat<T, I>(hat, koff, x, y, g);
+    post_hat9<T, I + 1>(hat, koff, x, y, g, v);
+  }
+}
+
+// Transpose of collide_node at one node. Inputs: forward node state m,
+// grad p, the populations' post-collision cotangents fh, gh. Outputs: the
+// direct cotangents of the pre-collision populations (in fh, gh) and the
+// cotangents of the node quantities the collision read.
+template <typename T>
+struct NodeBar {
+  T p, rho, ux, uy, Fx, Fy, drx, dry, D, phi, mu, dpx, dpy, alpha;
+};
+
+template <typename T>
+__device__ __forceinline__ void collide_node_T(T fh[9], T gh[9], const Macro<T>& m, T dpx, T dpy,
+                                               const Coef<T>& c, NodeBar<T>& nb) {
+  const T usq = m.ux * m.ux + m.uy * m.uy;
+  const T gpre = -T(3) * m.phi / m.rho;
+  const T hx = dpx - m.Fx, hy = dpy - m.Fy;
+  const T r3 = m.rho * T(1.0 / 3.0);
+  const T dx3 = m.drx * T(1.0 / 3.0), dy3 = m.dry * T(1.0 / 3.0);
+  T b_p = 0, b_r3 = 0, b_Fx = 0, b_Fy = 0, b_dx3 = 0, b_dy3 = 0, b_src1 = 0, b_amu = 0;
+  T b_phi = 0, b_gpre = 0, b_hx = 0, b_hy = 0, b_ux = 0, b_uy = 0, b_usq = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T w = T(WGT(i));
+    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
+    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
+    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T gm = T(1) + s;
+    const T a = fh[i] * c.inv_tau_f;   // cotangent of f^eq_i
+    const T b = fh[i] * c.kf;          // cotangent of F_i
+    const T a2 = gh[i] * c.inv_tau_g;  // cotangent of g^eq_i
+    const T b2 = gh[i] * c.kg;         // cotangent of G_i
+    fh[i] = fh[i] * (T(1) - c.inv_tau_f);
+    gh[i] = gh[i] * (T(1) - c.inv_tau_g);
+    T b_s = 0, b_gm = 0, b_cxu = 0, b_cyu = 0;
+    // f^eq = w (p + r3 s)
+    b_p += a * w;
+    b_r3 += a * w * s;
+    b_s += a * w * r3;
+    // F_i = w (cxu (gm Fx + s dx3) + cyu (gm Fy + s dy3) + src1)
+    const T bw = b * w;
+    b_cxu += bw * (gm * m.Fx + s * dx3);
+    b_cyu += bw * (gm * m.Fy + s * dy3);
+    b_gm += bw * (cxu * m.Fx + cyu * m.Fy);
+    b_Fx += bw * cxu * gm;
+    b_Fy += bw * cyu * gm;
+    b_s += bw * (cxu * dx3 + cyu * dy3);
+    b_dx3 += bw * cxu * s;
+    b_dy3 += bw * cyu * s;
+    b_src1 += bw;
+    // g^eq = H_i + w phi s, H_0 = phi - (5/9) amu, H_i = w amu
+    b_phi += a2 * w * s;
+    b_s += a2 * w * m.phi;
+    if (i == 0) {
+      b_phi += a2;
+      b_amu -= T(1.0 - 4.0 / 9.0) * a2;
+    } else {
+      b_amu += w * a2;
+    }
+    // G_i = gpre w gm E, E = cxu hx + cyu hy
+    const T E = cxu * hx + cyu * hy;
+    b_gpre += b2 * w * gm * E;
+    b_gm += b2 * gpre * w * E;
+    const T bE = b2 * gpre * w * gm;
+    b_cxu += bE * hx;
+    b_cyu += bE * hy;
+    b_hx += bE * cxu;
+    b_hy += bE * cyu;
+    // gm = 1 + s; s = 3 cu + 4.5 cu^2 - 1.5 usq; cu = c.u; cxu = c_x - ux
+    b_s += b_gm;
+    const T b_cu = b_s * (T(3) + T(9) * cu);
+    b_usq -= T(1.5) * b_s;
+    b_ux += b_cu * T(CXS(i)) - b_cxu;
+    b_uy += b_cu * T(CYS(i)) - b_cyu;
+  }
+  b_ux += T(2) * m.ux * b_usq;
+  b_uy += T(2) * m.uy * b_usq;
+  nb.p = b_p;
+  nb.rho = b_r3 * T(1.0 / 3.0) - b_src1 * c.gamma * m.D * T(1.0 / 3.0) +
+           b_gpre * T(3) * m.phi / (m.rho * m.rho);
+  nb.D = -b_src1 * m.rho * c.gamma * T(1.0 / 3.0);
+  nb.drx = b_dx3 * T(1.0 / 3.0);
+  nb.dry = b_dy3 * T(1.0 / 3.0);
+  nb.mu = c.alpha * b_amu;
+  nb.alpha = m.mu * b_amu;
+  nb.phi = b_phi - T(3) * b_gpre / m.rho;
+  nb.dpx = b_hx;
+  nb.dpy = b_hy;
+  nb.Fx = b_Fx - b_hx;
+  nb.Fy = b_Fy - b_hy;
+  nb.ux = b_ux;
+  nb.uy = b_uy;
+}
+
+// Forward node state (same arithmetic as the forward kernels).
+template <int P>
+__device__ __forceinline__ void fwd_node(const Pop<P>& in, const typename PrecT<P>::T* phi,
+                                         const typename PrecT<P>::T* mu, int x, int y,
+                                         const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                                         typename PrecT<P>::T f[9], Macro<typename PrecT<P>::T>& m,
+                                         typename PrecT<P>::T& S, typename PrecT<P>::T& jx,
+                                         typename PrecT<P>::T& jy, typename PrecT<P>::T& gmux,
+                                         typename PrecT<P>::T& gmuy, typename PrecT<P>::T& lapmu) {
+  using T = typename PrecT<P>::T;
+#define QILBM_PULLF(I)                   \
+  {                                      \
+    int plane;                           \
+    int64_t idx;                         \
+    pull_src<I>(x, y, g, plane, idx);    \
+    f[I] = in.ld(plane, idx);            \
+  }
+  QILBM_PULLF(0) QILBM_PULLF(1) QILBM_PULLF(2) QILBM_PULLF(3) QILBM_PULLF(4)
+  QILBM_PULLF(5) QILBM_PULLF(6) QILBM_PULLF(7) QILBM_PULLF(8)
+#undef QILBM_PULLF
+  S = f[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) S += f[i];
+  jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
+  jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+  T v[3][3], gphx, gphy, lapphi;
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = phi[row + wrap_x(x + dx, g.nx)];
+  }
+  stencil(v, gphx, gphy, lapphi);
+  const T ph = v[1][1];
+#pragma unroll
+  for (int dy = -1; dy <= 1; ++dy) {
+    const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
+#pragma unroll
+    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = mu[row + wrap_x(x + dx, g.nx)];
+  }
+  stencil(v, gmux, gmuy, lapmu);
+  macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
+}
+
+// AK1: collision transpose. Reads the cotangent of s_{t+1}; writes the
+// direct population cotangents and the node-quantity cotangents.
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_collide(Pop<P> in, const typename PrecT<P>::T* __restrict__ fphi,
+                                                     const typename PrecT<P>::T* __restrict__ fmu,
+                                                     const typename PrecT<P>::T* __restrict__ fp,
+                                                     const typename PrecT<P>::T* __restrict__ hat,
+                                                     typename PrecT<P>::T* __restrict__ direct,
+                                                     AF<typename PrecT<P>::T> af, double* acc_part,
+                                                     Coef<typename PrecT<P>::T> c, Geom g) {
+  using T = typename PrecT<P>::T;
+  double alpha_acc = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+    T f[9], S, jx, jy, gmux, gmuy, lapmu;
+    Macro<T> m;
+    fwd_node<P>(in, fphi, fmu, x, y, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
+    T v[3][3], dpx, dpy, lapp;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = fp[row + wrap_x(x + dx, g.nx)];
+    }
+    stencil(v, dpx, dpy, lapp);
+    T fh[9], gh[9];
+    post_hat9<T>(hat, 0, x, y, g, fh);
+    post_hat9<T>(hat, 9, x, y, g, gh);
+    NodeBar<T> nb;
+    collide_node_T(fh, gh, m, dpx, dpy, c, nb);
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      direct[(int64_t)i * g.Ns + n] = fh[i];
+      direct[(int64_t)(9 + i) * g.Ns + n] = gh[i];
+    }
+    af[A_DPX][n] = nb.dpx;
+    af[A_DPY][n] = nb.dpy;
+    af[A_P][n] = nb.p;
+    af[A_RHO][n] = nb.rho;
+    af[A_UX][n] = nb.ux;
+    af[A_UY][n] = nb.uy;
+    af[A_FX][n] = nb.Fx;
+    af[A_FY][n] = nb.Fy;
+    af[A_DRX][n] = nb.drx;
+    af[A_DRY][n] = nb.dry;
+    af[A_D][n] = nb.D;
+    af[A_PHI1][n] = nb.phi;
+    af[A_MU1][n] = nb.mu;
+    alpha_acc += double(nb.alpha);
+  }
+  block_add(alpha_acc, AP_ALPHA, acc_part);
+}
+
+// AK2: transposes of grad p (gathered), the pressure, velocity, force, D,
+// grad rho and rho definitions.
+template <int P>
+__global__ __launch_bounds__(256) void k_adj_macro(Pop<P> in, const typename PrecT<P>::T* __restrict__ fphi,
+                                                   const typename PrecT<P>::T* __restrict__ fmu,
+                                                   AF<typename PrecT<P>::T> af, double* acc_part,
+                                                   Coef<typename PrecT<P>::T> c, Geom g) {
+  using T = typename PrecT<P>::T;
+  double lam_acc = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+    T f[9], S, jx, jy, gmux, gmuy, lapmu;
+    Macro<T> m;
+    fwd_node<P>(in, fphi, fmu, x, y, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
+    T b_p = af[A_P][n] + stencil_T<T>(af[A_DPX], af[A_DPY], nullptr, x, y, g);
+    T b_rho = af[A_RHO][n], b_ux = af[A_UX][n], b_uy = af[A_UY][n];
+    T b_Fx = af[A_FX][n], b_Fy = af[A_FY][n], b_drx = af[A_DRX][n], b_dry = af[A_DRY][n];
+    T b_D = af[A_D][n], b_phi = af[A_PHI1][n];
+    // p = S + (ux drx + uy dry - gamma rho D) / 6
+    const T b_S = b_p;
+    b_ux += b_p * m.drx * T(1.0 / 6.0);
+    b_uy += b_p * m.dry * T(1.0 / 6.0);
+    b_drx += b_p * m.ux * T(1.0 / 6.0);
+    b_dry += b_p * m.uy * T(1.0 / 6.0);
+    b_rho -= b_p * c.gamma * m.D * T(1.0 / 6.0);
+    b_D -= b_p * c.gamma * m.rho * T(1.0 / 6.0);
+    // u = (j + F / 6) * inv, inv = 3 / rho
+    const T inv = T(3) / m.rho;
+    const T b_jx = b_ux * inv, b_jy = b_uy * inv;
+    b_Fx += b_ux * inv * T(1.0 / 6.0);
+    b_Fy += b_uy * inv * T(1.0 / 6.0);
+    const T b_inv = b_ux * (jx + m.Fx * T(1.0 / 6.0)) + b_uy * (jy + m.Fy * T(1.0 / 6.0));
+    b_rho -= b_inv * inv / m.rho;
+    // F = -phi grad mu + (rho - rho_ref) g
+    b_phi -= b_Fx * gmux + b_Fy * gmuy;
+    const T b_gmux = -m.phi * b_Fx, b_gmuy = -m.phi * b_Fy;
+    b_rho += b_Fx * c.gx + b_Fy * c.gy;
+    // D = lambda lap mu; grad rho = drho grad phi; rho = rho_B + drho phi
+    lam_acc += double(b_D) * double(lapmu);
+    af[A_S][n] = b_S;
+    af[A_JX][n] = b_jx;
+    af[A_JY][n] = b_jy;
+    af[A_GMUX][n] = b_gmux;
+    af[A_GMUY][n] = b_gmuy;
+    af[A_LMU][n] = c.lam * b_D;
+    af[A_GPHX][n] = c.drho * b_drx;
+    af[A_GPHY][n] = c.drho * b_dry;
+    af[A_PHI2][n] = b_phi + c.drho * b_rho;
+  }
+  block_add(lam_acc, AP_LAMBDA, acc_part);
+}
+
+// AK3: mu cotangent (node part + grad^T + lap^T), then the chemical
+// potential mu = 4 beta (phi-1) phi (phi-1/2) - kappa lap phi.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_mu(const T* __restrict__ fphi, AF<T> af,
+                                                double* acc_part, Coef<T> c, Geom g) {
+  double beta_acc = 0.0, kappa_acc = 0.0;
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+    const T b_mu = af[A_MU1][n] + stencil_T<T>(af[A_GMUX], af[A_GMUY], af[A_LMU], x, y, g);
+    T v[3][3], gx, gy, lapphi;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = fphi[row + wrap_x(x + dx, g.nx)];
+    }
+    stencil(v, gx, gy, lapphi);
+    const T ph = v[1][1];
+    const T dbulk = c.beta4 * (T(3) * ph * ph - T(3) * ph + T(0.5));
+    af[A_PHI3][n] = af[A_PHI2][n] + b_mu * dbulk;
+    af[A_LPHI][n] = -c.kappa * b_mu;
+    beta_acc += double(b_mu) * 4.0 * double((ph - T(1)) * ph * (ph - T(0.5)));
+    kappa_acc -= double(b_mu) * double(lapphi);
+  }
+  block_add(beta_acc, AP_BETA, acc_part);
+  block_add(kappa_acc, AP_KAPPA, acc_part);
+}
+
+// AK4: phi cotangent (grad^T of grad phi's, lap^T of lap phi's), then the
+// moments: gbar_i = direct + phibar, fbar_i = direct + Sbar + c_i.jbar.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_final(const T* __restrict__ direct, AF<T> af,
+                                                   T* __restrict__ hat_out, Geom g) {
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+    const T b_phi = af[A_PHI3][n] + stencil_T<T>(af[A_GPHX], af[A_GPHY], af[A_LPHI], x, y, g);
+    const T bS = af[A_S][n], bjx = af[A_JX][n], bjy = af[A_JY][n];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      hat_out[(int64_t)i * g.Ns + n] =
+          direct[(int64_t)i * g.Ns + n] + bS + T(CXS(i)) * bjx + T(CYS(i)) * bjy;
+      hat_out[(int64_t)(9 + i) * g.Ns + n] = direct[(int64_t)(9 + i) * g.Ns + n] + b_phi;
+    }
+  }
+}
+
+// Initial-state map transpose (FP64): s_0 = (0, H_i(phi0, mu0)),
+// mu0 = 4 beta (phi0-1) phi0 (phi0-1/2) - kappa lap phi0.
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_init_local(const double* __restrict__ phi0,
+                                                        const T* __restrict__ hat,
+                                                        double* __restrict__ lphi_bar,
+                                                        double* __restrict__ phi_bar,
+                                                        double* acc_part, Coef<double> c, Geom g) {
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+    double v[3][3], gx, gy, lap;
+#pragma unroll
+    for (int dy = -1; dy <= 1; ++dy) {
+      const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
+#pragma unroll
+      for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = phi0[row + wrap_x(x + dx, g.nx)];
+    }
+    stencil(v, gx, gy, lap);
+    const double ph = v[1][1];
+    const double mu0 = mu_bulk(ph, c) - c.kappa * lap;
+    double b_amu = -(1.0 - 4.0 / 9.0) * double(hat[(int64_t)9 * g.Ns + n]);
+#pragma unroll
+    for (int i = 1; i < 9; ++i) b_amu += WGT(i) * double(hat[(int64_t)(9 + i) * g.Ns + n]);
+    const double b_mu = c.alpha * b_amu;
+    acc[AP_ALPHA] += mu0 * b_amu;
+    acc[AP_BETA] += b_mu * 4.0 * (ph - 1.0) * ph * (ph - 0.5);
+    acc[AP_KAPPA] -= b_mu * lap;
+    phi_bar[n] = double(hat[(int64_t)9 * g.Ns + n]) +
+                 b_mu * c.beta4 * (3.0 * ph * ph - 3.0 * ph + 0.5);
+    lphi_bar[n] = -c.kappa * b_mu;
+  }
+  block_add(acc[AP_BETA], AP_BETA, acc_part);
+  block_add(acc[AP_KAPPA], AP_KAPPA, acc_part);
+  block_add(acc[AP_ALPHA], AP_ALPHA, acc_part);
+}
+
+__global__ __launch_bounds__(256) void k_adj_init_final(const double* __restrict__ lphi_bar,
+                                                        const double* __restrict__ phi_bar,
+                                                        double* __restrict__ out, Geom g) {
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+    out[n] = phi_bar[n] + stencil_T<double>(nullptr, nullptr, lphi_bar, x, y, g);
+  }
+}
+
+// Canonical FP64 [9][N] pair <-> adjoint population planes [18][Ns].
+template <typename T>
+__global__ __launch_bounds__(256) void k_hat_from(const double* __restrict__ f,
+                                                  const double* __restrict__ gg, T* __restrict__ hat,
+                                                  Geom g) {
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      hat[(int64_t)i * g.Ns + n] = T(f[(int64_t)i * g.N + n]);
+      hat[(int64_t)(9 + i) * g.Ns + n] = T(gg[(int64_t)i * g.N + n]);
+    }
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_hat_to(const T* __restrict__ hat, double* __restrict__ f,
+                                                double* __restrict__ gg, Geom g) {
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
+       n += (int64_t)gridDim.x * 256) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f[(int64_t)i * g.N + n] = double(hat[(int64_t)i * g.Ns + n]);
+      gg[(int64_t)i * g.N + n] = double(hat[(int64_t)(9 + i) * g.Ns + n]);
+    }
+  }
+}
+
+// ------------------------------------------------------------------ host
+template <typename T>
+Coef<T> coef_of(const CtxView& v) {
+  const lbm_params* p = v.prm;
+  Coef<T> k;
+  k.beta4 = T(4.0 * v.beta);
+  k.kappa = T(v.kappa);
+  k.lam = T(v.lam);
+  k.alpha = T(v.alpha);
+  k.gamma = T(v.gamma);
+  k.drho = T(v.drho);
+  k.rho_B = T(p->rho_B);
+  k.rho_ref = T(p->rho_ref);
+  k.gx = T(p->gx);
+  k.gy = T(p->gy);
+  k.inv_tau_f = T(1.0 / p->tau_f);
+  k.inv_tau_g = T(1.0 / p->tau_g);
+  k.kf = T(1.0 - 0.5 / p->tau_f);
+  k.kg = T(1.0 - 0.5 / p->tau_g);
+  return k;
+}
+
+struct AdjLayout {
+  size_t hat0, hat1, direct, fld, afld, part, acc, total;
+  int nred;
+};
+
+AdjLayout adj_layout(const lbm_params* p) {
+  const int64_t N = (int64_t)p->nx * p->ny;
+  const int64_t Ns = (N + 255) / 256 * 256;
+  const size_t ts = p->precision == LBM_FP64 ? 8 : 4;
+  AdjLayout L;
+  L.nred = (int)((N + 255) / 256);
+  if (L.nred > 2048) L.nred = 2048;
+  const size_t pops = up(18 * (size_t)Ns * ts);
+  L.hat0 = 0;
+  L.hat1 = L.hat0 + pops;
+  L.direct = L.hat1 + pops;
+  L.fld = L.direct + pops;
+  // the initial-state transpose uses two FP64 planes of the field area
+  const size_t fb = up(3 * (size_t)Ns * (ts > 8 ? ts : 8));
+  L.afld = L.fld + fb;
+  L.part = L.afld + up((size_t)A_NFIELDS * Ns * ts);
+  L.acc = L.part + up((size_t)L.nred * 4 * 8);
+  L.total = L.acc + up(8 * 8);
+  return L;
+}
+
+template <int P>
+lbm_status adj_step_p(const CtxView& v, const void* fwd) {
+  using T = typename PrecT<P>::T;
+  AdjointState& a = *v.adj;
+  const Geom& g = v.geom;
+  const Coef<T> k = coef_of<T>(v);
+  T* phi = (T*)a.fld;
+  T* mu = phi + g.Ns;
+  T* p = mu + g.Ns;
+  hipError_t e = launch_fields<P>(fwd, phi, mu, k, g, v.stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  e = launch_macro<P>(fwd, phi, mu, p, MomentOut{}, k, g, v.stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  Pop<P> in{(char*)fwd, g.Ns};
+  AF<T> af{(T*)a.afld, g.Ns};
+  const T* hin = (const T*)a.hat[a.cur];
+  T* hout = (T*)a.hat[a.cur ^ 1];
+  T* dir = (T*)a.direct;
+  const dim3 grid(a.nred), blk(256);
+  hipLaunchKernelGGL(k_adj_collide<P>, grid, blk, 0, v.stream, in, (const T*)phi, (const T*)mu,
+                     (const T*)p, hin, dir, af, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_macro<P>, grid, blk, 0, v.stream, in, (const T*)phi, (const T*)mu, af,
+                     a.part, k, g);
+  hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, (const T*)phi, af, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, (const T*)dir, af, hout, g);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  a.cur ^= 1;
+  return LBM_OK;
+}
+
+template <typename T>
+lbm_status adj_init_t(const CtxView& v, const double* phi0, double* dphi0, double out[2]) {
+  AdjointState& a = *v.adj;
+  const Geom& g = v.geom;
+  const Coef<double> k = coef_of<double>(v);
+  double* lphi = (double*)a.fld;
+  double* phib = lphi + g.Ns;
+  const dim3 grid(a.nred), blk(256);
+  hipLaunchKernelGGL(k_adj_init_local<T>, grid, blk, 0, v.stream, phi0, (const T*)a.hat[a.cur],
+                     lphi, phib, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_init_final, grid, blk, 0, v.stream, (const double*)lphi,
+                     (const double*)phib, dphi0, g);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  if (launch_sum_partials(a.part, a.nred, 4, a.acc + 4, v.stream) != hipSuccess)
+    return LBM_EDEVICE;
+  double tot[4];
+  if (hipMemcpyAsync(tot, a.acc + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, v.stream) !=
+      hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(v.stream) != hipSuccess) return LBM_EDEVICE;
+  const lbm_params* p = v.prm;
+  // beta, kappa proportional to sigma (W fixed); lambda = M, alpha proportional to M.
+  out[0] = (tot[AP_BETA] * v.beta + tot[AP_KAPPA] * v.kappa) / p->sigma;
+  out[1] = tot[AP_LAMBDA] + tot[AP_ALPHA] * v.alpha / p->M;
+  return LBM_OK;
+}
+
+}  // namespace
+}  // namespace qilbm
+
+using namespace qilbm;
+
+extern "C" {
+
+size_t lbm_adjoint_workspace_bytes(const lbm_params* params) {
+  if (!params || lbm_workspace_bytes(params) == 0) return 0;
+  return adj_layout(params).total;
+}
+
+lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* ws, size_t bytes, const double* dL_dphi) {
+  if (!ctx || !ws || !dL_dphi) return LBM_EINVAL;
+  if ((uintptr_t)ws % ALIGN != 0) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  const AdjLayout L = adj_layout(v.prm);
+  if (bytes < L.total) return LBM_ENOMEM;
+  AdjointState& a = *v.adj;
+  a.ws = (char*)ws;
+  a.bytes = bytes;
+  a.hat[0] = a.ws + L.hat0;
+  a.hat[1] = a.ws + L.hat1;
+  a.cur = 0;
+  a.direct = a.ws + L.direct;
+  a.fld = a.ws + L.fld;
+  a.afld = a.ws + L.afld;
+  a.part = (double*)(a.ws + L.part);
+  a.acc = (double*)(a.ws + L.acc);
+  a.nred = L.nred;
+  a.active = true;
+  const Geom& g = v.geom;
+  hipLaunchKernelGGL(k_fill_zero, dim3(a.nred), dim3(256), 0, v.stream, a.part,
+                     (int64_t)a.nred * 4);
+  if (v.prm->precision == LBM_FP64)
+    hipLaunchKernelGGL(k_adj_seed<double>, dim3(a.nred), dim3(256), 0, v.stream, dL_dphi,
+                       (double*)a.hat[0], g);
+  else
+    hipLaunchKernelGGL(k_adj_seed<float>, dim3(a.nred), dim3(256), 0, v.stream, dL_dphi,
+                       (float*)a.hat[0], g);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state) {
+  if (!ctx || !fwd_state) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  if (!v.adj->active) return LBM_ESTATE;
+  switch (v.prm->precision) {
+    case LBM_FP64: return adj_step_p<P_F64>(v, fwd_state);
+    case LBM_FP32: return adj_step_p<P_F32>(v, fwd_state);
+    default: return adj_step_p<P_F16>(v, fwd_state);
+  }
+}
+
+lbm_status lbm_adjoint_init(lbm_ctx* ctx, const double* phi0, double* dphi0, double out[2]) {
+  if (!ctx || !phi0 || !dphi0 || !out) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  if (!v.adj->active) return LBM_ESTATE;
+  if (v.prm->precision == LBM_FP64) return adj_init_t<double>(v, phi0, dphi0, out);
+  return adj_init_t<float>(v, phi0, dphi0, out);
+}
+
+lbm_status lbm_adjoint_set(lbm_ctx* ctx, const double* fbar, const double* gbar) {
+  if (!ctx || !fbar || !gbar) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  AdjointState& a = *v.adj;
+  if (!a.active) return LBM_ESTATE;
+  hipLaunchKernelGGL(k_fill_zero, dim3(a.nred), dim3(256), 0, v.stream, a.part,
+                     (int64_t)a.nred * 4);
+  if (v.prm->precision == LBM_FP64)
+    hipLaunchKernelGGL(k_hat_from<double>, dim3(a.nred), dim3(256), 0, v.stream, fbar, gbar,
+                       (double*)a.hat[a.cur], v.geom);
+  else
+    hipLaunchKernelGGL(k_hat_from<float>, dim3(a.nred), dim3(256), 0, v.stream, fbar, gbar,
+                       (float*)a.hat[a.cur], v.geom);
+  return hipGetLastError() == hipSuccess ? LBM_OK : LBM_EDEVICE;
+}
+
+lbm_status lbm_adjoint_get(lbm_ctx* ctx, double* fbar, double* gbar, double out[2]) {
+  if (!ctx || !fbar || !gbar || !out) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  AdjointState& a = *v.adj;
+  if (!a.active) return LBM_ESTATE;
+  if (v.prm->precision == LBM_FP64)
+    hipLaunchKernelGGL(k_hat_to<double>, dim3(a.nred), dim3(256), 0, v.stream,
+                       (const double*)a.hat[a.cur], fbar, gbar, v.geom);
+  else
+    hipLaunchKernelGGL(k_hat_to<float>, dim3(a.nred), dim3(256), 0, v.stream,
+                       (const float*)a.hat[a.cur], fbar, gbar, v.geom);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  if (launch_sum_partials(a.part, a.nred, 4, a.acc + 4, v.stream) != hipSuccess)
+    return LBM_EDEVICE;
+  double tot[4];
+  if (hipMemcpyAsync(tot, a.acc + 4, 4 * sizeof(double), hipMemcpyDeviceToHost, v.stream) !=
+      hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(v.stream) != hipSuccess) return LBM_EDEVICE;
+  out[0] = (tot[AP_BETA] * v.beta + tot[AP_KAPPA] * v.kappa) / v.prm->sigma;
+  out[1] = tot[AP_LAMBDA] + tot[AP_ALPHA] * v.alpha / v.prm->M;
+  return LBM_OK;
+}
+
+}  // extern "C"

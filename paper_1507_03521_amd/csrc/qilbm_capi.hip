@@ -1,0 +1,346 @@
+// C ABI of the quasi-incompressible phase-field LBE library (include/qilbm.h).
+// Host code only: argument validation, derivation of the model coefficients,
+// workspace layout, and dispatch of the kernels on the context's stream.
+#include <math.h>
+#include <new>
+#include <string.h>
+
+#include "../../include/qilbm.h"
+#include "qilbm_adjoint.hpp"
+#include "qilbm_internal.hpp"
+
+using namespace qilbm;
+
+struct lbm_ctx {
+  lbm_params prm;
+  double beta, kappa, lam, alpha, gamma, drho;
+  Geom geom;
+  hipStream_t stream;
+  char* ws;
+  size_t ws_bytes;
+  char* pop[2];
+  int cur;
+  char* fields;       // phi, mu, p scratch (compute type, Ns elements each)
+  double* part;       // reduction partials, 4 per block
+  int nred;
+  double* red_out;    // 8 doubles
+  int64_t t;
+  int seg_rows;
+  int64_t pbytes;
+  AdjointState adj;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool finite_all(const lbm_params* p) {
+  const double v[] = {p->rho_A, p->rho_B, p->sigma, p->W, p->M, p->tau_f, p->tau_g,
+                      p->gx,    p->gy,    p->rho_ref};
+  for (double d : v)
+    if (!isfinite(d)) return false;
+  return true;
+}
+
+bool valid(const lbm_params* p) {
+  if (!p) return false;
+  if (p->nx < 3 || p->ny < 3) return false;
+  if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)1 << 34) return false;
+  if (!finite_all(p)) return false;
+  if (!(p->rho_A > 0.0) || !(p->rho_B > 0.0)) return false;
+  if (!(p->sigma > 0.0) || !(p->W > 0.0) || !(p->M > 0.0)) return false;
+  if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) return false;
+  if (p->bc != LBM_BC_PERIODIC && p->bc != LBM_BC_WALLS_Y) return false;
+  if (p->precision < LBM_FP64 || p->precision > LBM_FP16_STORE) return false;
+  if (p->flags & ~(uint32_t)(LBM_FLAG_NO_GAMMA | LBM_FLAG_UNFUSED)) return false;
+  return true;
+}
+
+Geom make_geom(const lbm_params* p) {
+  Geom g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.walls = p->bc == LBM_BC_WALLS_Y;
+  g.N = (int64_t)p->nx * p->ny;
+  g.Ns = (g.N + 255) / 256 * 256;
+  return g;
+}
+
+// Coefficients of Sec. II-III with phi_A = 1, phi_B = 0:
+// beta = 12 sigma / W, kappa = 3 sigma W / 2 (from the interface width
+// W = sqrt(8 kappa / beta) and sigma = sqrt(2 kappa beta) / 6),
+// lambda = M, alpha = lambda / (c_s^2 (tau_g - 1/2)),
+// gamma = rho_A / rho_B - 1, d rho / d phi = rho_A - rho_B.
+void derive(const lbm_params* p, double out[6]) {
+  out[0] = 12.0 * p->sigma / p->W;
+  out[1] = 1.5 * p->sigma * p->W;
+  out[2] = p->M;
+  out[3] = p->M / ((p->tau_g - 0.5) / 3.0);
+  out[4] = (p->flags & LBM_FLAG_NO_GAMMA) ? 0.0 : p->rho_A / p->rho_B - 1.0;
+  out[5] = p->rho_A - p->rho_B;
+}
+
+struct Layout {
+  size_t pop0, pop1, fields, part, red, total;
+  int nred;
+};
+
+Layout layout(const lbm_params* p) {
+  const Geom g = make_geom(p);
+  Layout L;
+  const size_t pb = up((size_t)pop_bytes(p->precision, g.Ns));
+  L.nred = (int)((g.N + 255) / 256);
+  if (L.nred > 2048) L.nred = 2048;
+  L.pop0 = 0;
+  L.pop1 = L.pop0 + pb;
+  L.fields = L.pop1 + pb;
+  L.part = L.fields + up(3 * (size_t)g.Ns * 8);
+  L.red = L.part + up((size_t)L.nred * 4 * 8);
+  L.total = L.red + up(8 * 8);
+  return L;
+}
+
+template <typename T>
+Coef<T> coef_t(const lbm_ctx* c) {
+  Coef<T> k;
+  k.beta4 = T(4.0 * c->beta);
+  k.kappa = T(c->kappa);
+  k.lam = T(c->lam);
+  k.alpha = T(c->alpha);
+  k.gamma = T(c->gamma);
+  k.drho = T(c->drho);
+  k.rho_B = T(c->prm.rho_B);
+  k.rho_ref = T(c->prm.rho_ref);
+  k.gx = T(c->prm.gx);
+  k.gy = T(c->prm.gy);
+  k.inv_tau_f = T(1.0 / c->prm.tau_f);
+  k.inv_tau_g = T(1.0 / c->prm.tau_g);
+  k.kf = T(1.0 - 0.5 / c->prm.tau_f);
+  k.kg = T(1.0 - 0.5 / c->prm.tau_g);
+  return k;
+}
+
+lbm_status st(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+char* phi_f(lbm_ctx* c) { return c->fields; }
+char* mu_f(lbm_ctx* c) { return c->fields + c->geom.Ns * 8; }
+char* p_f(lbm_ctx* c) { return c->fields + 2 * c->geom.Ns * 8; }
+
+template <int P>
+lbm_status step_p(lbm_ctx* c, int64_t n) {
+  using T = typename PrecT<P>::T;
+  const Coef<T> k = coef_t<T>(c);
+  const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
+  const FusedShape sh = fused_shape(c->geom, c->seg_rows);
+  for (int64_t s = 0; s < n; ++s) {
+    hipError_t e;
+    if (unfused)
+      e = launch_step_unfused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], phi_f(c), mu_f(c), p_f(c), k,
+                                 c->geom, c->stream);
+    else
+      e = launch_step_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh, c->stream);
+    if (e != hipSuccess) return LBM_EDEVICE;
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status moments_p(lbm_ctx* c, const MomentOut& mo) {
+  using T = typename PrecT<P>::T;
+  const Coef<T> k = coef_t<T>(c);
+  hipError_t e = launch_fields<P>(c->pop[c->cur], phi_f(c), mu_f(c), k, c->geom, c->stream);
+  if (e != hipSuccess) return LBM_EDEVICE;
+  return st(launch_macro<P>(c->pop[c->cur], phi_f(c), mu_f(c), nullptr, mo, k, c->geom, c->stream));
+}
+
+template <int P>
+lbm_status mass_p(lbm_ctx* c) {
+  using T = typename PrecT<P>::T;
+  return st(launch_mass<P>(c->pop[c->cur], phi_f(c), mu_f(c), c->part, c->nred, c->red_out,
+                           coef_t<T>(c), c->geom, c->stream));
+}
+
+}  // namespace
+
+// Precision dispatch: calls FN<P>(args...) for the context's precision.
+#define QILBM_DISPATCH(prec, FN, ...)                  \
+  ((prec) == LBM_FP64   ? FN<P_F64>(__VA_ARGS__)       \
+   : (prec) == LBM_FP32 ? FN<P_F32>(__VA_ARGS__)       \
+                        : FN<P_F16>(__VA_ARGS__))
+
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* params) {
+  if (!valid(params)) return 0;
+  return layout(params).total;
+}
+
+lbm_status lbm_coefficients(const lbm_params* params, double out[6]) {
+  if (!valid(params) || !out) return LBM_EINVAL;
+  derive(params, out);
+  return LBM_OK;
+}
+
+lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev,
+                    size_t workspace_bytes, const double* phi0_dev, void* stream) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!valid(params) || !workspace_dev || !phi0_dev) return LBM_EINVAL;
+  if ((uintptr_t)workspace_dev % ALIGN != 0) return LBM_EINVAL;
+  const Layout L = layout(params);
+  if (workspace_bytes < L.total) return LBM_ENOMEM;
+  lbm_ctx* c = new (std::nothrow) lbm_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->prm = *params;
+  double d[6];
+  derive(params, d);
+  c->beta = d[0];
+  c->kappa = d[1];
+  c->lam = d[2];
+  c->alpha = d[3];
+  c->gamma = d[4];
+  c->drho = d[5];
+  c->geom = make_geom(params);
+  c->stream = (hipStream_t)stream;
+  c->ws = (char*)workspace_dev;
+  c->ws_bytes = workspace_bytes;
+  c->pop[0] = c->ws + L.pop0;
+  c->pop[1] = c->ws + L.pop1;
+  c->cur = 0;
+  c->fields = c->ws + L.fields;
+  c->part = (double*)(c->ws + L.part);
+  c->nred = L.nred;
+  c->red_out = (double*)(c->ws + L.red);
+  c->t = 0;
+  c->seg_rows = 0;
+  c->pbytes = pop_bytes(params->precision, c->geom.Ns);
+  Coef<double> k = coef_t<double>(c);
+  const hipError_t e = QILBM_DISPATCH(params->precision, launch_init, phi0_dev, c->pop[0], k,
+                                      c->geom, c->stream);
+  if (e != hipSuccess) {
+    delete c;
+    return LBM_EDEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps);
+}
+
+lbm_status lbm_moments(lbm_ctx* c, double* phi, double* rho, double* ux, double* uy, double* p,
+                       double* mu) {
+  if (!c) return LBM_EINVAL;
+  MomentOut mo;
+  mo.phi = phi;
+  mo.rho = rho;
+  mo.ux = ux;
+  mo.uy = uy;
+  mo.p = p;
+  mo.mu = mu;
+  return QILBM_DISPATCH(c->prm.precision, moments_p, c, mo);
+}
+
+lbm_status lbm_mass(lbm_ctx* c, double out[4]) {
+  if (!c || !out) return LBM_EINVAL;
+  lbm_status s = QILBM_DISPATCH(c->prm.precision, mass_p, c);
+  if (s != LBM_OK) return s;
+  if (hipMemcpyAsync(out, c->red_out, 4 * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_EDEVICE;
+  for (int k = 0; k < 4; ++k)
+    if (!isfinite(out[k])) return LBM_EDIVERGED;
+  return LBM_OK;
+}
+
+lbm_status lbm_get_state(lbm_ctx* c, double* f, double* g) {
+  if (!c || !f || !g) return LBM_EINVAL;
+  return st(QILBM_DISPATCH(c->prm.precision, launch_to_canonical, c->pop[c->cur], f, g, c->geom,
+                           c->stream));
+}
+
+lbm_status lbm_set_state(lbm_ctx* c, const double* f, const double* g) {
+  if (!c || !f || !g) return LBM_EINVAL;
+  return st(QILBM_DISPATCH(c->prm.precision, launch_from_canonical, f, g, c->pop[c->cur], c->geom,
+                           c->stream));
+}
+
+size_t lbm_state_bytes(const lbm_ctx* c) { return c ? (size_t)c->pbytes : 0; }
+
+lbm_status lbm_save_raw(lbm_ctx* c, void* dst) {
+  if (!c || !dst) return LBM_EINVAL;
+  return st(hipMemcpyAsync(dst, c->pop[c->cur], c->pbytes, hipMemcpyDeviceToDevice, c->stream));
+}
+
+lbm_status lbm_load_raw(lbm_ctx* c, const void* src, int64_t t) {
+  if (!c || !src || t < 0) return LBM_EINVAL;
+  c->t = t;
+  return st(hipMemcpyAsync(c->pop[c->cur], src, c->pbytes, hipMemcpyDeviceToDevice, c->stream));
+}
+
+int64_t lbm_time(const lbm_ctx* c) { return c ? c->t : -1; }
+
+lbm_status lbm_set_stream(lbm_ctx* c, void* stream) {
+  if (!c) return LBM_EINVAL;
+  c->stream = (hipStream_t)stream;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_launch(lbm_ctx* c, int32_t seg_rows) {
+  if (!c || seg_rows < 0) return LBM_EINVAL;
+  c->seg_rows = seg_rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
+  if (!c || !out) return LBM_EINVAL;
+  const FusedShape sh = fused_shape(c->geom, c->seg_rows);
+  out[0] = sh.nstrips;
+  out[1] = sh.nseg;
+  out[2] = sh.seg_rows;
+  out[3] = sh.threads;
+  return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx* c) { delete c; }
+
+const char* lbm_strerror(lbm_status s) {
+  switch (s) {
+    case LBM_OK: return "success";
+    case LBM_EINVAL: return "invalid argument";
+    case LBM_ENOMEM: return "workspace too small or host allocation failed";
+    case LBM_EDEVICE: return "HIP runtime error";
+    case LBM_EDIVERGED: return "non-finite lattice total (diverged)";
+    case LBM_ESTATE: return "call not valid in the current state";
+  }
+  return "unknown status";
+}
+
+}  // extern "C"
+
+// ------------------------------------------------------------------ adjoint
+// The adjoint entry points live in qilbm_adjoint.hip; they reach the context
+// through these accessors.
+namespace qilbm {
+CtxView ctx_view(lbm_ctx* c) {
+  CtxView v;
+  v.prm = &c->prm;
+  v.beta = c->beta;
+  v.kappa = c->kappa;
+  v.lam = c->lam;
+  v.alpha = c->alpha;
+  v.gamma = c->gamma;
+  v.drho = c->drho;
+  v.geom = c->geom;
+  v.stream = c->stream;
+  v.adj = &c->adj;
+  v.pbytes = c->pbytes;
+  return v;
+}
+}  // namespace qilbm

@@ -1,0 +1,225 @@
+// Device-side building blocks of the quasi-incompressible phase-field LBE
+// step (Yang & Guo, Sec. III) for gfx950: D2Q9 tables, derived
+// coefficients, population storage formats, pull-streaming addressing with
+// half-way bounce-back, the isotropic stencils and the per-node collision.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <hip/hip_fp16.h>
+#include <stdint.h>
+
+namespace qilbm {
+
+// ------------------------------------------------------------------ lattice
+// D2Q9 (Sec. III): c_0 = 0; c_1..4 axis-aligned at angles (i-1) pi/2;
+// c_5..8 diagonal at (2i-1) pi/4. Weights 4/9, 1/9, 1/36; c_s^2 = 1/3.
+__host__ __device__ constexpr int CXS(int i) {
+  return i == 1 || i == 5 || i == 8 ? 1 : (i == 3 || i == 6 || i == 7 ? -1 : 0);
+}
+__host__ __device__ constexpr int CYS(int i) {
+  return i == 2 || i == 5 || i == 6 ? 1 : (i == 4 || i == 7 || i == 8 ? -1 : 0);
+}
+__host__ __device__ constexpr int OPP(int i) {
+  return i == 0 ? 0 : (i <= 4 ? ((i + 1) & 3) + 1 : ((i - 3) & 3) + 5);
+}
+__host__ __device__ constexpr double WGT(int i) {
+  return i == 0 ? 4.0 / 9.0 : (i <= 4 ? 1.0 / 9.0 : 1.0 / 36.0);
+}
+static_assert(OPP(1) == 3 && OPP(2) == 4 && OPP(3) == 1 && OPP(4) == 2, "opp");
+static_assert(OPP(5) == 7 && OPP(6) == 8 && OPP(7) == 5 && OPP(8) == 6, "opp");
+
+// ------------------------------------------------------------- coefficients
+// Everything the step needs, derived on the host in FP64 (Sec. II-III) and
+// rounded once to the compute type T.
+template <typename T>
+struct Coef {
+  T beta4;      // 4 beta (bulk chemical potential 4 beta (phi-1) phi (phi-1/2))
+  T kappa;      // gradient-energy coefficient
+  T lam;        // mobility lambda
+  T alpha;      // alpha of H_i
+  T gamma;      // quasi-incompressibility coefficient (0 for the ablation)
+  T drho;       // d rho / d phi
+  T rho_B;      // density at phi = 0
+  T rho_ref;    // reference density of the body force
+  T gx, gy;     // gravity
+  T inv_tau_f, inv_tau_g;
+  T kf, kg;     // 1 - 1 / (2 tau)
+};
+
+struct Geom {
+  int nx, ny;
+  int walls;    // 1: bounce-back walls below row 0 and above row ny-1
+  int64_t N;    // nx * ny
+  int64_t Ns;   // plane stride in elements (N rounded up to 256)
+};
+
+// ----------------------------------------------------------- storage formats
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_F16 = 2 };
+
+// Power-of-two scale of binary16 plane i (f_i and g_i, i >= 1; also f_0):
+// 2^14 times the power of two nearest 1/w_i, so that populations of size
+// ~ w_i * 1e-2 sit well inside the normal binary16 range.
+__host__ __device__ constexpr float H_SCALE(int i) {
+  return i == 0 ? 32768.0f : (i <= 4 ? 131072.0f : 524288.0f);
+}
+__host__ __device__ constexpr float H_INV(int i) {
+  return i == 0 ? (1.0f / 32768.0f) : (i <= 4 ? (1.0f / 131072.0f) : (1.0f / 524288.0f));
+}
+
+template <int P> struct PrecT;
+template <> struct PrecT<P_F64> { using T = double; };
+template <> struct PrecT<P_F32> { using T = float; };
+template <> struct PrecT<P_F16> { using T = float; };
+
+// Bytes of one population buffer (18 planes).
+__host__ __device__ inline int64_t pop_bytes(int P, int64_t Ns) {
+  return P == P_F64 ? 18 * Ns * 8 : (P == P_F32 ? 18 * Ns * 4 : 17 * Ns * 2 + Ns * 4);
+}
+
+// Plane k in 0..17: f_0..f_8 are k = 0..8, g_0..g_8 are k = 9..17.
+// F16 layout: f planes (binary16), then g_0 (binary32), then g_1..8 (binary16).
+template <int P>
+struct Pop {
+  char* base;
+  int64_t Ns;
+  using T = typename PrecT<P>::T;
+
+  __device__ __forceinline__ T ld(int k, int64_t idx) const {
+    if constexpr (P == P_F64) {
+      return reinterpret_cast<const double*>(base)[k * Ns + idx];
+    } else if constexpr (P == P_F32) {
+      return reinterpret_cast<const float*>(base)[k * Ns + idx];
+    } else {
+      if (k == 9) return reinterpret_cast<const float*>(base + 18 * Ns)[idx];
+      const __half* h = reinterpret_cast<const __half*>(k < 9 ? base : base + 22 * Ns);
+      const int plane = k < 9 ? k : k - 10;
+      return __half2float(h[plane * Ns + idx]) * H_INV(k < 9 ? k : k - 9);
+    }
+  }
+  __device__ __forceinline__ void st(int k, int64_t idx, T v) const {
+    if constexpr (P == P_F64) {
+      reinterpret_cast<double*>(base)[k * Ns + idx] = v;
+    } else if constexpr (P == P_F32) {
+      reinterpret_cast<float*>(base)[k * Ns + idx] = v;
+    } else {
+      if (k == 9) { reinterpret_cast<float*>(base + 18 * Ns)[idx] = v; return; }
+      __half* h = reinterpret_cast<__half*>(k < 9 ? base : base + 22 * Ns);
+      const int plane = k < 9 ? k : k - 10;
+      h[plane * Ns + idx] = __float2half_rn(v * H_SCALE(k < 9 ? k : k - 9));
+    }
+  }
+};
+
+// ------------------------------------------------------------- addressing
+__device__ __forceinline__ int wrap_x(int x, int nx) {
+  return x < 0 ? x + nx : (x >= nx ? x - nx : x);
+}
+// Row of the stencil neighbour: periodic wrap, or the mirrored boundary row
+// (ghost rows psi(x,-1) = psi(x,0), psi(x,ny) = psi(x,ny-1)) at walls.
+__device__ __forceinline__ int nbr_row(int y, const Geom& g) {
+  if (y < 0) return g.walls ? 0 : y + g.ny;
+  if (y >= g.ny) return g.walls ? g.ny - 1 : y - g.ny;
+  return y;
+}
+
+// Pull streaming: the pre-collision population i at (x, y) is the
+// post-collision population i of node (x - c_i, y - c_i,y); when that node
+// lies beyond a wall it is the post-collision population opp(i) of (x, y)
+// itself (half-way bounce-back). Returns plane offset (0..8) and index.
+template <int I>
+__device__ __forceinline__ void pull_src(int x, int y, const Geom& g, int& plane, int64_t& idx) {
+  constexpr int cx = CXS(I), cy = CYS(I);
+  int ys = y - cy;
+  if (ys < 0 || ys >= g.ny) {
+    if (g.walls) { plane = OPP(I); idx = (int64_t)y * g.nx + x; return; }
+    ys = ys < 0 ? ys + g.ny : ys - g.ny;
+  }
+  plane = I;
+  idx = (int64_t)ys * g.nx + wrap_x(x - cx, g.nx);
+}
+
+// --------------------------------------------------------- per-node algebra
+// Bulk part of mu: 4 beta (phi - phi_A)(phi - phi_B)(phi - (phi_A+phi_B)/2)
+// with phi_A = 1, phi_B = 0 (Sec. II).
+template <typename T>
+__device__ __forceinline__ T mu_bulk(T phi, const Coef<T>& c) {
+  return c.beta4 * (phi - T(1)) * phi * (phi - T(0.5));
+}
+
+// Isotropic central stencils on a 3x3 neighbourhood v[dy+1][dx+1]:
+// grad = 3 sum_i w_i c_i v(c_i), lap = 6 sum_i w_i (v(c_i) - v(0)).
+template <typename T>
+__device__ __forceinline__ void stencil(const T v[3][3], T& gx, T& gy, T& lap) {
+  const T a = T(1.0 / 9.0), d = T(1.0 / 36.0);
+  const T ex = v[1][2] - v[1][0];
+  const T ey = v[2][1] - v[0][1];
+  const T d1 = v[2][2] - v[0][0];   // (1,1) - (-1,-1)
+  const T d2 = v[0][2] - v[2][0];   // (1,-1) - (-1,1)
+  gx = T(3) * (a * ex + d * (d1 + d2));
+  gy = T(3) * (a * ey + d * (d1 - d2));
+  const T sa = (v[1][2] + v[1][0]) + (v[2][1] + v[0][1]);
+  const T sd = (v[2][2] + v[0][0]) + (v[0][2] + v[2][0]);
+  lap = T(6) * (a * sa + d * sd - T(5.0 / 9.0) * v[1][1]);
+}
+
+// Macroscopic state of one node needed by the collision.
+template <typename T>
+struct Macro {
+  T phi, rho, mu, ux, uy, p, Fx, Fy, drx, dry, D;
+};
+
+// Force F = -phi grad mu + (rho - rho_ref) g, velocity
+// u = (j + F/6) / (rho/3), pressure p = S + (u.grad rho - gamma rho D)/6
+// (Sec. III moments; Sec. II force).
+template <typename T>
+__device__ __forceinline__ void macro_node(T phi, T mu, T gphx, T gphy, T gmux, T gmuy,
+                                           T lapmu, T S, T jx, T jy, const Coef<T>& c,
+                                           Macro<T>& m) {
+  m.phi = phi;
+  m.mu = mu;
+  m.rho = c.rho_B + c.drho * phi;
+  m.drx = c.drho * gphx;
+  m.dry = c.drho * gphy;
+  m.D = c.lam * lapmu;
+  const T b = m.rho - c.rho_ref;
+  m.Fx = -phi * gmux + b * c.gx;
+  m.Fy = -phi * gmuy + b * c.gy;
+  const T inv = T(3) / m.rho;
+  m.ux = (jx + m.Fx * T(1.0 / 6.0)) * inv;
+  m.uy = (jy + m.Fy * T(1.0 / 6.0)) * inv;
+  m.p = S + T(1.0 / 6.0) * (m.ux * m.drx + m.uy * m.dry - c.gamma * m.rho * m.D);
+}
+
+// BGK collision of both populations with the source terms (Sec. III):
+// s_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2, Gamma_i = 1 + s_i,
+// f^eq = w (p + rho s / 3), F_i = w (c-u).(Gamma F + s grad rho / 3) - w rho gamma D / 3,
+// g^eq = H_i + w phi s, G_i = -3 (phi/rho) w Gamma (c-u).(grad p - F),
+// x* = x - (x - x^eq)/tau + (1 - 1/(2 tau)) X_i.
+template <typename T>
+__device__ __forceinline__ void collide_node(T f[9], T g[9], const Macro<T>& m, T dpx, T dpy,
+                                             const Coef<T>& c) {
+  const T usq = m.ux * m.ux + m.uy * m.uy;
+  const T gpre = -T(3) * m.phi / m.rho;
+  const T hx = dpx - m.Fx, hy = dpy - m.Fy;
+  const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
+  const T amu = c.alpha * m.mu;
+  const T r3 = m.rho * T(1.0 / 3.0);
+  const T dx3 = m.drx * T(1.0 / 3.0), dy3 = m.dry * T(1.0 / 3.0);
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T w = T(WGT(i));
+    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
+    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
+    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T gm = T(1) + s;
+    const T feq = w * (m.p + r3 * s);
+    const T Fi = w * (cxu * (gm * m.Fx + s * dx3) + cyu * (gm * m.Fy + s * dy3) + src1);
+    const T H = (i == 0) ? m.phi - T(1.0 - 4.0 / 9.0) * amu : w * amu;
+    const T geq = H + w * m.phi * s;
+    const T Gi = gpre * w * gm * (cxu * hx + cyu * hy);
+    f[i] = f[i] - (f[i] - feq) * c.inv_tau_f + c.kf * Fi;
+    g[i] = g[i] - (g[i] - geq) * c.inv_tau_g + c.kg * Gi;
+  }
+}
+
+}  // namespace qilbm

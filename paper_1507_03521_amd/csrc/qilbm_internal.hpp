@@ -1,0 +1,56 @@
+// Host-side declarations shared by the C-ABI layer and the kernel files.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "qilbm_device.hpp"
+
+namespace qilbm {
+
+// FP64 outputs of the moments kernel; NULL members are skipped.
+struct MomentOut {
+  double* phi = nullptr;
+  double* rho = nullptr;
+  double* ux = nullptr;
+  double* uy = nullptr;
+  double* p = nullptr;
+  double* mu = nullptr;
+};
+
+// Launch shape of the fused step kernel.
+struct FusedShape {
+  int nstrips = 0, nseg = 0, seg_rows = 0, threads = 0;
+};
+
+FusedShape fused_shape(const Geom& g, int seg_rows);
+
+template <int P>
+hipError_t launch_init(const double* phi0, void* pop, const Coef<double>& c, const Geom& g,
+                       hipStream_t s);
+template <int P>
+hipError_t launch_from_canonical(const double* f, const double* gg, void* pop, const Geom& g,
+                                 hipStream_t s);
+template <int P>
+hipError_t launch_to_canonical(const void* pop, double* f, double* gg, const Geom& g,
+                               hipStream_t s);
+template <int P>
+hipError_t launch_fields(const void* pop, void* phi, void* mu,
+                         const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);
+template <int P>
+hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* p,
+                        const MomentOut& mo, const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                        hipStream_t s);
+template <int P>
+hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu, void* p,
+                               const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                               hipStream_t s);
+template <int P>
+hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
+                             const Geom& g, const FusedShape& sh, hipStream_t s);
+template <int P>
+hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
+                       const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);
+hipError_t launch_sum_partials(const double* part, int nb, int width, double* out, hipStream_t s);
+
+}  // namespace qilbm

@@ -10,3 +10,14 @@ if ROOT not in sys.path:
 
 def pytest_configure(config):
     config.addinivalue_line("markers", "gpu: needs an AMD GPU (gfx950) and the built HIP library")
+
+
+@pytest.fixture(scope="session", autouse=True)
+def _built_library():
+    """Builds the HIP library once if no build is present (the library is
+    never rebuilt over an existing one here)."""
+    from paper_1507_03521_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1507_03521_amd import build
+        build.build()
+    yield
