@@ -1,0 +1,240 @@
+"""Benchmark of the coupled phase-field LBE step on one MI355X.
+
+Workload: the 2048 x 8192 Rayleigh-Taylor problem between bounce-back walls
+(Atwood 0.5, Re 3000, Pe 1000, W 4), synthetic initial interface, no
+datasets. A step is one coupled f+g update of the whole lattice (moments,
+chemical potential, gradients, force, velocity, pressure, both collisions,
+streaming) -- one launch of the fused kernel.
+
+Printed: ONE JSON line. ``value`` is the FP32 rate in MLUPS (million lattice
+updates per second); the line also carries the FP64 and FP16-storage rates
+with their deviation from the FP64 GPU run, the adjoint/forward step-time
+ratio, the roofline position of the fused kernel and the CPU-oracle rate.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (coupled f+g) FP64 vs FP32 at stated error; adjoint/forward step ratio"
+PEAK_HBM_GBS = 8000.0
+BYTES_PER_LU = {"fp64": 288, "fp32": 144, "fp16": 76}
+PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fused_step_rt2048_fp32_pmc.txt")
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_1507_03521_amd", "csrc", f)
+                  for f in ("qilbm_kernels.hip", "qilbm_device.hpp")]
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def source_digest() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def timed_steps(lat, steps: int, warmup: int):
+    import torch
+    lat.step(warmup)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    lat.step(steps)
+    stop.record(lat.stream)
+    torch.cuda.synchronize()
+    return start.elapsed_time(stop) / steps          # ms per step (= per fused launch)
+
+
+def run_precision(pb, phi0, precision, steps, warmup, seg_rows):
+    from paper_1507_03521_amd import Lattice
+    lat = Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0")
+    if seg_rows:
+        lat.set_launch(seg_rows)
+    m0 = lat.mass()
+    ms = timed_steps(lat, steps, warmup)
+    m1 = lat.mass()
+    phi = lat.moments(("phi",))["phi"]
+    info = lat.launch_info()
+    del lat
+    return ms, phi, m0, m1, info
+
+
+def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
+    """Adjoint step time (and with its forward recompute and state save, as
+    checkpoint-recompute needs) over the forward step time."""
+    import torch
+    from paper_1507_03521_amd import Lattice
+    lat = Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0")
+    lat.step(5)
+    raw = lat.save_raw()
+    seed = torch.zeros((pb.ny, pb.nx), dtype=torch.float64, device="cuda:0")
+    lat.adjoint_begin(seed)
+    lat.adjoint_step(raw)
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    start.record(lat.stream)
+    for _ in range(nadj):
+        lat.adjoint_step(raw)
+    stop.record(lat.stream)
+    torch.cuda.synchronize()
+    adj_ms = start.elapsed_time(stop) / nadj
+    start.record(lat.stream)
+    for _ in range(nadj):
+        lat.save_raw(raw)
+        lat.step(1)
+    stop.record(lat.stream)
+    torch.cuda.synchronize()
+    rec_ms = start.elapsed_time(stop) / nadj
+    del lat
+    return dict(adjoint_ms_per_step=round(adj_ms, 4), ratio=round(adj_ms / fwd_ms, 3),
+                ratio_with_recompute=round((adj_ms + rec_ms) / fwd_ms, 3), precision=precision)
+
+
+def traffic_from_profile(n_nodes):
+    """HBM bytes per fused launch from the committed PMC summary, if it was
+    taken on the current kernel source; else None."""
+    if not os.path.exists(PROFILE_TRAFFIC):
+        return None
+    kv = {}
+    with open(PROFILE_TRAFFIC) as fh:
+        for line in fh:
+            if "=" in line and not line.startswith("#"):
+                k, v = line.split("=", 1)
+                kv[k.strip()] = v.strip()
+    if kv.get("kernel_source_sha") != source_digest():
+        return None
+    try:
+        return float(kv["hbm_bytes_per_launch"])
+    except (KeyError, ValueError):
+        return None
+
+
+def cpu_baseline(pb, phi0, rows: int, steps: int):
+    """The oracle as it stands, on a crop of the same workload (all columns,
+    the middle ``rows`` rows between walls), FP64, timed on the host."""
+    import torch
+    from oracle import qilbm_oracle as O
+    y0 = pb.ny // 2 - rows // 2
+    sub = pb.with_(ny=rows)
+    crop = phi0[y0:y0 + rows]
+    co = O.coefficients_of(sub)
+    with torch.no_grad():
+        f, g = O.initial_state(crop, co)
+        f, g = O.step(f, g, co)               # first touch outside the timing
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            f, g = O.step(f, g, co)
+        dt = time.perf_counter() - t0
+    return dict(value=round(sub.nx * rows * steps / dt / 1e6, 4), unit="MLUPS",
+                cores=torch.get_num_threads(), kind="oracle",
+                sample=f"{steps} FP64 steps of a {sub.nx}x{rows} crop (middle rows, walls) "
+                       f"of the {pb.nx}x{pb.ny} Rayleigh-Taylor lattice, {dt:.1f} s")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1000)
+    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--only", choices=["fp32", "fp64", "fp16"], default=None,
+                    help="time one precision only (for profiler runs)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--cpu-rows", type=int, default=2048)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a 1 GiB device copy (PMC byte-counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
+              f"(the multi-GPU decomposition is a design only)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads as wl
+
+    pb = wl.rt2048()
+    phi0 = wl.phi0(pb)
+    N = pb.nx * pb.ny
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copy calibration: 3 x 1 GiB read + 1 GiB write")
+
+    precisions = [args.only] if args.only else ["fp32", "fp64", "fp16"]
+    res = {}
+    for prec in precisions:
+        log(f"timing {prec}: {args.steps} steps after {args.warmup} warm-up")
+        ms, phi, m0, m1, info = run_precision(pb, phi0, prec, args.steps, args.warmup,
+                                              args.seg_rows)
+        res[prec] = dict(ms=ms, phi=phi, m0=m0, m1=m1, info=info)
+        log(f"  {prec}: {ms:.4f} ms/step, {N / ms / 1e3:.1f} MLUPS, launch {info}")
+
+    def entry(prec):
+        r = res[prec]
+        out = dict(mlups=round(N / r["ms"] / 1e3, 2), ms_per_step=round(r["ms"], 5),
+                   hbm_roofline_frac=round(BYTES_PER_LU[prec] * N / (r["ms"] * 1e-3) / 1e9
+                                           / PEAK_HBM_GBS, 4),
+                   mass_drift_rel=abs(r["m1"][1] - r["m0"][1]) / abs(r["m0"][1]))
+        if "fp64" in res and prec != "fp64":
+            out["phi_max_abs_dev_vs_fp64"] = float((r["phi"] - res["fp64"]["phi"]).abs().max())
+        return out
+
+    main_prec = args.only or "fp32"
+    ms = res[main_prec]["ms"]
+    alg_bytes = BYTES_PER_LU[main_prec] * N
+    achieved = alg_bytes / (ms * 1e-3) / 1e9
+    traffic = traffic_from_profile(N) if main_prec == "fp32" else None
+    line = {
+        "metric": METRIC,
+        "value": round(N / ms / 1e3, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms, 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp32": "f32", "fp64": "f64", "fp16": "f16-store/f32"}[main_prec],
+        "data": "synthetic",
+        "config": {"workload": "rt2048: Rayleigh-Taylor 2048x8192, walls in y, Atwood 0.5, "
+                               "Re 3000, Pe 1000, W 4",
+                   "nx": pb.nx, "ny": pb.ny, "precision": main_prec,
+                   "launch": res[main_prec]["info"]},
+        "roofline": {"bound": "hbm", "kernel": f"k_step_fused<{main_prec}>",
+                     "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "alg_bytes_per_launch": alg_bytes,
+                     "traffic": None if traffic is None else round(traffic, 0)},
+    }
+    for prec in res:
+        line[{"fp64": "fp64", "fp32": "fp32", "fp16": "fp16_store"}[prec]] = entry(prec)
+    if not args.no_adjoint and main_prec in ("fp32", "fp64"):
+        log("timing adjoint")
+        line["adjoint"] = adjoint_ratio(pb, phi0, main_prec, ms)
+    if not args.no_cpu_baseline:
+        log("timing CPU oracle sample")
+        line["cpu_baseline"] = cpu_baseline(pb, phi0, args.cpu_rows, args.cpu_steps)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()
