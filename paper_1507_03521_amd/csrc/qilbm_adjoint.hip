@@ -251,7 +251,7 @@ __device__ __forceinline__ void fwd_node(const Pop<P>& in, const typename PrecT<
 #define QILBM_PULLF(I)                   \
   {                                      \
     int plane;                           \
-    int64_t idx;                         \
+    uint32_t idx;                        \
     pull_src<I>(x, y, g, plane, idx);    \
     f[I] = in.ld(plane, idx);            \
   }

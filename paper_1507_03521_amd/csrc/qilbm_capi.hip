@@ -26,6 +26,7 @@ struct lbm_ctx {
   double* red_out;    // 8 doubles
   int64_t t;
   int seg_rows;
+  int resident;       // fused workgroups resident at once on this device
   int64_t pbytes;
   AdjointState adj;
 };
@@ -46,7 +47,8 @@ bool finite_all(const lbm_params* p) {
 bool valid(const lbm_params* p) {
   if (!p) return false;
   if (p->nx < 3 || p->ny < 3) return false;
-  if ((int64_t)p->nx * (int64_t)p->ny > (int64_t)1 << 34) return false;
+  // 32-bit per-lane byte offsets inside a population plane (8-byte values)
+  if ((int64_t)p->nx * (int64_t)p->ny > ((int64_t)1 << 29) - 256) return false;
   if (!finite_all(p)) return false;
   if (!(p->rho_A > 0.0) || !(p->rho_B > 0.0)) return false;
   if (!(p->sigma > 0.0) || !(p->W > 0.0) || !(p->M > 0.0)) return false;
@@ -132,7 +134,7 @@ lbm_status step_p(lbm_ctx* c, int64_t n) {
   using T = typename PrecT<P>::T;
   const Coef<T> k = coef_t<T>(c);
   const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
-  const FusedShape sh = fused_shape(c->geom, c->seg_rows);
+  const FusedShape sh = fused_shape(c->geom, c->seg_rows, c->resident);
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e;
     if (unfused)
@@ -216,6 +218,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
   c->red_out = (double*)(c->ws + L.red);
   c->t = 0;
   c->seg_rows = 0;
+  c->resident = QILBM_DISPATCH(params->precision, fused_resident);
   c->pbytes = pop_bytes(params->precision, c->geom.Ns);
   Coef<double> k = coef_t<double>(c);
   const hipError_t e = QILBM_DISPATCH(params->precision, launch_init, phi0_dev, c->pop[0], k,
@@ -300,7 +303,7 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t seg_rows) {
 
 lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
   if (!c || !out) return LBM_EINVAL;
-  const FusedShape sh = fused_shape(c->geom, c->seg_rows);
+  const FusedShape sh = fused_shape(c->geom, c->seg_rows, c->resident);
   out[0] = sh.nstrips;
   out[1] = sh.nseg;
   out[2] = sh.seg_rows;

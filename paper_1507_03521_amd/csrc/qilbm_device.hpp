@@ -78,34 +78,44 @@ __host__ __device__ inline int64_t pop_bytes(int P, int64_t Ns) {
 
 // Plane k in 0..17: f_0..f_8 are k = 0..8, g_0..g_8 are k = 9..17.
 // F16 layout: f planes (binary16), then g_0 (binary32), then g_1..8 (binary16).
+// A plane's base address is uniform across the wavefront; the per-lane part
+// is a 32-bit byte offset (lattices are capped so that it cannot overflow),
+// which lets the compiler use scalar-base + 32-bit-offset addressing.
 template <int P>
 struct Pop {
   char* base;
   int64_t Ns;
   using T = typename PrecT<P>::T;
 
-  __device__ __forceinline__ T ld(int k, int64_t idx) const {
+  template <typename S>
+  __device__ __forceinline__ static S at(const char* plane, uint32_t idx) {
+    return *reinterpret_cast<const S*>(plane + idx * (uint32_t)sizeof(S));
+  }
+  template <typename S>
+  __device__ __forceinline__ static void put(char* plane, uint32_t idx, S v) {
+    *reinterpret_cast<S*>(plane + idx * (uint32_t)sizeof(S)) = v;
+  }
+
+  __device__ __forceinline__ T ld(int k, uint32_t idx) const {
     if constexpr (P == P_F64) {
-      return reinterpret_cast<const double*>(base)[k * Ns + idx];
+      return at<double>(base + k * Ns * 8, idx);
     } else if constexpr (P == P_F32) {
-      return reinterpret_cast<const float*>(base)[k * Ns + idx];
+      return at<float>(base + k * Ns * 4, idx);
     } else {
-      if (k == 9) return reinterpret_cast<const float*>(base + 18 * Ns)[idx];
-      const __half* h = reinterpret_cast<const __half*>(k < 9 ? base : base + 22 * Ns);
-      const int plane = k < 9 ? k : k - 10;
-      return __half2float(h[plane * Ns + idx]) * H_INV(k < 9 ? k : k - 9);
+      if (k == 9) return at<float>(base + 18 * Ns, idx);
+      const char* h = k < 9 ? base + k * Ns * 2 : base + 22 * Ns + (k - 10) * Ns * 2;
+      return __half2float(at<__half>(h, idx)) * H_INV(k < 9 ? k : k - 9);
     }
   }
-  __device__ __forceinline__ void st(int k, int64_t idx, T v) const {
+  __device__ __forceinline__ void st(int k, uint32_t idx, T v) const {
     if constexpr (P == P_F64) {
-      reinterpret_cast<double*>(base)[k * Ns + idx] = v;
+      put<double>(base + k * Ns * 8, idx, v);
     } else if constexpr (P == P_F32) {
-      reinterpret_cast<float*>(base)[k * Ns + idx] = v;
+      put<float>(base + k * Ns * 4, idx, v);
     } else {
-      if (k == 9) { reinterpret_cast<float*>(base + 18 * Ns)[idx] = v; return; }
-      __half* h = reinterpret_cast<__half*>(k < 9 ? base : base + 22 * Ns);
-      const int plane = k < 9 ? k : k - 10;
-      h[plane * Ns + idx] = __float2half_rn(v * H_SCALE(k < 9 ? k : k - 9));
+      if (k == 9) { put<float>(base + 18 * Ns, idx, v); return; }
+      char* h = k < 9 ? base + k * Ns * 2 : base + 22 * Ns + (k - 10) * Ns * 2;
+      put<__half>(h, idx, __float2half_rn(v * H_SCALE(k < 9 ? k : k - 9)));
     }
   }
 };
@@ -127,18 +137,22 @@ __device__ __forceinline__ int nbr_row(int y, const Geom& g) {
 // lies beyond a wall it is the post-collision population opp(i) of (x, y)
 // itself (half-way bounce-back). Returns plane offset (0..8) and index.
 template <int I>
-__device__ __forceinline__ void pull_src(int x, int y, const Geom& g, int& plane, int64_t& idx) {
+__device__ __forceinline__ void pull_src(int x, int y, const Geom& g, int& plane, uint32_t& idx) {
   constexpr int cx = CXS(I), cy = CYS(I);
   int ys = y - cy;
   if (ys < 0 || ys >= g.ny) {
-    if (g.walls) { plane = OPP(I); idx = (int64_t)y * g.nx + x; return; }
+    if (g.walls) { plane = OPP(I); idx = (uint32_t)(y * g.nx + x); return; }
     ys = ys < 0 ? ys + g.ny : ys - g.ny;
   }
   plane = I;
-  idx = (int64_t)ys * g.nx + wrap_x(x - cx, g.nx);
+  idx = (uint32_t)(ys * g.nx + wrap_x(x - cx, g.nx));
 }
 
 // --------------------------------------------------------- per-node algebra
+// 1/x: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32.
+__device__ __forceinline__ double recip(double x) { return 1.0 / x; }
+__device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // Bulk part of mu: 4 beta (phi - phi_A)(phi - phi_B)(phi - (phi_A+phi_B)/2)
 // with phi_A = 1, phi_B = 0 (Sec. II).
 template <typename T>
@@ -184,7 +198,7 @@ __device__ __forceinline__ void macro_node(T phi, T mu, T gphx, T gphy, T gmux, 
   const T b = m.rho - c.rho_ref;
   m.Fx = -phi * gmux + b * c.gx;
   m.Fy = -phi * gmuy + b * c.gy;
-  const T inv = T(3) / m.rho;
+  const T inv = T(3) * recip(m.rho);
   m.ux = (jx + m.Fx * T(1.0 / 6.0)) * inv;
   m.uy = (jy + m.Fy * T(1.0 / 6.0)) * inv;
   m.p = S + T(1.0 / 6.0) * (m.ux * m.drx + m.uy * m.dry - c.gamma * m.rho * m.D);
@@ -199,7 +213,7 @@ template <typename T>
 __device__ __forceinline__ void collide_node(T f[9], T g[9], const Macro<T>& m, T dpx, T dpy,
                                              const Coef<T>& c) {
   const T usq = m.ux * m.ux + m.uy * m.uy;
-  const T gpre = -T(3) * m.phi / m.rho;
+  const T gpre = -T(3) * m.phi * recip(m.rho);
   const T hx = dpx - m.Fx, hy = dpy - m.Fy;
   const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
   const T amu = c.alpha * m.mu;

@@ -20,10 +20,16 @@ struct MomentOut {
 
 // Launch shape of the fused step kernel.
 struct FusedShape {
-  int nstrips = 0, nseg = 0, seg_rows = 0, threads = 0;
+  int nstrips = 0, width = 0, nseg = 0, seg_rows = 0, threads = 0;
 };
 
-FusedShape fused_shape(const Geom& g, int seg_rows);
+// Launch shape for seg_rows rows per segment (0: automatic, from the number
+// of workgroups that can be resident at once, ``resident``).
+FusedShape fused_shape(const Geom& g, int seg_rows, int resident);
+
+// Workgroups of the fused kernel that the current device holds at once.
+template <int P>
+int fused_resident();
 
 template <int P>
 hipError_t launch_init(const double* phi0, void* pop, const Coef<double>& c, const Geom& g,

@@ -16,7 +16,7 @@ template <int P, int KOFF, int I>
 __device__ __forceinline__ typename PrecT<P>::T pull_ld(const Pop<P>& in, int x, int y,
                                                         const Geom& g) {
   int plane;
-  int64_t idx;
+  uint32_t idx;
   pull_src<I>(x, y, g, plane, idx);
   return in.ld(KOFF + plane, idx);
 }
@@ -78,7 +78,7 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi0, P
 #pragma unroll
   for (int i = 1; i < 9; ++i) h[i] = WGT(i) * amu;
   int plane;
-  int64_t idx;
+  uint32_t idx;
 #define QILBM_SCATTER(I)                                                   \
   pull_src<I>(x, y, g, plane, idx);                                        \
   out.st(plane, idx, typename PrecT<P>::T(0));                             \
@@ -97,7 +97,7 @@ __global__ __launch_bounds__(256) void k_from_canonical(const double* __restrict
   if (n >= g.N) return;
   const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
   int plane;
-  int64_t idx;
+  uint32_t idx;
   using T = typename PrecT<P>::T;
 #define QILBM_SCATTER(I)                                                   \
   pull_src<I>(x, y, g, plane, idx);                                        \
@@ -196,7 +196,7 @@ __global__ __launch_bounds__(256) void k_macro(Pop<P> in, const typename PrecT<P
 }
 
 template <int P>
-__device__ __forceinline__ void store_node(const Pop<P>& out, int64_t n,
+__device__ __forceinline__ void store_node(const Pop<P>& out, uint32_t n,
                                            const typename PrecT<P>::T f[9],
                                            const typename PrecT<P>::T gg[9]) {
 #pragma unroll
@@ -225,7 +225,7 @@ __global__ __launch_bounds__(256) void k_collide(Pop<P> in, Pop<P> out,
   gather3x3(p, x, y, g, v);
   stencil(v, dpx, dpy, lapp);
   collide_node(f, gg, m, dpx, dpy, c);
-  store_node<P>(out, n, f, gg);
+  store_node<P>(out, (uint32_t)n, f, gg);
 }
 
 // ------------------------------------------------------- mass reduction
@@ -287,23 +287,28 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 }
 
 // ------------------------------------------------------ fused step kernel
-// One pass over the lattice per time step. A workgroup owns a strip of
-// FW columns (plus FH halo columns on each side) and a segment of rows, and
-// sweeps the rows upwards keeping a ring of recent rows of phi, mu and p in
-// LDS. In the iteration that brings in row r it
-//   A: pulls g at row r and forms phi(r) (also on the halo columns),
+// One pass over the lattice per time step. A workgroup of FT lanes owns a
+// strip of at most FT - 2 FH columns plus FH halo columns on each side
+// (lane lc <-> column x0 - FH + lc) and a segment of rows, and sweeps the
+// rows upwards keeping rings of recent rows of phi, mu, p and the node
+// state in LDS. In the iteration that brings in row r it
+//   A: forms phi(r) from the pulled g of row r (halo lanes included),
 //   B: forms mu(r-1) from the phi rows r-2..r,
-//   C: pulls f at row r-2 and forms the force, velocity and pressure there,
+//   C: forms force, velocity and pressure at row r-2 from its pulled f and
+//      keeps them in LDS,
 //   D: collides row r-3, whose grad p now has all three p rows, and writes
 //      both post-collision populations.
-// The g values of a row are kept in registers from A to D (ring of four
-// rows), the f values from C to D (ring of two), so each population is read
-// once from memory and written once. Halo columns and the 3 rows of warm-up
-// at each segment end are recomputed by neighbouring workgroups.
-constexpr int FW = 256;
-constexpr int FH = 3;
-constexpr int FL = FW + 2 * FH;
-constexpr int FT = FW + 64;
+// The g values of a row stay in registers from A to D (ring of four rows),
+// the f values from C to D (ring of two), so each population is read once
+// from memory and written once. D first moves its row out of the rings and
+// refills the freed slots with the loads of the next iteration (g of row
+// r+1, f of row r-1), so their latency overlaps the collision, the stores
+// and the barrier. Halo columns and the 3 rows of warm-up at each segment
+// end are recomputed by the neighbouring workgroups.
+constexpr int FT = 256;         // lanes per workgroup (4 wavefronts)
+constexpr int FH = 3;           // halo columns per side
+constexpr int FWMAX = FT - 2 * FH;
+constexpr int NM = 7;           // node values kept from C to D
 
 // Tiles handed out so that blocks that the hardware places on one XCD
 // (consecutive blocks round-robin over 8 XCDs) get consecutive tiles, i.e.
@@ -313,18 +318,176 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
   return j * q + (j < rem ? j : rem) + pos;
 }
 
+// Population access of the fused kernel through buffer resources: one
+// descriptor each for the f planes, the g_0 plane and the g_1..8 planes.
+// The plane and row parts of an address are uniform over a wavefront and go
+// into the scalar offset; the lane's column is one of three precomputed
+// byte offsets (x - 1, x, x + 1). Loads beyond a descriptor's range return 0.
+constexpr int BUF_WORD3 = 0x00020000;
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
+template <int P> struct BufT;
+template <> struct BufT<P_F64> { using F = double; using G0 = double; using GR = double; };
+template <> struct BufT<P_F32> { using F = float; using G0 = float; using GR = float; };
+template <> struct BufT<P_F16> { using F = __half; using G0 = float; using GR = __half; };
+
+template <typename S>
+__device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(S) == 8) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else if constexpr (sizeof(S) == 4) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  }
+}
+template <typename S>
+__device__ __forceinline__ void buf_st(S v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff) {
+  if constexpr (sizeof(S) == 8) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
+  }
+}
+
+template <int P>
+struct BufPop {
+  using T = typename PrecT<P>::T;
+  using F = typename BufT<P>::F;
+  using G0 = typename BufT<P>::G0;
+  using GR = typename BufT<P>::GR;
+  __amdgpu_buffer_rsrc_t rf, rg0, rgr;
+  uint32_t pf, pg;     // plane strides (bytes) of the f and g_1..8 planes
+
+  __device__ __forceinline__ void init(const Pop<P>& p) {
+    const int64_t Ns = p.Ns;
+    char* b = p.base;
+    char *f, *g0, *gr;
+    if constexpr (P == P_F16) {
+      f = b;
+      g0 = b + 18 * Ns;
+      gr = b + 22 * Ns;
+    } else {
+      f = b;
+      g0 = b + 9 * Ns * (int64_t)sizeof(T);
+      gr = b + 10 * Ns * (int64_t)sizeof(T);
+    }
+    pf = (uint32_t)(Ns * sizeof(F));
+    pg = (uint32_t)(Ns * sizeof(GR));
+    rf = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(9 * (int64_t)pf), BUF_WORD3);
+    rg0 = __builtin_amdgcn_make_buffer_rsrc(g0, 0, (int)(Ns * sizeof(G0)), BUF_WORD3);
+    rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)(8 * (int64_t)pg), BUF_WORD3);
+  }
+  // value of f_i (G = false) or g_i (G = true) at plane I, element (row, col)
+  template <bool G, int I>
+  __device__ __forceinline__ T ld(uint32_t elem_row, const uint32_t col[3], int dx) const {
+    if constexpr (!G) {
+      const F v = buf_ld<F>(rf, col[dx + 1] * (uint32_t)sizeof(F),
+                            I * pf + elem_row * (uint32_t)sizeof(F));
+      if constexpr (P == P_F16) return __half2float(v) * H_INV(I);
+      else return v;
+    } else if constexpr (I == 0) {
+      return buf_ld<G0>(rg0, col[dx + 1] * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
+    } else {
+      const GR v = buf_ld<GR>(rgr, col[dx + 1] * (uint32_t)sizeof(GR),
+                              (I - 1) * pg + elem_row * (uint32_t)sizeof(GR));
+      if constexpr (P == P_F16) return __half2float(v) * H_INV(I);
+      else return v;
+    }
+  }
+  template <bool G, int I>
+  __device__ __forceinline__ void st(T v, uint32_t elem_row, uint32_t col) const {
+    if constexpr (!G) {
+      F w;
+      if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
+      else w = v;
+      buf_st<F>(w, rf, col * (uint32_t)sizeof(F), I * pf + elem_row * (uint32_t)sizeof(F));
+    } else if constexpr (I == 0) {
+      buf_st<G0>(G0(v), rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
+    } else {
+      GR w;
+      if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
+      else w = v;
+      buf_st<GR>(w, rgr, col * (uint32_t)sizeof(GR), (I - 1) * pg + elem_row * (uint32_t)sizeof(GR));
+    }
+  }
+};
+
+// Pulls the nine pre-collision populations of row y (uniform over the
+// workgroup) at this lane's column. Off the wall rows every direction reads
+// its plane at row y - c_iy (wrapped when periodic) and column x - c_ix; on a
+// wall row the directions whose source lies beyond the wall read the
+// opposite plane at the node itself (half-way bounce-back). WALL is 0 off
+// the walls, -1 on the bottom row and +1 on the top row; the choice per
+// direction is then fixed at compile time, so every offset stays scalar.
+template <int P, bool G, int WALL, int I = 0>
+__device__ __forceinline__ void pull_row_dirs(const BufPop<P>& B, const uint32_t rows[3],
+                                              const uint32_t col[3],
+                                              typename PrecT<P>::T v[9]) {
+  if constexpr (I < 9) {
+    constexpr int cx = CXS(I), cy = CYS(I);
+    if constexpr ((WALL == -1 && cy == 1) || (WALL == 1 && cy == -1))
+      v[I] = B.template ld<G, OPP(I)>(rows[1], col, 0);
+    else
+      v[I] = B.template ld<G, I>(rows[1 - cy], col, -cx);
+    pull_row_dirs<P, G, WALL, I + 1>(B, rows, col, v);
+  }
+}
+
 template <int P>
 struct FusedCtx {
   using T = typename PrecT<P>::T;
-  Pop<P> in, out;
+  BufPop<P> in, out;
   Coef<T> c;
   Geom g;
   int lc, x, wi, y0, y1;
+  uint32_t col[3];     // element columns x - 1, x, x + 1 (wrapped)
   bool act;
 };
 
+// Pull row y (physical) of population set G.
+template <int P, bool G>
+__device__ __forceinline__ void pull_row(const FusedCtx<P>& k, int y, typename PrecT<P>::T v[9]) {
+  const Geom& g = k.g;
+  const int nx = g.nx;
+  int ym = y - 1, yp = y + 1;
+  if (!g.walls) {
+    ym = ym < 0 ? ym + g.ny : ym;
+    yp = yp >= g.ny ? yp - g.ny : yp;
+  }
+  const uint32_t rows[3] = {(uint32_t)(ym * nx), (uint32_t)(y * nx), (uint32_t)(yp * nx)};
+  if (g.walls && y == 0)
+    pull_row_dirs<P, G, -1>(k.in, rows, k.col, v);
+  else if (g.walls && y == g.ny - 1)
+    pull_row_dirs<P, G, 1>(k.in, rows, k.col, v);
+  else
+    pull_row_dirs<P, G, 0>(k.in, rows, k.col, v);
+}
+
+template <int P, int I = 0>
+__device__ __forceinline__ void store_row(const FusedCtx<P>& k, uint32_t row,
+                                          const typename PrecT<P>::T f[9],
+                                          const typename PrecT<P>::T gg[9]) {
+  if constexpr (I < 9) {
+    k.out.template st<false, I>(f[I], row, k.col[1]);
+    k.out.template st<true, I>(gg[I], row, k.col[1]);
+    store_row<P, I + 1>(k, row, f, gg);
+  }
+}
+
 template <typename T>
-__device__ __forceinline__ void lds3x3(const T (*ring)[FL], int mask, int v, int ny, int walls,
+struct FusedLds {
+  T phi[8][FT];
+  T mu[4][FT];
+  T p[4][FT];
+  T node[2][NM][FT];   // ux, uy, Fx, Fy, drx, dry, D
+};
+
+template <typename T>
+__device__ __forceinline__ void lds3x3(const T (*ring)[FT], int mask, int v, int ny, int walls,
                                        int lc, T out[3][3]) {
   const int vm = (walls && v == 0) ? v : v - 1;
   const int vp = (walls && v == ny - 1) ? v : v + 1;
@@ -346,109 +509,136 @@ __device__ __forceinline__ bool row_ok(int v, const Geom& g) {
   return !g.walls || (v >= 0 && v < g.ny);
 }
 
+// Row r needs phi (stage A) / row q needs F, u, p (stage C) on this lane.
+template <int P>
+__device__ __forceinline__ bool need_phi(const FusedCtx<P>& k, int r) {
+  return k.act && r < k.y1 + 3 && row_ok(r, k.g);
+}
+template <int P>
+__device__ __forceinline__ bool need_p(const FusedCtx<P>& k, int q) {
+  return k.act && k.lc >= 2 && k.lc < k.wi + 4 && q >= k.y0 - 1 && q < k.y1 + 1 && row_ok(q, k.g);
+}
+
 template <int P, int J>
 __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
                                            typename PrecT<P>::T (&gb)[4][9],
                                            typename PrecT<P>::T (&fb)[2][9],
-                                           typename PrecT<P>::T (*s_phi)[FL],
-                                           typename PrecT<P>::T (*s_mu)[FL],
-                                           typename PrecT<P>::T (*s_p)[FL]) {
+                                           FusedLds<typename PrecT<P>::T>& L) {
   using T = typename PrecT<P>::T;
   const Geom& g = k.g;
   const int lc = k.lc;
-  // A: phi at row r
-  if (k.act && r < k.y1 + 3 && row_ok(r, g)) {
-    pull9<P, 9>(k.in, k.x, phys_row(r, g), g, gb[J]);
-    s_phi[r & 7][lc] = sum9(gb[J]);
-  }
+  // A: phi at row r (its g was loaded by the previous iteration)
+  if (need_phi(k, r)) L.phi[r & 7][lc] = sum9(gb[J]);
   __syncthreads();
   // B: mu at row r - 1
   const int b = r - 1;
   if (k.act && lc >= 1 && lc < k.wi + 5 && b >= k.y0 - 2 && b < k.y1 + 2 && row_ok(b, g)) {
     T v[3][3], gx, gy, lap;
-    lds3x3<T>(s_phi, 7, b, g.ny, g.walls, lc, v);
+    lds3x3<T>(L.phi, 7, b, g.ny, g.walls, lc, v);
     stencil(v, gx, gy, lap);
-    s_mu[b & 3][lc] = mu_bulk(v[1][1], k.c) - k.c.kappa * lap;
+    L.mu[b & 3][lc] = mu_bulk(v[1][1], k.c) - k.c.kappa * lap;
   }
   __syncthreads();
   // C: force, velocity, pressure at row r - 2
   const int q = r - 2;
-  if (k.act && lc >= 2 && lc < k.wi + 4 && q >= k.y0 - 1 && q < k.y1 + 1 && row_ok(q, g)) {
-    pull9<P, 0>(k.in, k.x, phys_row(q, g), g, fb[J & 1]);
+  if (need_p(k, q)) {
     T S, jx, jy;
     moments9(fb[J & 1], S, jx, jy);
     T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
-    lds3x3<T>(s_phi, 7, q, g.ny, g.walls, lc, v);
+    lds3x3<T>(L.phi, 7, q, g.ny, g.walls, lc, v);
     stencil(v, gphx, gphy, lapphi);
     const T ph = v[1][1];
-    lds3x3<T>(s_mu, 3, q, g.ny, g.walls, lc, v);
+    lds3x3<T>(L.mu, 3, q, g.ny, g.walls, lc, v);
     stencil(v, gmux, gmuy, lapmu);
     Macro<T> m;
     macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, k.c, m);
-    s_p[q & 3][lc] = m.p;
+    L.p[q & 3][lc] = m.p;
+    T* nd = &L.node[q & 1][0][0];
+    nd[0 * FT + lc] = m.ux;
+    nd[1 * FT + lc] = m.uy;
+    nd[2 * FT + lc] = m.Fx;
+    nd[3 * FT + lc] = m.Fy;
+    nd[4 * FT + lc] = m.drx;
+    nd[5 * FT + lc] = m.dry;
+    nd[6 * FT + lc] = m.D;
   }
   __syncthreads();
-  // D: collide row r - 3 and store
+  // D: collide row r - 3 and store; meanwhile fetch the next iteration's rows
   const int cr = r - 3;
+  T f[9], gg[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    f[i] = fb[(J + 1) & 1][i];
+    gg[i] = gb[(J + 1) & 3][i];
+  }
+  if (need_phi(k, r + 1)) pull_row<P, true>(k, phys_row(r + 1, g), gb[(J + 1) & 3]);
+  if (need_p(k, r - 1)) pull_row<P, false>(k, phys_row(r - 1, g), fb[(J + 1) & 1]);
   if (k.act && lc >= FH && lc < k.wi + FH && cr >= k.y0 && cr < k.y1) {
-    T* f = fb[(J + 1) & 1];
-    T* gg = gb[(J + 1) & 3];
-    T S, jx, jy;
-    moments9(f, S, jx, jy);
-    T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu, dpx, dpy, lapp;
-    lds3x3<T>(s_phi, 7, cr, g.ny, g.walls, lc, v);
-    stencil(v, gphx, gphy, lapphi);
-    const T ph = v[1][1];
-    lds3x3<T>(s_mu, 3, cr, g.ny, g.walls, lc, v);
-    stencil(v, gmux, gmuy, lapmu);
     Macro<T> m;
-    macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, k.c, m);
-    lds3x3<T>(s_p, 3, cr, g.ny, g.walls, lc, v);
+    const T* nd = &L.node[cr & 1][0][0];
+    m.phi = L.phi[cr & 7][lc];
+    m.mu = L.mu[cr & 3][lc];
+    m.rho = k.c.rho_B + k.c.drho * m.phi;
+    m.ux = nd[0 * FT + lc];
+    m.uy = nd[1 * FT + lc];
+    m.Fx = nd[2 * FT + lc];
+    m.Fy = nd[3 * FT + lc];
+    m.drx = nd[4 * FT + lc];
+    m.dry = nd[5 * FT + lc];
+    m.D = nd[6 * FT + lc];
+    T v[3][3], dpx, dpy, lapp;
+    lds3x3<T>(L.p, 3, cr, g.ny, g.walls, lc, v);
+    m.p = v[1][1];
     stencil(v, dpx, dpy, lapp);
     collide_node(f, gg, m, dpx, dpy, k.c);
-    store_node<P>(k.out, (int64_t)cr * g.nx + k.x, f, gg);
+    store_row<P>(k, (uint32_t)(cr * g.nx), f, gg);
   }
 }
 
+// Occupancy the register allocation targets (waves per SIMD): 4 for the
+// 32-bit compute paths (<= 128 VGPRs), 2 for FP64.
+#ifndef QILBM_FUSED_WAVES32
+#define QILBM_FUSED_WAVES32 4
+#endif
+template <int P> struct FusedWaves { static constexpr int value = QILBM_FUSED_WAVES32; };
+template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
+
 template <int P>
-__global__ __launch_bounds__(FT) void k_step_fused(Pop<P> in, Pop<P> out,
-                                                   Coef<typename PrecT<P>::T> c, Geom g, int nseg,
-                                                   int seg_len) {
+__global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
+                                                   Coef<typename PrecT<P>::T> c, Geom g, int width,
+                                                   int nseg, int seg_len) {
   using T = typename PrecT<P>::T;
-  __shared__ T s_phi[8][FL];
-  __shared__ T s_mu[4][FL];
-  __shared__ T s_p[4][FL];
+  __shared__ FusedLds<T> L;
   FusedCtx<P> k;
-  k.in = in;
-  k.out = out;
+  k.in.init(in);
+  k.out.init(out);
   k.c = c;
   k.g = g;
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
   const int strip = tile / nseg, seg = tile - strip * nseg;
-  const int x0 = strip * FW;
-  k.wi = min(FW, g.nx - x0);
+  const int x0 = strip * width;
+  k.wi = min(width, g.nx - x0);
   k.y0 = seg * seg_len;
   k.y1 = min(g.ny, k.y0 + seg_len);
   const int t = threadIdx.x;
-  int lc = -1;
-  if (t < FW) {
-    lc = t < k.wi ? t + FH : -1;
-  } else {
-    const int j = t - FW;
-    lc = j < FH ? j : (j < 2 * FH ? k.wi + j : -1);
-  }
-  k.lc = lc < 0 ? FH : lc;
-  k.act = lc >= 0;
+  k.act = t < k.wi + 2 * FH;
+  k.lc = k.act ? t : FH;
   k.x = wrap_x(x0 + k.lc - FH, g.nx);
+  k.col[0] = (uint32_t)wrap_x(k.x - 1, g.nx);
+  k.col[1] = (uint32_t)k.x;
+  k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
   T gb[4][9];
   T fb[2][9];
   const int r0 = k.y0 - 3;
   const int nit = (k.y1 - k.y0) + 6;
+  // prologue: g of the first row (the first f row is needed 2 iterations later
+  // and is fetched by iteration 1)
+  if (need_phi(k, r0)) pull_row<P, true>(k, phys_row(r0, g), gb[0]);
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, 0>(k, r0 + it + 0, gb, fb, s_phi, s_mu, s_p);
-    fused_iter<P, 1>(k, r0 + it + 1, gb, fb, s_phi, s_mu, s_p);
-    fused_iter<P, 2>(k, r0 + it + 2, gb, fb, s_phi, s_mu, s_p);
-    fused_iter<P, 3>(k, r0 + it + 3, gb, fb, s_phi, s_mu, s_p);
+    fused_iter<P, 0>(k, r0 + it + 0, gb, fb, L);
+    fused_iter<P, 1>(k, r0 + it + 1, gb, fb, L);
+    fused_iter<P, 2>(k, r0 + it + 2, gb, fb, L);
+    fused_iter<P, 3>(k, r0 + it + 3, gb, fb, L);
   }
 }
 
@@ -515,12 +705,17 @@ hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu,
   return hipGetLastError();
 }
 
-FusedShape fused_shape(const Geom& g, int seg_rows) {
+FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
   FusedShape sh;
-  sh.nstrips = (g.nx + FW - 1) / FW;
+  // strips of equal width (at most FWMAX interior columns) so that every
+  // workgroup carries the same work
+  sh.nstrips = (g.nx + FWMAX - 1) / FWMAX;
+  sh.width = (g.nx + sh.nstrips - 1) / sh.nstrips;
   if (seg_rows <= 0) {
-    // about 2048 workgroups in flight: 8 per CU on 256 CUs, rows >= 16
-    const int want = (2048 + sh.nstrips - 1) / sh.nstrips;
+    // one round of workgroups: as many segments as fit resident at once
+    // (CUs x workgroups per CU), but no segment shorter than 16 rows
+    if (resident < 1) resident = 768;
+    const int want = (resident + sh.nstrips - 1) / sh.nstrips;
     seg_rows = (g.ny + want - 1) / want;
     if (seg_rows < 16) seg_rows = 16;
   }
@@ -532,11 +727,21 @@ FusedShape fused_shape(const Geom& g, int seg_rows) {
 }
 
 template <int P>
+int fused_resident() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P>, FT, 0) != hipSuccess)
+    return 0;
+  return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
                              const Geom& g, const FusedShape& sh, hipStream_t s) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
   hipLaunchKernelGGL(k_step_fused<P>, dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o, c, g,
-                     sh.nseg, sh.seg_rows);
+                     sh.width, sh.nseg, sh.seg_rows);
   return hipGetLastError();
 }
 
@@ -574,6 +779,7 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
                                              const Coef<PrecT<P>::T>&, const Geom&, hipStream_t); \
   template hipError_t launch_step_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,         \
                                            const Geom&, const FusedShape&, hipStream_t);         \
+  template int fused_resident<P>();                                                              \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
                                      const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
 
