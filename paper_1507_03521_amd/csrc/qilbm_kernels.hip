@@ -712,10 +712,12 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
   sh.nstrips = (g.nx + FWMAX - 1) / FWMAX;
   sh.width = (g.nx + sh.nstrips - 1) / sh.nstrips;
   if (seg_rows <= 0) {
-    // one round of workgroups: as many segments as fit resident at once
-    // (CUs x workgroups per CU), but no segment shorter than 16 rows
-    if (resident < 1) resident = 768;
-    const int want = (resident + sh.nstrips - 1) / sh.nstrips;
+    // about 2.25 workgroups per resident slot (CUs x workgroups per CU):
+    // measured best on MI355X for all three precisions at 2048 x 8192;
+    // no segment shorter than 16 rows
+    if (resident < 1) resident = 1024;
+    const int total = (resident * 9 + 3) / 4;
+    const int want = (total + sh.nstrips - 1) / sh.nstrips;
     seg_rows = (g.ny + want - 1) / want;
     if (seg_rows < 16) seg_rows = 16;
   }
