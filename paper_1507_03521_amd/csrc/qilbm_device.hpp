@@ -71,13 +71,31 @@ template <> struct PrecT<P_F64> { using T = double; };
 template <> struct PrecT<P_F32> { using T = float; };
 template <> struct PrecT<P_F16> { using T = float; };
 
+// In the 32-bit and 16-bit storage modes the order-parameter populations g
+// are kept in fixed point Q2.29 (int32: range +-4, step 2^-29): all nine in
+// FP32 mode, g_0 (the O(1) one) in FP16-storage mode, whose g_1..8 stay
+// scaled binary16. The collision writes g_0* = phi_q - sum_{i>=1} q(g_i*)
+// with phi_q the exact integer sum of the node's pulled g, and streaming and
+// bounce-back move the stored words unchanged, so the lattice total of phi
+// is an exact integer invariant (the mass conservation of the model).
+template <int P> struct FixedG { static constexpr bool value = P != P_F64; };
+constexpr float GQ = 536870912.0f;            // 2^29
+constexpr float GQI = 1.0f / 536870912.0f;
+constexpr double GQI_D = 1.0 / 536870912.0;
+// Q2.29 contribution of a binary16 plane value: its value times 2^29, i.e.
+// the stored half times 2^29 / H_SCALE(i), a power of two.
+__host__ __device__ constexpr float HQ(int i) {
+  return i == 0 ? 16384.0f : (i <= 4 ? 4096.0f : 1024.0f);
+}
+
 // Bytes of one population buffer (18 planes).
 __host__ __device__ inline int64_t pop_bytes(int P, int64_t Ns) {
   return P == P_F64 ? 18 * Ns * 8 : (P == P_F32 ? 18 * Ns * 4 : 17 * Ns * 2 + Ns * 4);
 }
 
 // Plane k in 0..17: f_0..f_8 are k = 0..8, g_0..g_8 are k = 9..17.
-// F16 layout: f planes (binary16), then g_0 (binary32), then g_1..8 (binary16).
+// FP64: all binary64. FP32: f binary32, g Q2.29 int32. FP16 storage: f
+// planes (binary16), then g_0 (Q2.29 int32), then g_1..8 (binary16).
 // A plane's base address is uniform across the wavefront; the per-lane part
 // is a 32-bit byte offset (lattices are capped so that it cannot overflow),
 // which lets the compiler use scalar-base + 32-bit-offset addressing.
@@ -95,28 +113,73 @@ struct Pop {
   __device__ __forceinline__ static void put(char* plane, uint32_t idx, S v) {
     *reinterpret_cast<S*>(plane + idx * (uint32_t)sizeof(S)) = v;
   }
+  __device__ __forceinline__ const char* half_plane(int k) const {
+    return k < 9 ? base + k * Ns * 2 : base + 22 * Ns + (k - 10) * Ns * 2;
+  }
+  __device__ __forceinline__ static int dir(int k) { return k < 9 ? k : k - 9; }
 
+  // value of plane k at idx
   __device__ __forceinline__ T ld(int k, uint32_t idx) const {
     if constexpr (P == P_F64) {
       return at<double>(base + k * Ns * 8, idx);
     } else if constexpr (P == P_F32) {
-      return at<float>(base + k * Ns * 4, idx);
+      if (k < 9) return at<float>(base + k * Ns * 4, idx);
+      return float(at<int32_t>(base + k * Ns * 4, idx)) * GQI;
     } else {
-      if (k == 9) return at<float>(base + 18 * Ns, idx);
-      const char* h = k < 9 ? base + k * Ns * 2 : base + 22 * Ns + (k - 10) * Ns * 2;
-      return __half2float(at<__half>(h, idx)) * H_INV(k < 9 ? k : k - 9);
+      if (k == 9) return float(at<int32_t>(base + 18 * Ns, idx)) * GQI;
+      return __half2float(at<__half>(half_plane(k), idx)) * H_INV(dir(k));
     }
   }
-  __device__ __forceinline__ void st(int k, uint32_t idx, T v) const {
+  // value of plane k at idx in binary64: exact for f planes and FP64; for g
+  // planes in the fixed-point modes the Q2.29 value, the quantity whose
+  // lattice total the scheme conserves exactly
+  __device__ __forceinline__ double ld_exact(int k, uint32_t idx) const {
+    if constexpr (P == P_F64) {
+      return at<double>(base + k * Ns * 8, idx);
+    } else {
+      if (k >= 9) return double(ld_q(k, idx)) * GQI_D;
+      if constexpr (P == P_F32) return double(at<float>(base + k * Ns * 4, idx));
+      else return double(__half2float(at<__half>(half_plane(k), idx))) * double(H_INV(k));
+    }
+  }
+  // Q2.29 contribution of g plane k (9..17) at idx (fixed-point modes only)
+  __device__ __forceinline__ int32_t ld_q(int k, uint32_t idx) const {
+    if constexpr (P == P_F32) {
+      return at<int32_t>(base + k * Ns * 4, idx);
+    } else {
+      if (k == 9) return at<int32_t>(base + 18 * Ns, idx);
+      return __float2int_rn(__half2float(at<__half>(half_plane(k), idx)) * HQ(dir(k)));
+    }
+  }
+  // stores v into plane k; for g planes in the fixed-point modes returns the
+  // Q2.29 contribution of what was stored (0 otherwise)
+  __device__ __forceinline__ int32_t st(int k, uint32_t idx, T v) const {
     if constexpr (P == P_F64) {
       put<double>(base + k * Ns * 8, idx, v);
+      return 0;
     } else if constexpr (P == P_F32) {
-      put<float>(base + k * Ns * 4, idx, v);
+      if (k < 9) {
+        put<float>(base + k * Ns * 4, idx, v);
+        return 0;
+      }
+      const int32_t q = __float2int_rn(v * GQ);
+      put<int32_t>(base + k * Ns * 4, idx, q);
+      return q;
     } else {
-      if (k == 9) { put<float>(base + 18 * Ns, idx, v); return; }
-      char* h = k < 9 ? base + k * Ns * 2 : base + 22 * Ns + (k - 10) * Ns * 2;
-      put<__half>(h, idx, __float2half_rn(v * H_SCALE(k < 9 ? k : k - 9)));
+      if (k == 9) {
+        const int32_t q = __float2int_rn(v * GQ);
+        put<int32_t>(base + 18 * Ns, idx, q);
+        return q;
+      }
+      const __half h = __float2half_rn(v * H_SCALE(dir(k)));
+      put<__half>(const_cast<char*>(half_plane(k)), idx, h);
+      return k < 9 ? 0 : __float2int_rn(__half2float(h) * HQ(dir(k)));
     }
+  }
+  // stores the Q2.29 word q into g_0 (fixed-point modes)
+  __device__ __forceinline__ void st_g0_q(uint32_t idx, int32_t q) const {
+    if constexpr (P == P_F32) put<int32_t>(base + 9 * Ns * 4, idx, q);
+    else if constexpr (P == P_F16) put<int32_t>(base + 18 * Ns, idx, q);
   }
 };
 

@@ -195,14 +195,51 @@ __global__ __launch_bounds__(256) void k_macro(Pop<P> in, const typename PrecT<P
   if (mo.mu) mo.mu[n] = double(m.mu);
 }
 
+// Stores a node's post-collision populations. In the fixed-point modes g_0
+// is written as phi_q - sum_{i>=1} q(g_i), phi_q being the exact Q2.29 sum
+// of the node's pre-collision g, so the stored g of the node sum exactly to
+// phi_q.
 template <int P>
 __device__ __forceinline__ void store_node(const Pop<P>& out, uint32_t n,
                                            const typename PrecT<P>::T f[9],
-                                           const typename PrecT<P>::T gg[9]) {
+                                           const typename PrecT<P>::T gg[9], int32_t phi_q) {
 #pragma unroll
   for (int i = 0; i < 9; ++i) out.st(i, n, f[i]);
+  if constexpr (FixedG<P>::value) {
+    int32_t rest = 0;
 #pragma unroll
-  for (int i = 0; i < 9; ++i) out.st(9 + i, n, gg[i]);
+    for (int i = 1; i < 9; ++i) rest += out.st(9 + i, n, gg[i]);
+    out.st_g0_q(n, phi_q - rest);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) out.st(9 + i, n, gg[i]);
+  }
+}
+
+// Exact Q2.29 sum of the pulled g of node (x, y) (fixed-point modes).
+template <int P, int I = 0>
+__device__ __forceinline__ int32_t pull_phi_q(const Pop<P>& in, int x, int y, const Geom& g) {
+  if constexpr (I < 9) {
+    int plane;
+    uint32_t idx;
+    pull_src<I>(x, y, g, plane, idx);
+    return in.ld_q(9 + plane, idx) + pull_phi_q<P, I + 1>(in, x, y, g);
+  } else {
+    return 0;
+  }
+}
+
+// Exact binary64 sum of the pulled g of node (x, y).
+template <int P, int I = 0>
+__device__ __forceinline__ double pull_phi_exact(const Pop<P>& in, int x, int y, const Geom& g) {
+  if constexpr (I < 9) {
+    int plane;
+    uint32_t idx;
+    pull_src<I>(x, y, g, plane, idx);
+    return in.ld_exact(9 + plane, idx) + pull_phi_exact<P, I + 1>(in, x, y, g);
+  } else {
+    return 0.0;
+  }
 }
 
 // Collision with all fields materialised; post-collision values stay at
@@ -224,8 +261,10 @@ __global__ __launch_bounds__(256) void k_collide(Pop<P> in, Pop<P> out,
   T v[3][3], dpx, dpy, lapp;
   gather3x3(p, x, y, g, v);
   stencil(v, dpx, dpy, lapp);
+  int32_t phi_q = 0;
+  if constexpr (FixedG<P>::value) phi_q = pull_phi_q<P>(in, x, y, g);
   collide_node(f, gg, m, dpx, dpy, c);
-  store_node<P>(out, (uint32_t)n, f, gg);
+  store_node<P>(out, (uint32_t)n, f, gg, phi_q);
 }
 
 // ------------------------------------------------------- mass reduction
@@ -268,8 +307,12 @@ __global__ __launch_bounds__(256) void k_mass_partial(Pop<P> in,
     T f[9];
     Macro<T> m;
     node_macro<P>(in, phi, mu, x, y, c, g, f, m);
-    a[0] += double(m.phi);
-    a[1] += double(m.rho);
+    // phi and rho from the exact stored values (so that the totals show the
+    // scheme's conservation rather than the rounding of the compute type)
+    const double ph = pull_phi_exact<P>(in, x, y, g);
+    const double rho = double(c.rho_B) + double(c.drho) * ph;
+    a[0] += ph;
+    a[1] += rho;
     a[2] += double(m.rho) * double(m.ux);
     a[3] += double(m.rho) * double(m.uy);
   }
@@ -323,13 +366,15 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 // The plane and row parts of an address are uniform over a wavefront and go
 // into the scalar offset; the lane's column is one of three precomputed
 // byte offsets (x - 1, x, x + 1). Loads beyond a descriptor's range return 0.
+// Loads return the raw storage word (R), decoded only where the value is
+// first used, so that a prefetched load is not waited for early.
 constexpr int BUF_WORD3 = 0x00020000;
 typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
 
 template <int P> struct BufT;
-template <> struct BufT<P_F64> { using F = double; using G0 = double; using GR = double; };
-template <> struct BufT<P_F32> { using F = float; using G0 = float; using GR = float; };
-template <> struct BufT<P_F16> { using F = __half; using G0 = float; using GR = __half; };
+template <> struct BufT<P_F64> { using F = double; using G0 = double; using GR = double; using R = double; };
+template <> struct BufT<P_F32> { using F = float; using G0 = int32_t; using GR = int32_t; using R = uint32_t; };
+template <> struct BufT<P_F16> { using F = __half; using G0 = int32_t; using GR = __half; using R = uint32_t; };
 
 template <typename S>
 __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -359,6 +404,7 @@ struct BufPop {
   using F = typename BufT<P>::F;
   using G0 = typename BufT<P>::G0;
   using GR = typename BufT<P>::GR;
+  using R = typename BufT<P>::R;
   __amdgpu_buffer_rsrc_t rf, rg0, rgr;
   uint32_t pf, pg;     // plane strides (bytes) of the f and g_1..8 planes
 
@@ -381,52 +427,87 @@ struct BufPop {
     rg0 = __builtin_amdgcn_make_buffer_rsrc(g0, 0, (int)(Ns * sizeof(G0)), BUF_WORD3);
     rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)(8 * (int64_t)pg), BUF_WORD3);
   }
-  // value of f_i (G = false) or g_i (G = true) at plane I, element (row, col)
+  template <typename S>
+  __device__ __forceinline__ static R raw(S v) {
+    if constexpr (sizeof(S) == 8) return v;
+    else if constexpr (sizeof(S) == 4) return __builtin_bit_cast(uint32_t, v);
+    else return (uint32_t)__builtin_bit_cast(uint16_t, v);
+  }
+  // raw word of f_I (G = false) or g_I (G = true) at element (row, col[dx+1])
   template <bool G, int I>
-  __device__ __forceinline__ T ld(uint32_t elem_row, const uint32_t col[3], int dx) const {
+  __device__ __forceinline__ R ld(uint32_t elem_row, const uint32_t col[3], int dx) const {
     if constexpr (!G) {
-      const F v = buf_ld<F>(rf, col[dx + 1] * (uint32_t)sizeof(F),
-                            I * pf + elem_row * (uint32_t)sizeof(F));
-      if constexpr (P == P_F16) return __half2float(v) * H_INV(I);
-      else return v;
+      return raw(buf_ld<F>(rf, col[dx + 1] * (uint32_t)sizeof(F),
+                           I * pf + elem_row * (uint32_t)sizeof(F)));
     } else if constexpr (I == 0) {
-      return buf_ld<G0>(rg0, col[dx + 1] * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
+      return raw(buf_ld<G0>(rg0, col[dx + 1] * (uint32_t)sizeof(G0),
+                            elem_row * (uint32_t)sizeof(G0)));
     } else {
-      const GR v = buf_ld<GR>(rgr, col[dx + 1] * (uint32_t)sizeof(GR),
-                              (I - 1) * pg + elem_row * (uint32_t)sizeof(GR));
-      if constexpr (P == P_F16) return __half2float(v) * H_INV(I);
-      else return v;
+      return raw(buf_ld<GR>(rgr, col[dx + 1] * (uint32_t)sizeof(GR),
+                            (I - 1) * pg + elem_row * (uint32_t)sizeof(GR)));
     }
   }
-  template <bool G, int I>
-  __device__ __forceinline__ void st(T v, uint32_t elem_row, uint32_t col) const {
-    if constexpr (!G) {
-      F w;
-      if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
-      else w = v;
-      buf_st<F>(w, rf, col * (uint32_t)sizeof(F), I * pf + elem_row * (uint32_t)sizeof(F));
-    } else if constexpr (I == 0) {
-      buf_st<G0>(G0(v), rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
+  // decoded values of raw words
+  template <int I>
+  __device__ __forceinline__ static T val_f(R w) {
+    if constexpr (P == P_F64) return w;
+    else if constexpr (P == P_F32) return __builtin_bit_cast(float, w);
+    else return __half2float(__builtin_bit_cast(__half, (uint16_t)w)) * H_INV(I);
+  }
+  template <int I>
+  __device__ __forceinline__ static T val_g(R w) {
+    if constexpr (P == P_F64) return w;
+    else if constexpr (P == P_F32 || I == 0) return float((int32_t)w) * GQI;
+    else return __half2float(__builtin_bit_cast(__half, (uint16_t)w)) * H_INV(I);
+  }
+  // Q2.29 contribution of a raw g word (fixed-point modes)
+  template <int I>
+  __device__ __forceinline__ static int32_t q_g(R w) {
+    if constexpr (P == P_F32 || I == 0) return (int32_t)w;
+    else return __float2int_rn(__half2float(__builtin_bit_cast(__half, (uint16_t)w)) * HQ(I));
+  }
+  template <int I>
+  __device__ __forceinline__ void st_f(T v, uint32_t elem_row, uint32_t col) const {
+    F w;
+    if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
+    else w = v;
+    buf_st<F>(w, rf, col * (uint32_t)sizeof(F), I * pf + elem_row * (uint32_t)sizeof(F));
+  }
+  // stores g_I (I >= 1); returns its Q2.29 contribution in the fixed-point modes
+  template <int I>
+  __device__ __forceinline__ int32_t st_g(T v, uint32_t elem_row, uint32_t col) const {
+    const uint32_t so = (I - 1) * pg + elem_row * (uint32_t)sizeof(GR);
+    if constexpr (P == P_F64) {
+      buf_st<GR>(v, rgr, col * (uint32_t)sizeof(GR), so);
+      return 0;
+    } else if constexpr (P == P_F32) {
+      const int32_t q = __float2int_rn(v * GQ);
+      buf_st<GR>(q, rgr, col * (uint32_t)sizeof(GR), so);
+      return q;
     } else {
-      GR w;
-      if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
-      else w = v;
-      buf_st<GR>(w, rgr, col * (uint32_t)sizeof(GR), (I - 1) * pg + elem_row * (uint32_t)sizeof(GR));
+      const __half h = __float2half_rn(v * H_SCALE(I));
+      buf_st<GR>(h, rgr, col * (uint32_t)sizeof(GR), so);
+      return __float2int_rn(__half2float(h) * HQ(I));
     }
+  }
+  __device__ __forceinline__ void st_g0(T v, int32_t q, uint32_t elem_row, uint32_t col) const {
+    if constexpr (P == P_F64) buf_st<G0>(v, rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
+    else buf_st<G0>(q, rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
   }
 };
 
 // Pulls the nine pre-collision populations of row y (uniform over the
-// workgroup) at this lane's column. Off the wall rows every direction reads
-// its plane at row y - c_iy (wrapped when periodic) and column x - c_ix; on a
-// wall row the directions whose source lies beyond the wall read the
-// opposite plane at the node itself (half-way bounce-back). WALL is 0 off
-// the walls, -1 on the bottom row and +1 on the top row; the choice per
-// direction is then fixed at compile time, so every offset stays scalar.
+// workgroup) at this lane's column, as raw words. Off the wall rows every
+// direction reads its plane at row y - c_iy (wrapped when periodic) and
+// column x - c_ix; on a wall row the directions whose source lies beyond the
+// wall read the opposite plane at the node itself (half-way bounce-back).
+// WALL is 0 off the walls, -1 on the bottom row and +1 on the top row; the
+// choice per direction is then fixed at compile time, so every offset stays
+// scalar.
 template <int P, bool G, int WALL, int I = 0>
 __device__ __forceinline__ void pull_row_dirs(const BufPop<P>& B, const uint32_t rows[3],
                                               const uint32_t col[3],
-                                              typename PrecT<P>::T v[9]) {
+                                              typename BufT<P>::R v[9]) {
   if constexpr (I < 9) {
     constexpr int cx = CXS(I), cy = CYS(I);
     if constexpr ((WALL == -1 && cy == 1) || (WALL == 1 && cy == -1))
@@ -450,7 +531,7 @@ struct FusedCtx {
 
 // Pull row y (physical) of population set G.
 template <int P, bool G>
-__device__ __forceinline__ void pull_row(const FusedCtx<P>& k, int y, typename PrecT<P>::T v[9]) {
+__device__ __forceinline__ void pull_row(const FusedCtx<P>& k, int y, typename BufT<P>::R v[9]) {
   const Geom& g = k.g;
   const int nx = g.nx;
   int ym = y - 1, yp = y + 1;
@@ -467,20 +548,68 @@ __device__ __forceinline__ void pull_row(const FusedCtx<P>& k, int y, typename P
     pull_row_dirs<P, G, 0>(k.in, rows, k.col, v);
 }
 
+template <int P, int I = 1>
+__device__ __forceinline__ int32_t store_g_rest(const FusedCtx<P>& k, uint32_t row,
+                                              const typename PrecT<P>::T gg[9]) {
+  if constexpr (I < 9) {
+    const int32_t q = k.out.template st_g<I>(gg[I], row, k.col[1]);
+    return q + store_g_rest<P, I + 1>(k, row, gg);
+  } else {
+    return 0;
+  }
+}
+
 template <int P, int I = 0>
+__device__ __forceinline__ void store_f(const FusedCtx<P>& k, uint32_t row,
+                                        const typename PrecT<P>::T f[9]) {
+  if constexpr (I < 9) {
+    k.out.template st_f<I>(f[I], row, k.col[1]);
+    store_f<P, I + 1>(k, row, f);
+  }
+}
+
+// Stores a node's post-collision populations; in the fixed-point modes g_0
+// closes the node's Q2.29 sum at phi_q exactly.
+template <int P>
 __device__ __forceinline__ void store_row(const FusedCtx<P>& k, uint32_t row,
                                           const typename PrecT<P>::T f[9],
-                                          const typename PrecT<P>::T gg[9]) {
+                                          const typename PrecT<P>::T gg[9], int32_t phi_q) {
+  store_f<P>(k, row, f);
+  const int32_t rest = store_g_rest<P>(k, row, gg);
+  k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
+}
+
+// Decodes raw words in place (R holds the bits of the compute-type value
+// afterwards); for g also returns the exact Q2.29 sum.
+template <int P, int I = 0>
+__device__ __forceinline__ int32_t decode_g(typename BufT<P>::R w[9]) {
   if constexpr (I < 9) {
-    k.out.template st<false, I>(f[I], row, k.col[1]);
-    k.out.template st<true, I>(gg[I], row, k.col[1]);
-    store_row<P, I + 1>(k, row, f, gg);
+    int32_t q = 0;
+    if constexpr (FixedG<P>::value) q = BufPop<P>::template q_g<I>(w[I]);
+    const typename PrecT<P>::T v = BufPop<P>::template val_g<I>(w[I]);
+    w[I] = BufPop<P>::raw(v);
+    return q + decode_g<P, I + 1>(w);
+  } else {
+    return 0;
   }
+}
+template <int P, int I = 0>
+__device__ __forceinline__ void decode_f(typename BufT<P>::R w[9]) {
+  if constexpr (I < 9) {
+    w[I] = BufPop<P>::raw(BufPop<P>::template val_f<I>(w[I]));
+    decode_f<P, I + 1>(w);
+  }
+}
+template <int P>
+__device__ __forceinline__ typename PrecT<P>::T as_val(typename BufT<P>::R w) {
+  if constexpr (P == P_F64) return w;
+  else return __builtin_bit_cast(float, w);
 }
 
 template <typename T>
 struct FusedLds {
   T phi[8][FT];
+  int32_t phiq[8][FT];   // exact Q2.29 phi (fixed-point modes)
   T mu[4][FT];
   T p[4][FT];
   T node[2][NM][FT];   // ux, uy, Fx, Fy, drx, dry, D
@@ -521,14 +650,25 @@ __device__ __forceinline__ bool need_p(const FusedCtx<P>& k, int q) {
 
 template <int P, int J>
 __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
-                                           typename PrecT<P>::T (&gb)[4][9],
-                                           typename PrecT<P>::T (&fb)[2][9],
+                                           typename BufT<P>::R (&gb)[4][9],
+                                           typename BufT<P>::R (&fb)[2][9],
                                            FusedLds<typename PrecT<P>::T>& L) {
   using T = typename PrecT<P>::T;
   const Geom& g = k.g;
   const int lc = k.lc;
   // A: phi at row r (its g was loaded by the previous iteration)
-  if (need_phi(k, r)) L.phi[r & 7][lc] = sum9(gb[J]);
+  if (need_phi(k, r)) {
+    const int32_t q = decode_g<P>(gb[J]);
+    if constexpr (FixedG<P>::value) {
+      L.phi[r & 7][lc] = T(q) * T(GQI);
+      L.phiq[r & 7][lc] = q;
+    } else {
+      T v[9];
+#pragma unroll
+      for (int i = 0; i < 9; ++i) v[i] = as_val<P>(gb[J][i]);
+      L.phi[r & 7][lc] = sum9(v);
+    }
+  }
   __syncthreads();
   // B: mu at row r - 1
   const int b = r - 1;
@@ -542,8 +682,12 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
   // C: force, velocity, pressure at row r - 2
   const int q = r - 2;
   if (need_p(k, q)) {
+    decode_f<P>(fb[J & 1]);
+    T fv[9];
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fv[i] = as_val<P>(fb[J & 1][i]);
     T S, jx, jy;
-    moments9(fb[J & 1], S, jx, jy);
+    moments9(fv, S, jx, jy);
     T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
     lds3x3<T>(L.phi, 7, q, g.ny, g.walls, lc, v);
     stencil(v, gphx, gphy, lapphi);
@@ -568,8 +712,8 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
   T f[9], gg[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    f[i] = fb[(J + 1) & 1][i];
-    gg[i] = gb[(J + 1) & 3][i];
+    f[i] = as_val<P>(fb[(J + 1) & 1][i]);
+    gg[i] = as_val<P>(gb[(J + 1) & 3][i]);
   }
   if (need_phi(k, r + 1)) pull_row<P, true>(k, phys_row(r + 1, g), gb[(J + 1) & 3]);
   if (need_p(k, r - 1)) pull_row<P, false>(k, phys_row(r - 1, g), fb[(J + 1) & 1]);
@@ -590,8 +734,9 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
     lds3x3<T>(L.p, 3, cr, g.ny, g.walls, lc, v);
     m.p = v[1][1];
     stencil(v, dpx, dpy, lapp);
+    const int32_t phi_q = FixedG<P>::value ? L.phiq[cr & 7][lc] : 0;
     collide_node(f, gg, m, dpx, dpy, k.c);
-    store_row<P>(k, (uint32_t)(cr * g.nx), f, gg);
+    store_row<P>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
   }
 }
 
@@ -627,8 +772,8 @@ __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> 
   k.col[0] = (uint32_t)wrap_x(k.x - 1, g.nx);
   k.col[1] = (uint32_t)k.x;
   k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
-  T gb[4][9];
-  T fb[2][9];
+  typename BufT<P>::R gb[4][9];
+  typename BufT<P>::R fb[2][9];
   const int r0 = k.y0 - 3;
   const int nit = (k.y1 - k.y0) + 6;
   // prologue: g of the first row (the first f row is needed 2 iterations later
