@@ -333,19 +333,19 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 // One pass over the lattice per time step. A workgroup of FT lanes owns a
 // strip of at most FT - 2 FH columns plus FH halo columns on each side
 // (lane lc <-> column x0 - FH + lc) and a segment of rows, and sweeps the
-// rows upwards keeping rings of recent rows of phi, mu, p and the node
-// state in LDS. In the iteration that brings in row r it
+// rows in direction d (+1 or -1) keeping rings of recent rows of phi, mu,
+// p and the node state in LDS. In the iteration that brings in row r it
 //   A: forms phi(r) from the pulled g of row r (halo lanes included),
-//   B: forms mu(r-1) from the phi rows r-2..r,
-//   C: forms force, velocity and pressure at row r-2 from its pulled f and
+//   B: forms mu(r-d) from the phi rows r-2d..r,
+//   C: forms force, velocity and pressure at row r-2d from its pulled f and
 //      keeps them in LDS,
-//   D: collides row r-3, whose grad p now has all three p rows, and writes
+//   D: collides row r-3d, whose grad p now has all three p rows, and writes
 //      both post-collision populations.
 // The g values of a row stay in registers from A to D (ring of four rows),
 // the f values from C to D (ring of two), so each population is read once
 // from memory and written once. D first moves its row out of the rings and
 // refills the freed slots with the loads of the next iteration (g of row
-// r+1, f of row r-1), so their latency overlaps the collision, the stores
+// r+d, f of row r-d), so their latency overlaps the collision, the stores
 // and the barrier. Halo columns and the 3 rows of warm-up at each segment
 // end are recomputed by the neighbouring workgroups.
 constexpr int FT = 256;         // lanes per workgroup (4 wavefronts)
@@ -355,7 +355,7 @@ constexpr int NM = 7;           // node values kept from C to D
 
 // Tiles handed out so that blocks that the hardware places on one XCD
 // (consecutive blocks round-robin over 8 XCDs) get consecutive tiles, i.e.
-// vertically adjacent segments of one strip share that XCD's L2.
+// neighbouring tiles share that XCD's L2.
 __device__ __forceinline__ int xcd_tile(int bid, int n) {
   const int q = n >> 3, rem = n & 7, j = bid & 7, pos = bid >> 3;
   return j * q + (j < rem ? j : rem) + pos;
@@ -525,6 +525,7 @@ struct FusedCtx {
   Coef<T> c;
   Geom g;
   int lc, x, wi, y0, y1;
+  int d;               // sweep direction: +1 upwards, -1 downwards
   uint32_t col[3];     // element columns x - 1, x, x + 1 (wrapped)
   bool act;
 };
@@ -641,7 +642,7 @@ __device__ __forceinline__ bool row_ok(int v, const Geom& g) {
 // Row r needs phi (stage A) / row q needs F, u, p (stage C) on this lane.
 template <int P>
 __device__ __forceinline__ bool need_phi(const FusedCtx<P>& k, int r) {
-  return k.act && r < k.y1 + 3 && row_ok(r, k.g);
+  return k.act && r >= k.y0 - 3 && r < k.y1 + 3 && row_ok(r, k.g);
 }
 template <int P>
 __device__ __forceinline__ bool need_p(const FusedCtx<P>& k, int q) {
@@ -670,8 +671,8 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
     }
   }
   __syncthreads();
-  // B: mu at row r - 1
-  const int b = r - 1;
+  // B: mu at row r - d
+  const int b = r - k.d;
   if (k.act && lc >= 1 && lc < k.wi + 5 && b >= k.y0 - 2 && b < k.y1 + 2 && row_ok(b, g)) {
     T v[3][3], gx, gy, lap;
     lds3x3<T>(L.phi, 7, b, g.ny, g.walls, lc, v);
@@ -679,8 +680,8 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
     L.mu[b & 3][lc] = mu_bulk(v[1][1], k.c) - k.c.kappa * lap;
   }
   __syncthreads();
-  // C: force, velocity, pressure at row r - 2
-  const int q = r - 2;
+  // C: force, velocity, pressure at row r - 2d
+  const int q = r - 2 * k.d;
   if (need_p(k, q)) {
     decode_f<P>(fb[J & 1]);
     T fv[9];
@@ -707,16 +708,16 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
     nd[6 * FT + lc] = m.D;
   }
   __syncthreads();
-  // D: collide row r - 3 and store; meanwhile fetch the next iteration's rows
-  const int cr = r - 3;
+  // D: collide row r - 3d and store; meanwhile fetch the next iteration's rows
+  const int cr = r - 3 * k.d;
   T f[9], gg[9];
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
     f[i] = as_val<P>(fb[(J + 1) & 1][i]);
     gg[i] = as_val<P>(gb[(J + 1) & 3][i]);
   }
-  if (need_phi(k, r + 1)) pull_row<P, true>(k, phys_row(r + 1, g), gb[(J + 1) & 3]);
-  if (need_p(k, r - 1)) pull_row<P, false>(k, phys_row(r - 1, g), fb[(J + 1) & 1]);
+  if (need_phi(k, r + k.d)) pull_row<P, true>(k, phys_row(r + k.d, g), gb[(J + 1) & 3]);
+  if (need_p(k, r - k.d)) pull_row<P, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
   if (k.act && lc >= FH && lc < k.wi + FH && cr >= k.y0 && cr < k.y1) {
     Macro<T> m;
     const T* nd = &L.node[cr & 1][0][0];
@@ -751,7 +752,7 @@ template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
 template <int P>
 __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
                                                    Coef<typename PrecT<P>::T> c, Geom g, int width,
-                                                   int nseg, int seg_len) {
+                                                   int nstrips, int seg_len) {
   using T = typename PrecT<P>::T;
   __shared__ FusedLds<T> L;
   FusedCtx<P> k;
@@ -759,12 +760,19 @@ __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> 
   k.out.init(out);
   k.c = c;
   k.g = g;
+  // tiles in row-band order: the strips of one segment are consecutive, so
+  // they run together on one XCD and share their halo columns in its L2
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
-  const int strip = tile / nseg, seg = tile - strip * nseg;
+  const int seg = tile / nstrips, strip = tile - seg * nstrips;
   const int x0 = strip * width;
   k.wi = min(width, g.nx - x0);
   k.y0 = seg * seg_len;
   k.y1 = min(g.ny, k.y0 + seg_len);
+  // even segments sweep upwards, odd ones downwards: two neighbouring
+  // segments then read the rows they both need (3 warm-up rows of g and
+  // 1 of f beyond each end) at the same time, at the start or at the end of
+  // their sweeps, and the second read hits L2
+  k.d = (seg & 1) ? -1 : 1;
   const int t = threadIdx.x;
   k.act = t < k.wi + 2 * FH;
   k.lc = k.act ? t : FH;
@@ -774,16 +782,16 @@ __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> 
   k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
   typename BufT<P>::R gb[4][9];
   typename BufT<P>::R fb[2][9];
-  const int r0 = k.y0 - 3;
+  const int r0 = k.d > 0 ? k.y0 - 3 : k.y1 + 2;
   const int nit = (k.y1 - k.y0) + 6;
   // prologue: g of the first row (the first f row is needed 2 iterations later
   // and is fetched by iteration 1)
   if (need_phi(k, r0)) pull_row<P, true>(k, phys_row(r0, g), gb[0]);
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, 0>(k, r0 + it + 0, gb, fb, L);
-    fused_iter<P, 1>(k, r0 + it + 1, gb, fb, L);
-    fused_iter<P, 2>(k, r0 + it + 2, gb, fb, L);
-    fused_iter<P, 3>(k, r0 + it + 3, gb, fb, L);
+    fused_iter<P, 0>(k, r0 + k.d * (it + 0), gb, fb, L);
+    fused_iter<P, 1>(k, r0 + k.d * (it + 1), gb, fb, L);
+    fused_iter<P, 2>(k, r0 + k.d * (it + 2), gb, fb, L);
+    fused_iter<P, 3>(k, r0 + k.d * (it + 3), gb, fb, L);
   }
 }
 
@@ -857,14 +865,16 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
   sh.nstrips = (g.nx + FWMAX - 1) / FWMAX;
   sh.width = (g.nx + sh.nstrips - 1) / sh.nstrips;
   if (seg_rows <= 0) {
-    // about 2.25 workgroups per resident slot (CUs x workgroups per CU):
-    // measured best on MI355X for all three precisions at 2048 x 8192;
-    // no segment shorter than 16 rows
+    // about 2.25 workgroups per resident slot (CUs x workgroups per CU),
+    // segments of 16..32 rows: measured best on MI355X for all three
+    // precisions at 2048 x 8192 (longer segments leave the last wave of
+    // workgroups too unbalanced, shorter ones recompute more warm-up rows)
     if (resident < 1) resident = 1024;
     const int total = (resident * 9 + 3) / 4;
     const int want = (total + sh.nstrips - 1) / sh.nstrips;
     seg_rows = (g.ny + want - 1) / want;
     if (seg_rows < 16) seg_rows = 16;
+    if (seg_rows > 32) seg_rows = 32;
   }
   if (seg_rows > g.ny) seg_rows = g.ny;
   sh.seg_rows = seg_rows;
@@ -888,7 +898,7 @@ hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename Pr
                              const Geom& g, const FusedShape& sh, hipStream_t s) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
   hipLaunchKernelGGL(k_step_fused<P>, dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o, c, g,
-                     sh.width, sh.nseg, sh.seg_rows);
+                     sh.width, sh.nstrips, sh.seg_rows);
   return hipGetLastError();
 }
 
