@@ -80,7 +80,8 @@ typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_WALLS_Y = 1 } lbm_bc;
                                  to rounding; used for cross-checks)        */
 
 typedef struct {
-  int32_t nx, ny;         /* lattice size; nx >= 3, ny >= 3                  */
+  int32_t nx, ny;         /* lattice size; nx >= 3, ny >= 3,
+                             nx * ny <= 2^29 - 4096                          */
   double rho_A, rho_B;    /* densities of fluid A (phi = 1) and B (phi = 0) */
   double sigma;           /* surface tension, > 0                            */
   double W;               /* interface width in lattice units, > 0          */
@@ -110,8 +111,10 @@ lbm_status lbm_coefficients(const lbm_params* params, double out[6]);
  * p = 0, hence f_i = f_i^eq = 0, and g_i = H_i(phi0, mu0) with
  * mu0 = mu(phi0) (Sec. III equilibria), so that sum_i g_i = phi0.
  * workspace_dev: caller-owned, at least lbm_workspace_bytes(params) bytes,
- * 256-byte aligned, kept alive until lbm_destroy. stream: a hipStream_t
- * (NULL = default stream). On success *out receives the context. */
+ * 256-byte aligned, kept alive until lbm_destroy; lbm_init zeroes its
+ * population buffers (padding included, so raw snapshots of equal states
+ * are equal byte for byte). stream: a hipStream_t (NULL = default stream).
+ * On success *out receives the context. */
 lbm_status lbm_init(lbm_ctx** out, const lbm_params* params,
                     void* workspace_dev, size_t workspace_bytes,
                     const double* phi0_dev, void* stream);
@@ -158,11 +161,13 @@ int64_t lbm_time(const lbm_ctx* ctx);
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 
 /* Launch shape of the fused step kernel: rows per workgroup segment
- * (0 = automatic, about 2048 workgroups). Results do not depend on it. */
+ * (0 = automatic: about 2.25 workgroups per resident slot, 16..32 rows).
+ * Results do not depend on it. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t seg_rows);
 
-/* Current fused launch shape into out[4] (host): strips of 256 columns,
- * segments per strip, rows per segment, threads per workgroup. */
+/* Current fused launch shape into out[4] (host): column strips (of equal
+ * width, at most 250 columns), segments per strip, rows per segment,
+ * threads per workgroup. */
 lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
 
 /* ---------------------------------------------------------------- adjoint

@@ -542,7 +542,7 @@ struct AdjLayout {
 
 AdjLayout adj_layout(const lbm_params* p) {
   const int64_t N = (int64_t)p->nx * p->ny;
-  const int64_t Ns = (N + 255) / 256 * 256;
+  const int64_t Ns = plane_stride(N);
   const size_t ts = p->precision == LBM_FP64 ? 8 : 4;
   AdjLayout L;
   L.nred = (int)((N + 255) / 256);

@@ -47,8 +47,9 @@ bool finite_all(const lbm_params* p) {
 bool valid(const lbm_params* p) {
   if (!p) return false;
   if (p->nx < 3 || p->ny < 3) return false;
-  // 32-bit per-lane byte offsets inside a population plane (8-byte values)
-  if ((int64_t)p->nx * (int64_t)p->ny > ((int64_t)1 << 29) - 256) return false;
+  // 32-bit byte offsets inside a population plane (8-byte values, plane
+  // stride below 2^29 elements including the stagger)
+  if ((int64_t)p->nx * (int64_t)p->ny > ((int64_t)1 << 29) - 4096) return false;
   if (!finite_all(p)) return false;
   if (!(p->rho_A > 0.0) || !(p->rho_B > 0.0)) return false;
   if (!(p->sigma > 0.0) || !(p->W > 0.0) || !(p->M > 0.0)) return false;
@@ -65,7 +66,7 @@ Geom make_geom(const lbm_params* p) {
   g.ny = p->ny;
   g.walls = p->bc == LBM_BC_WALLS_Y;
   g.N = (int64_t)p->nx * p->ny;
-  g.Ns = (g.N + 255) / 256 * 256;
+  g.Ns = plane_stride(g.N);
   return g;
 }
 
@@ -221,8 +222,12 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
   c->resident = QILBM_DISPATCH(params->precision, fused_resident);
   c->pbytes = pop_bytes(params->precision, c->geom.Ns);
   Coef<double> k = coef_t<double>(c);
-  const hipError_t e = QILBM_DISPATCH(params->precision, launch_init, phi0_dev, c->pop[0], k,
-                                      c->geom, c->stream);
+  // both population buffers start zeroed, padding included, so that raw
+  // snapshots of equal states are equal byte for byte
+  hipError_t e = launch_zero(c->ws + L.pop0, L.fields - L.pop0, c->stream);
+  if (e == hipSuccess)
+    e = QILBM_DISPATCH(params->precision, launch_init, phi0_dev, c->pop[0], k, c->geom,
+                       c->stream);
   if (e != hipSuccess) {
     delete c;
     return LBM_EDEVICE;

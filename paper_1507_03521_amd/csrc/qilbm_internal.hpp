@@ -8,6 +8,14 @@
 
 namespace qilbm {
 
+// Stride (elements) between the planes of every per-node array: N rounded
+// up to 256, plus a stagger of 2304 elements so that the planes a row
+// touches at one column do not all start at the same offset modulo a large
+// power of two (a power-of-two lattice would otherwise send all 18 plane
+// streams to the same memory channels; the stagger is worth ~3 % at
+// 2048 x 8192 on MI355X). The one definition used by every layout.
+inline int64_t plane_stride(int64_t N) { return (N + 255) / 256 * 256 + 2304; }
+
 // FP64 outputs of the moments kernel; NULL members are skipped.
 struct MomentOut {
   double* phi = nullptr;
@@ -30,6 +38,15 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident);
 // Workgroups of the fused kernel that the current device holds at once.
 template <int P>
 int fused_resident();
+
+// True when a group of population planes spans more than 4 GiB - 1 bytes:
+// the fused kernel then addresses every plane with its own descriptor.
+template <int P>
+bool fused_big(const Geom& g);
+
+// Zeroes bytes (a multiple of 16, 16-byte aligned) of device memory with a
+// kernel (no memset node, so the call may sit in a captured graph).
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s);
 
 template <int P>
 hipError_t launch_init(const double* phi0, void* pop, const Coef<double>& c, const Geom& g,

@@ -398,7 +398,11 @@ __device__ __forceinline__ void buf_st(S v, __amdgpu_buffer_rsrc_t r, uint32_t v
   }
 }
 
-template <int P>
+// BIG: a group of population planes (f_0..8 or g_1..8) spans 4 GiB or more,
+// beyond the 32-bit range of one descriptor; every access then builds a
+// descriptor for its own plane (scalar work only) and the scalar offset
+// holds the row alone.
+template <int P, bool BIG = false>
 struct BufPop {
   using T = typename PrecT<P>::T;
   using F = typename BufT<P>::F;
@@ -407,6 +411,7 @@ struct BufPop {
   using R = typename BufT<P>::R;
   __amdgpu_buffer_rsrc_t rf, rg0, rgr;
   uint32_t pf, pg;     // plane strides (bytes) of the f and g_1..8 planes
+  char *fp, *gp;       // first f plane and g_1 plane
 
   __device__ __forceinline__ void init(const Pop<P>& p) {
     const int64_t Ns = p.Ns;
@@ -421,11 +426,15 @@ struct BufPop {
       g0 = b + 9 * Ns * (int64_t)sizeof(T);
       gr = b + 10 * Ns * (int64_t)sizeof(T);
     }
+    fp = f;
+    gp = gr;
     pf = (uint32_t)(Ns * sizeof(F));
     pg = (uint32_t)(Ns * sizeof(GR));
-    rf = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(9 * (int64_t)pf), BUF_WORD3);
     rg0 = __builtin_amdgcn_make_buffer_rsrc(g0, 0, (int)(Ns * sizeof(G0)), BUF_WORD3);
-    rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)(8 * (int64_t)pg), BUF_WORD3);
+    if constexpr (!BIG) {
+      rf = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(9 * (int64_t)pf), BUF_WORD3);
+      rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)(8 * (int64_t)pg), BUF_WORD3);
+    }
   }
   template <typename S>
   __device__ __forceinline__ static R raw(S v) {
@@ -433,18 +442,35 @@ struct BufPop {
     else if constexpr (sizeof(S) == 4) return __builtin_bit_cast(uint32_t, v);
     else return (uint32_t)__builtin_bit_cast(uint16_t, v);
   }
+  // descriptor and scalar offset of f_I / g_I (I >= 1) at element row elem_row
+  template <int I>
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t f_rsrc() const {
+    if constexpr (BIG) return __builtin_amdgcn_make_buffer_rsrc(fp + (int64_t)I * pf, 0, (int)pf, BUF_WORD3);
+    else return rf;
+  }
+  template <int I>
+  __device__ __forceinline__ uint32_t f_soff(uint32_t elem_row) const {
+    return (BIG ? 0u : I * pf) + elem_row * (uint32_t)sizeof(F);
+  }
+  template <int I>
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t g_rsrc() const {
+    if constexpr (BIG) return __builtin_amdgcn_make_buffer_rsrc(gp + (int64_t)(I - 1) * pg, 0, (int)pg, BUF_WORD3);
+    else return rgr;
+  }
+  template <int I>
+  __device__ __forceinline__ uint32_t g_soff(uint32_t elem_row) const {
+    return (BIG ? 0u : (I - 1) * pg) + elem_row * (uint32_t)sizeof(GR);
+  }
   // raw word of f_I (G = false) or g_I (G = true) at element (row, col[dx+1])
   template <bool G, int I>
   __device__ __forceinline__ R ld(uint32_t elem_row, const uint32_t col[3], int dx) const {
     if constexpr (!G) {
-      return raw(buf_ld<F>(rf, col[dx + 1] * (uint32_t)sizeof(F),
-                           I * pf + elem_row * (uint32_t)sizeof(F)));
+      return raw(buf_ld<F>(f_rsrc<I>(), col[dx + 1] * (uint32_t)sizeof(F), f_soff<I>(elem_row)));
     } else if constexpr (I == 0) {
       return raw(buf_ld<G0>(rg0, col[dx + 1] * (uint32_t)sizeof(G0),
                             elem_row * (uint32_t)sizeof(G0)));
     } else {
-      return raw(buf_ld<GR>(rgr, col[dx + 1] * (uint32_t)sizeof(GR),
-                            (I - 1) * pg + elem_row * (uint32_t)sizeof(GR)));
+      return raw(buf_ld<GR>(g_rsrc<I>(), col[dx + 1] * (uint32_t)sizeof(GR), g_soff<I>(elem_row)));
     }
   }
   // decoded values of raw words
@@ -471,22 +497,22 @@ struct BufPop {
     F w;
     if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
     else w = v;
-    buf_st<F>(w, rf, col * (uint32_t)sizeof(F), I * pf + elem_row * (uint32_t)sizeof(F));
+    buf_st<F>(w, f_rsrc<I>(), col * (uint32_t)sizeof(F), f_soff<I>(elem_row));
   }
   // stores g_I (I >= 1); returns its Q2.29 contribution in the fixed-point modes
   template <int I>
   __device__ __forceinline__ int32_t st_g(T v, uint32_t elem_row, uint32_t col) const {
-    const uint32_t so = (I - 1) * pg + elem_row * (uint32_t)sizeof(GR);
+    const uint32_t so = g_soff<I>(elem_row);
     if constexpr (P == P_F64) {
-      buf_st<GR>(v, rgr, col * (uint32_t)sizeof(GR), so);
+      buf_st<GR>(v, g_rsrc<I>(), col * (uint32_t)sizeof(GR), so);
       return 0;
     } else if constexpr (P == P_F32) {
       const int32_t q = __float2int_rn(v * GQ);
-      buf_st<GR>(q, rgr, col * (uint32_t)sizeof(GR), so);
+      buf_st<GR>(q, g_rsrc<I>(), col * (uint32_t)sizeof(GR), so);
       return q;
     } else {
       const __half h = __float2half_rn(v * H_SCALE(I));
-      buf_st<GR>(h, rgr, col * (uint32_t)sizeof(GR), so);
+      buf_st<GR>(h, g_rsrc<I>(), col * (uint32_t)sizeof(GR), so);
       return __float2int_rn(__half2float(h) * HQ(I));
     }
   }
@@ -504,8 +530,8 @@ struct BufPop {
 // WALL is 0 off the walls, -1 on the bottom row and +1 on the top row; the
 // choice per direction is then fixed at compile time, so every offset stays
 // scalar.
-template <int P, bool G, int WALL, int I = 0>
-__device__ __forceinline__ void pull_row_dirs(const BufPop<P>& B, const uint32_t rows[3],
+template <int P, bool BIG, bool G, int WALL, int I = 0>
+__device__ __forceinline__ void pull_row_dirs(const BufPop<P, BIG>& B, const uint32_t rows[3],
                                               const uint32_t col[3],
                                               typename BufT<P>::R v[9]) {
   if constexpr (I < 9) {
@@ -514,14 +540,14 @@ __device__ __forceinline__ void pull_row_dirs(const BufPop<P>& B, const uint32_t
       v[I] = B.template ld<G, OPP(I)>(rows[1], col, 0);
     else
       v[I] = B.template ld<G, I>(rows[1 - cy], col, -cx);
-    pull_row_dirs<P, G, WALL, I + 1>(B, rows, col, v);
+    pull_row_dirs<P, BIG, G, WALL, I + 1>(B, rows, col, v);
   }
 }
 
-template <int P>
+template <int P, bool BIG>
 struct FusedCtx {
   using T = typename PrecT<P>::T;
-  BufPop<P> in, out;
+  BufPop<P, BIG> in, out;
   Coef<T> c;
   Geom g;
   int lc, x, wi, y0, y1;
@@ -531,8 +557,8 @@ struct FusedCtx {
 };
 
 // Pull row y (physical) of population set G.
-template <int P, bool G>
-__device__ __forceinline__ void pull_row(const FusedCtx<P>& k, int y, typename BufT<P>::R v[9]) {
+template <int P, bool BIG, bool G>
+__device__ __forceinline__ void pull_row(const FusedCtx<P, BIG>& k, int y, typename BufT<P>::R v[9]) {
   const Geom& g = k.g;
   const int nx = g.nx;
   int ym = y - 1, yp = y + 1;
@@ -542,41 +568,41 @@ __device__ __forceinline__ void pull_row(const FusedCtx<P>& k, int y, typename B
   }
   const uint32_t rows[3] = {(uint32_t)(ym * nx), (uint32_t)(y * nx), (uint32_t)(yp * nx)};
   if (g.walls && y == 0)
-    pull_row_dirs<P, G, -1>(k.in, rows, k.col, v);
+    pull_row_dirs<P, BIG, G, -1>(k.in, rows, k.col, v);
   else if (g.walls && y == g.ny - 1)
-    pull_row_dirs<P, G, 1>(k.in, rows, k.col, v);
+    pull_row_dirs<P, BIG, G, 1>(k.in, rows, k.col, v);
   else
-    pull_row_dirs<P, G, 0>(k.in, rows, k.col, v);
+    pull_row_dirs<P, BIG, G, 0>(k.in, rows, k.col, v);
 }
 
-template <int P, int I = 1>
-__device__ __forceinline__ int32_t store_g_rest(const FusedCtx<P>& k, uint32_t row,
+template <int P, bool BIG, int I = 1>
+__device__ __forceinline__ int32_t store_g_rest(const FusedCtx<P, BIG>& k, uint32_t row,
                                               const typename PrecT<P>::T gg[9]) {
   if constexpr (I < 9) {
     const int32_t q = k.out.template st_g<I>(gg[I], row, k.col[1]);
-    return q + store_g_rest<P, I + 1>(k, row, gg);
+    return q + store_g_rest<P, BIG, I + 1>(k, row, gg);
   } else {
     return 0;
   }
 }
 
-template <int P, int I = 0>
-__device__ __forceinline__ void store_f(const FusedCtx<P>& k, uint32_t row,
+template <int P, bool BIG, int I = 0>
+__device__ __forceinline__ void store_f(const FusedCtx<P, BIG>& k, uint32_t row,
                                         const typename PrecT<P>::T f[9]) {
   if constexpr (I < 9) {
     k.out.template st_f<I>(f[I], row, k.col[1]);
-    store_f<P, I + 1>(k, row, f);
+    store_f<P, BIG, I + 1>(k, row, f);
   }
 }
 
 // Stores a node's post-collision populations; in the fixed-point modes g_0
 // closes the node's Q2.29 sum at phi_q exactly.
-template <int P>
-__device__ __forceinline__ void store_row(const FusedCtx<P>& k, uint32_t row,
+template <int P, bool BIG>
+__device__ __forceinline__ void store_row(const FusedCtx<P, BIG>& k, uint32_t row,
                                           const typename PrecT<P>::T f[9],
                                           const typename PrecT<P>::T gg[9], int32_t phi_q) {
-  store_f<P>(k, row, f);
-  const int32_t rest = store_g_rest<P>(k, row, gg);
+  store_f<P, BIG>(k, row, f);
+  const int32_t rest = store_g_rest<P, BIG>(k, row, gg);
   k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
 }
 
@@ -640,17 +666,17 @@ __device__ __forceinline__ bool row_ok(int v, const Geom& g) {
 }
 
 // Row r needs phi (stage A) / row q needs F, u, p (stage C) on this lane.
-template <int P>
-__device__ __forceinline__ bool need_phi(const FusedCtx<P>& k, int r) {
+template <int P, bool BIG>
+__device__ __forceinline__ bool need_phi(const FusedCtx<P, BIG>& k, int r) {
   return k.act && r >= k.y0 - 3 && r < k.y1 + 3 && row_ok(r, k.g);
 }
-template <int P>
-__device__ __forceinline__ bool need_p(const FusedCtx<P>& k, int q) {
+template <int P, bool BIG>
+__device__ __forceinline__ bool need_p(const FusedCtx<P, BIG>& k, int q) {
   return k.act && k.lc >= 2 && k.lc < k.wi + 4 && q >= k.y0 - 1 && q < k.y1 + 1 && row_ok(q, k.g);
 }
 
-template <int P, int J>
-__device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
+template <int P, bool BIG, int J>
+__device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
                                            typename BufT<P>::R (&gb)[4][9],
                                            typename BufT<P>::R (&fb)[2][9],
                                            FusedLds<typename PrecT<P>::T>& L) {
@@ -716,8 +742,8 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
     f[i] = as_val<P>(fb[(J + 1) & 1][i]);
     gg[i] = as_val<P>(gb[(J + 1) & 3][i]);
   }
-  if (need_phi(k, r + k.d)) pull_row<P, true>(k, phys_row(r + k.d, g), gb[(J + 1) & 3]);
-  if (need_p(k, r - k.d)) pull_row<P, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
+  if (need_phi(k, r + k.d)) pull_row<P, BIG, true>(k, phys_row(r + k.d, g), gb[(J + 1) & 3]);
+  if (need_p(k, r - k.d)) pull_row<P, BIG, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
   if (k.act && lc >= FH && lc < k.wi + FH && cr >= k.y0 && cr < k.y1) {
     Macro<T> m;
     const T* nd = &L.node[cr & 1][0][0];
@@ -737,7 +763,7 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
     stencil(v, dpx, dpy, lapp);
     const int32_t phi_q = FixedG<P>::value ? L.phiq[cr & 7][lc] : 0;
     collide_node(f, gg, m, dpx, dpy, k.c);
-    store_row<P>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
+    store_row<P, BIG>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
   }
 }
 
@@ -749,13 +775,13 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P>& k, int r,
 template <int P> struct FusedWaves { static constexpr int value = QILBM_FUSED_WAVES32; };
 template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
 
-template <int P>
+template <int P, bool BIG>
 __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
                                                    Coef<typename PrecT<P>::T> c, Geom g, int width,
                                                    int nstrips, int seg_len) {
   using T = typename PrecT<P>::T;
   __shared__ FusedLds<T> L;
-  FusedCtx<P> k;
+  FusedCtx<P, BIG> k;
   k.in.init(in);
   k.out.init(out);
   k.c = c;
@@ -786,17 +812,30 @@ __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> 
   const int nit = (k.y1 - k.y0) + 6;
   // prologue: g of the first row (the first f row is needed 2 iterations later
   // and is fetched by iteration 1)
-  if (need_phi(k, r0)) pull_row<P, true>(k, phys_row(r0, g), gb[0]);
+  if (need_phi(k, r0)) pull_row<P, BIG, true>(k, phys_row(r0, g), gb[0]);
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, 0>(k, r0 + k.d * (it + 0), gb, fb, L);
-    fused_iter<P, 1>(k, r0 + k.d * (it + 1), gb, fb, L);
-    fused_iter<P, 2>(k, r0 + k.d * (it + 2), gb, fb, L);
-    fused_iter<P, 3>(k, r0 + k.d * (it + 3), gb, fb, L);
+    fused_iter<P, BIG, 0>(k, r0 + k.d * (it + 0), gb, fb, L);
+    fused_iter<P, BIG, 1>(k, r0 + k.d * (it + 1), gb, fb, L);
+    fused_iter<P, BIG, 2>(k, r0 + k.d * (it + 2), gb, fb, L);
+    fused_iter<P, BIG, 3>(k, r0 + k.d * (it + 3), gb, fb, L);
   }
 }
 
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+__global__ __launch_bounds__(256) void k_zero_words(uint4* __restrict__ p, int64_t n16) {
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n16; i += (int64_t)gridDim.x * 256)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+}
+
+hipError_t launch_zero(void* p, size_t bytes, hipStream_t s) {
+  const int64_t n16 = (int64_t)(bytes / 16);
+  if (n16 == 0) return hipSuccess;
+  const unsigned grid = nblk(n16, 256) < 8192u ? nblk(n16, 256) : 8192u;
+  hipLaunchKernelGGL(k_zero_words, dim3(grid), dim3(256), 0, s, (uint4*)p, n16);
+  return hipGetLastError();
+}
 
 template <int P>
 hipError_t launch_init(const double* phi0, void* pop, const Coef<double>& c, const Geom& g,
@@ -884,11 +923,18 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
 }
 
 template <int P>
+bool fused_big(const Geom& g) {
+  const int64_t f_group = 9 * g.Ns * (int64_t)sizeof(typename BufT<P>::F);
+  const int64_t g_group = 8 * g.Ns * (int64_t)sizeof(typename BufT<P>::GR);
+  return f_group > (int64_t)UINT32_MAX || g_group > (int64_t)UINT32_MAX;
+}
+
+template <int P>
 int fused_resident() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P>, FT, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P, false>, FT, 0) != hipSuccess)
     return 0;
   return cus * (per_cu > 0 ? per_cu : 1);
 }
@@ -897,8 +943,12 @@ template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
                              const Geom& g, const FusedShape& sh, hipStream_t s) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
-  hipLaunchKernelGGL(k_step_fused<P>, dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o, c, g,
-                     sh.width, sh.nstrips, sh.seg_rows);
+  if (fused_big<P>(g))
+    hipLaunchKernelGGL((k_step_fused<P, true>), dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o,
+                       c, g, sh.width, sh.nstrips, sh.seg_rows);
+  else
+    hipLaunchKernelGGL((k_step_fused<P, false>), dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o,
+                       c, g, sh.width, sh.nstrips, sh.seg_rows);
   return hipGetLastError();
 }
 
@@ -937,6 +987,7 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
   template hipError_t launch_step_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,         \
                                            const Geom&, const FusedShape&, hipStream_t);         \
   template int fused_resident<P>();                                                              \
+  template bool fused_big<P>(const Geom&);                                                       \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
                                      const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
 

@@ -333,8 +333,9 @@ def _q229_total(raw, precision, nx, ny):
     state buffer (Q2.29 words; binary16 g_1..8 mapped to Q2.29 the way the
     kernels map them)."""
     N = nx * ny
-    Ns = (N + 255) // 256 * 256
-    raw = raw.cpu()
+    # plane stride from the buffer size: 18 planes of 4 bytes (FP32) or
+    # 17 of 2 bytes + 1 of 4 (FP16 storage)
+    Ns = raw.numel() // (72 if precision == "fp32" else 38)
     if precision == "fp32":
         words = raw[9 * Ns * 4:18 * Ns * 4].view(torch.int32).view(9, Ns)[:, :N]
         return int(words.to(torch.int64).sum())
@@ -363,3 +364,65 @@ def test_reduced_precision_conserves_mass_exactly(precision, bc):
     m1 = lat.mass()
     assert q1 == q0
     assert abs(m1[0] - m0[0]) <= 1e-13 * abs(m0[0])
+
+
+# Lattices whose population plane groups exceed the 4 GiB range of one
+# buffer descriptor (the fused kernel then addresses every plane with its own
+# descriptor): nodes just above the threshold for each storage precision.
+# The two paths evaluate the same arithmetic in different orders, so they
+# agree to rounding, not bitwise. Tolerances (f, g) relative to the largest
+# magnitude: FP64 as the one-step oracle parity; FP32 and FP16 storage as the
+# full-size tests that start from the equilibrium initial state, where f is
+# small and formed by cancellation (an addressing error would be O(1)).
+BIG_SHAPES = [("fp64", 4000, 15000, (1e-12, 1e-12)), ("fp32", 8000, 15000, (2e-3, 1e-6)),
+              ("fp16", 16000, 15000, (4e-3, 1e-5)),
+              ("fp64", 300, 41, (1e-12, 1e-12)), ("fp32", 300, 41, (2e-3, 1e-6)),
+              ("fp16", 300, 41, (4e-3, 1e-5))]
+
+
+@pytest.mark.parametrize("precision,nx,ny,tol", BIG_SHAPES)
+def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol):
+    """At sizes where nine planes of populations span more than 4 GiB (and,
+    for comparison, at a small size), two fused steps (walls and gravity on)
+    agree with two steps of the unfused kernels, which address memory with
+    64-bit pointers; in the fixed-point modes both conserve the exact
+    integer total of g."""
+    from paper_1507_03521_amd import LBM_FLAG_UNFUSED, Lattice
+    pb = wl.rt2048().with_(nx=nx, ny=ny)
+    dev = torch.device("cuda:0")
+    y = torch.arange(ny, device=dev, dtype=torch.float64)[:, None]
+    x = torch.arange(nx, device=dev, dtype=torch.float64)[None, :]
+    h = ny / 2 + 40.0 * torch.cos(2 * math.pi * 3 * x / nx)
+    phi0 = 0.5 + 0.5 * torch.tanh(2.0 * (y - h) / pb.W)
+    del x, y, h
+    states, raws_equal = [], None
+    first_raw = None
+    for flags in (0, LBM_FLAG_UNFUSED):
+        lat = Lattice(pb.as_dict(), phi0, precision=precision, flags=flags, device=dev)
+        per_node = {"fp64": 144, "fp32": 72, "fp16": 38}[precision]
+        Ns = lat.state_bytes // per_node
+        elem = {"fp64": 8, "fp32": 4, "fp16": 2}[precision]
+        # the per-plane addressing is in use at the large sizes only
+        assert (9 * Ns * elem > 2**32 - 1) == (nx * ny > 10**7)
+        if precision != "fp64":
+            q0 = _q229_total(lat.save_raw(), precision, nx, ny)
+        lat.step(2)
+        raw = lat.save_raw()
+        if precision != "fp64":
+            assert _q229_total(raw, precision, nx, ny) == q0
+        if first_raw is None:
+            first_raw = raw.clone()
+        else:
+            raws_equal = bool(torch.equal(first_raw, raw))
+        del raw
+        states.append(lat.get_state())
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    del first_raw
+    (f0, g0), (f1, g1) = states
+    ef = float((f0 - f1).abs().max() / f1.abs().max())
+    eg = float((g0 - g1).abs().max() / g1.abs().max())
+    print(f"{precision} {nx}x{ny}: fused vs unfused rel f {ef:.2e} g {eg:.2e}, "
+          f"raw bitwise equal: {raws_equal}", flush=True)
+    assert ef <= tol[0] and eg <= tol[1]
