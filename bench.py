@@ -144,6 +144,64 @@ def cpu_baseline(pb, phi0, rows: int, steps: int):
                        f"of the {pb.nx}x{pb.ny} Rayleigh-Taylor lattice, {dt:.1f} s")
 
 
+def interface_tips(phi, nx):
+    """Spike tip: lowest phi = 1/2 crossing along x = nx/2 (heavy fluid
+    falling); bubble tip: highest crossing along x = 0 (light fluid rising);
+    linear interpolation between nodes."""
+    def crossings(col):
+        c = col.cpu().numpy()
+        return [y + (0.5 - c[y]) / (c[y + 1] - c[y]) for y in range(len(c) - 1)
+                if (c[y] - 0.5) * (c[y + 1] - 0.5) < 0]
+    lo, hi = crossings(phi[:, nx // 2]), crossings(phi[:, 0])
+    return (min(lo) if lo else float("nan")), (max(hi) if hi else float("nan"))
+
+
+def precision_study(pb, phi0, steps: int, every: int):
+    """Long run of the same workload in FP64, FP32 and FP16 storage: tip
+    positions every ``every`` steps, mass drift, and the deviation of the
+    reduced-precision runs from the FP64 GPU run."""
+    import torch
+    from paper_1507_03521_amd import Lattice, QilbmError
+    out, phi64, tips64 = {}, None, None
+    t_unit = math.sqrt(abs(pb.gy) / pb.nx)        # t* = t sqrt(g / L), L = nx
+    for prec in ("fp64", "fp32", "fp16"):
+        lat = Lattice(pb.as_dict(), phi0, precision=prec, device="cuda:0")
+        m0 = lat.mass()
+        tips, diverged, t0 = [], None, time.perf_counter()
+        done = 0
+        while done < steps:
+            n = min(every, steps - done)
+            lat.step(n)
+            done += n
+            try:
+                lat.mass()
+            except QilbmError:
+                diverged = done
+                log(f"  {prec}: non-finite state by step {done}")
+                break
+            s, b = interface_tips(lat.moments(("phi",))["phi"], pb.nx)
+            tips.append((done, round(s, 4), round(b, 4)))
+            log(f"  {prec}: step {done}/{steps} (t* {done * t_unit:.3f}) spike {s:.3f} "
+                f"bubble {b:.3f}, {time.perf_counter() - t0:.0f} s")
+        r = dict(tips_every=every, tips=tips, diverged_at=diverged,
+                 seconds=round(time.perf_counter() - t0, 1))
+        if diverged is None:
+            m1 = lat.mass()
+            r["mass_drift_rel"] = abs(m1[1] - m0[1]) / abs(m0[1])
+            phi = lat.moments(("phi",))["phi"]
+            if prec == "fp64":
+                phi64, tips64 = phi, tips
+            elif phi64 is not None:
+                r["phi_max_abs_dev_vs_fp64"] = float((phi - phi64).abs().max())
+                r["tip_max_abs_dev_vs_fp64"] = max(
+                    max(abs(a[1] - b[1]), abs(a[2] - b[2])) for a, b in zip(tips, tips64))
+        out[prec] = r
+        del lat
+        torch.cuda.empty_cache()
+    return dict(study="precision", workload=f"{pb.name} {pb.nx}x{pb.ny}", steps=steps,
+                t_star=round(steps * t_unit, 4), **out)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,6 +216,10 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (PMC byte-counter calibration)")
+    ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
+                    help="instead of timing: run STEPS steps in each precision and print "
+                         "tip positions, mass drift and deviation from FP64 (one JSON line)")
+    ap.add_argument("--study-every", type=int, default=5000)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -170,6 +232,10 @@ def main():
     pb = wl.rt2048()
     phi0 = wl.phi0(pb)
     N = pb.nx * pb.ny
+    if args.precision_study:
+        print(json.dumps(precision_study(pb, phi0, args.precision_study, args.study_every)),
+              flush=True)
+        return
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
         dst = torch.empty_like(src)
