@@ -14,7 +14,9 @@
 //
 // The adjoint populations are kept in the canonical pre-collision layout
 // ([18][ny][nx], compute type); the forward state s_t is recomputed by the
-// caller and handed in raw (pull layout). Cotangents of beta, kappa, lambda,
+// caller and handed in raw (pull layout). The direct (diagonal) part of the
+// collision transpose, (1 - 1/tau) times the post-collision cotangent, is
+// recomputed where it is added rather than stored. Cotangents of beta, kappa, lambda,
 // alpha are summed in FP64 in a fixed block order (run-to-run reproducible)
 // and turned into dL/dsigma and dL/dM at the end (beta, kappa are
 // proportional to sigma at fixed W; lambda = M and alpha = M/(c_s^2 (tau_g - 1/2))).
@@ -38,6 +40,45 @@ struct AF {
   __device__ __forceinline__ T* operator[](int k) const { return base + (int64_t)k * Ns; }
 };
 
+// ------------------------------------------------------- node indexing
+// Element offsets around node (x, y), all 32-bit (N < 2^29):
+//   rs: rows y-1, y, y+1 as the forward stencils see them (periodic wrap or
+//       the mirrored ghost row at a wall),
+//   rt: the same rows for gathers, -1 where the row lies beyond a wall,
+//   cl: columns x-1, x, x+1 (periodic).
+struct NodeIdx {
+  int n, x, y;
+  int rs[3], rt[3], cl[3];
+  bool lo, hi;   // bottom / top wall row
+};
+
+__device__ __forceinline__ NodeIdx node_idx(int n, const Geom& g) {
+  NodeIdx k;
+  k.n = n;
+  k.y = (int)((unsigned)n / (unsigned)g.nx);
+  k.x = n - k.y * g.nx;
+  k.lo = g.walls && k.y == 0;
+  k.hi = g.walls && k.y == g.ny - 1;
+#pragma unroll
+  for (int d = -1; d <= 1; ++d) {
+    const int yy = k.y + d;
+    const bool out = yy < 0 || yy >= g.ny;
+    k.rs[d + 1] = nbr_row(yy, g) * g.nx;
+    k.rt[d + 1] = (out && g.walls) ? -1 : k.rs[d + 1];
+    k.cl[d + 1] = wrap_x(k.x + d, g.nx);
+  }
+  return k;
+}
+
+// 3x3 neighbourhood of a field as the forward stencils see it.
+template <typename T>
+__device__ __forceinline__ void load3x3(const T* psi, const NodeIdx& k, T v[3][3]) {
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) v[a][b] = psi[k.rs[a] + k.cl[b]];
+}
+
 // ------------------------------------------------ transposed stencils
 // grad psi(y) = 3 sum_i w_i c_i psi(nb(y, c_i)) and
 // lap psi(y) = 6 sum_i w_i (psi(nb(y, c_i)) - psi(y)), with nb the periodic
@@ -45,43 +86,37 @@ struct AF {
 // collects from every (y, i) with nb(y, c_i) = x. Off the walls that is
 // y = x - c_i; on a wall row the mirrored ghost adds y = x - (c_ix, 0) for
 // the directions pointing into the wall.
-template <typename T, int I>
-__device__ __forceinline__ void gt_term(const T* vx, const T* vy, const T* ws, int x, int y,
-                                        const Geom& g, T& gacc, T& lacc) {
+template <typename T, bool GR, bool LP, int I>
+__device__ __forceinline__ void gt_term(const T* vx, const T* vy, const T* ws, const NodeIdx& k,
+                                        T& gacc, T& lacc) {
   constexpr int cx = CXS(I), cy = CYS(I);
   const T w3 = T(3.0 * WGT(I)), w6 = T(6.0 * WGT(I));
-  int ys = y - cy;
-  bool ok = true;
-  if (ys < 0 || ys >= g.ny) {
-    if (g.walls) ok = false;
-    else ys = ys < 0 ? ys + g.ny : ys - g.ny;
+  const int r = k.rt[1 - cy];
+  if (r >= 0) {
+    const int m = r + k.cl[1 - cx];
+    if constexpr (GR) gacc += w3 * (T(cx) * vx[m] + T(cy) * vy[m]);
+    if constexpr (LP) lacc += w6 * ws[m];
   }
-  if (ok) {
-    const int64_t n = (int64_t)ys * g.nx + wrap_x(x - cx, g.nx);
-    if (vx) gacc += w3 * (T(cx) * vx[n] + T(cy) * vy[n]);
-    if (ws) lacc += w6 * ws[n];
-  }
-  if (g.walls && ((cy == -1 && y == 0) || (cy == 1 && y == g.ny - 1))) {
-    const int64_t n = (int64_t)y * g.nx + wrap_x(x - cx, g.nx);
-    if (vx) gacc += w3 * (T(cx) * vx[n] + T(cy) * vy[n]);
-    if (ws) lacc += w6 * ws[n];
+  if ((cy == -1 && k.lo) || (cy == 1 && k.hi)) {
+    const int m = k.rs[1] + k.cl[1 - cx];
+    if constexpr (GR) gacc += w3 * (T(cx) * vx[m] + T(cy) * vy[m]);
+    if constexpr (LP) lacc += w6 * ws[m];
   }
 }
 
-// Returns grad^T(vx, vy)(x) + lap^T(ws)(x); either input may be null.
-template <typename T>
-__device__ __forceinline__ T stencil_T(const T* vx, const T* vy, const T* ws, int x, int y,
-                                       const Geom& g) {
+// Returns grad^T(vx, vy)(x) (if GR) + lap^T(ws)(x) (if LP).
+template <typename T, bool GR, bool LP>
+__device__ __forceinline__ T stencil_T(const T* vx, const T* vy, const T* ws, const NodeIdx& k) {
   T gacc = T(0), lacc = T(0);
-  gt_term<T, 1>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 2>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 3>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 4>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 5>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 6>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 7>(vx, vy, ws, x, y, g, gacc, lacc);
-  gt_term<T, 8>(vx, vy, ws, x, y, g, gacc, lacc);
-  if (ws) lacc -= T(10.0 / 3.0) * ws[(int64_t)y * g.nx + x];
+  gt_term<T, GR, LP, 1>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 2>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 3>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 4>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 5>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 6>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 7>(vx, vy, ws, k, gacc, lacc);
+  gt_term<T, GR, LP, 8>(vx, vy, ws, k, gacc, lacc);
+  if constexpr (LP) lacc -= T(10.0 / 3.0) * ws[k.n];
   return gacc + lacc;
 }
 
@@ -127,22 +162,19 @@ __global__ __launch_bounds__(256) void k_adj_seed(const double* __restrict__ dph
 // population it becomes at t+1 is i at x + c_i, or opp(i) at x itself when
 // x + c_i lies beyond a wall.
 template <typename T, int I>
-__device__ __forceinline__ T post_hat(const T* hat, int koff, int x, int y, const Geom& g) {
+__device__ __forceinline__ T post_hat(const T* hat, int koff, const NodeIdx& k, int64_t Ns) {
   constexpr int cx = CXS(I), cy = CYS(I);
-  int yd = y + cy;
-  if (yd < 0 || yd >= g.ny) {
-    if (g.walls) return hat[(int64_t)(koff + OPP(I)) * g.Ns + (int64_t)y * g.nx + x];
-    yd = yd < 0 ? yd + g.ny : yd - g.ny;
-  }
-  return hat[(int64_t)(koff + I) * g.Ns + (int64_t)yd * g.nx + wrap_x(x + cx, g.nx)];
+  const int r = k.rt[1 + cy];
+  if (r < 0) return hat[(int64_t)(koff + OPP(I)) * Ns + k.n];
+  return hat[(int64_t)(koff + I) * Ns + (r + k.cl[1 + cx])];
 }
 
 template <typename T, int I = 0>
-__device__ __forceinline__ void post_hat9(const T* hat, int koff, int x, int y, const Geom& g,
+__device__ __forceinline__ void post_hat9(const T* hat, int koff, const NodeIdx& k, int64_t Ns,
                                           T v[9]) {
   if constexpr (I < 9) {
-    v[I] = post_hat<T, I>(hat, koff, x, y, g);
-    post_hat9<T, I + 1>(hat, koff, x, y, g, v);
+    v[I] = post_hat<T, I>(hat, koff, k, Ns);
+    post_hat9<T, I + 1>(hat, koff, k, Ns, v);
   }
 }
 
@@ -241,7 +273,7 @@ __device__ __forceinline__ void collide_node_T(T fh[9], T gh[9], const Macro<T>&
 // Forward node state (same arithmetic as the forward kernels).
 template <int P>
 __device__ __forceinline__ void fwd_node(const Pop<P>& in, const typename PrecT<P>::T* phi,
-                                         const typename PrecT<P>::T* mu, int x, int y,
+                                         const typename PrecT<P>::T* mu, const NodeIdx& k,
                                          const Coef<typename PrecT<P>::T>& c, const Geom& g,
                                          typename PrecT<P>::T f[9], Macro<typename PrecT<P>::T>& m,
                                          typename PrecT<P>::T& S, typename PrecT<P>::T& jx,
@@ -252,7 +284,7 @@ __device__ __forceinline__ void fwd_node(const Pop<P>& in, const typename PrecT<
   {                                      \
     int plane;                           \
     uint32_t idx;                        \
-    pull_src<I>(x, y, g, plane, idx);    \
+    pull_src<I>(k.x, k.y, g, plane, idx); \
     f[I] = in.ld(plane, idx);            \
   }
   QILBM_PULLF(0) QILBM_PULLF(1) QILBM_PULLF(2) QILBM_PULLF(3) QILBM_PULLF(4)
@@ -264,60 +296,38 @@ __device__ __forceinline__ void fwd_node(const Pop<P>& in, const typename PrecT<
   jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
   jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
   T v[3][3], gphx, gphy, lapphi;
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = phi[row + wrap_x(x + dx, g.nx)];
-  }
+  load3x3(phi, k, v);
   stencil(v, gphx, gphy, lapphi);
   const T ph = v[1][1];
-#pragma unroll
-  for (int dy = -1; dy <= 1; ++dy) {
-    const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
-#pragma unroll
-    for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = mu[row + wrap_x(x + dx, g.nx)];
-  }
+  load3x3(mu, k, v);
   stencil(v, gmux, gmuy, lapmu);
   macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
 }
 
 // AK1: collision transpose. Reads the cotangent of s_{t+1}; writes the
-// direct population cotangents and the node-quantity cotangents.
+// node-quantity cotangents (the direct population part is added by AK4).
 template <int P>
 __global__ __launch_bounds__(256) void k_adj_collide(Pop<P> in, const typename PrecT<P>::T* __restrict__ fphi,
                                                      const typename PrecT<P>::T* __restrict__ fmu,
                                                      const typename PrecT<P>::T* __restrict__ fp,
                                                      const typename PrecT<P>::T* __restrict__ hat,
-                                                     typename PrecT<P>::T* __restrict__ direct,
                                                      AF<typename PrecT<P>::T> af, double* acc_part,
                                                      Coef<typename PrecT<P>::T> c, Geom g) {
   using T = typename PrecT<P>::T;
   double alpha_acc = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
-       n += (int64_t)gridDim.x * 256) {
-    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
+    const NodeIdx k = node_idx(n, g);
     T f[9], S, jx, jy, gmux, gmuy, lapmu;
     Macro<T> m;
-    fwd_node<P>(in, fphi, fmu, x, y, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
+    fwd_node<P>(in, fphi, fmu, k, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
     T v[3][3], dpx, dpy, lapp;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = fp[row + wrap_x(x + dx, g.nx)];
-    }
+    load3x3(fp, k, v);
     stencil(v, dpx, dpy, lapp);
     T fh[9], gh[9];
-    post_hat9<T>(hat, 0, x, y, g, fh);
-    post_hat9<T>(hat, 9, x, y, g, gh);
+    post_hat9<T>(hat, 0, k, g.Ns, fh);
+    post_hat9<T>(hat, 9, k, g.Ns, gh);
     NodeBar<T> nb;
     collide_node_T(fh, gh, m, dpx, dpy, c, nb);
-#pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      direct[(int64_t)i * g.Ns + n] = fh[i];
-      direct[(int64_t)(9 + i) * g.Ns + n] = gh[i];
-    }
     af[A_DPX][n] = nb.dpx;
     af[A_DPY][n] = nb.dpy;
     af[A_P][n] = nb.p;
@@ -345,13 +355,12 @@ __global__ __launch_bounds__(256) void k_adj_macro(Pop<P> in, const typename Pre
                                                    Coef<typename PrecT<P>::T> c, Geom g) {
   using T = typename PrecT<P>::T;
   double lam_acc = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
-       n += (int64_t)gridDim.x * 256) {
-    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
+    const NodeIdx k = node_idx(n, g);
     T f[9], S, jx, jy, gmux, gmuy, lapmu;
     Macro<T> m;
-    fwd_node<P>(in, fphi, fmu, x, y, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
-    T b_p = af[A_P][n] + stencil_T<T>(af[A_DPX], af[A_DPY], nullptr, x, y, g);
+    fwd_node<P>(in, fphi, fmu, k, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
+    T b_p = af[A_P][n] + stencil_T<T, true, false>(af[A_DPX], af[A_DPY], nullptr, k);
     T b_rho = af[A_RHO][n], b_ux = af[A_UX][n], b_uy = af[A_UY][n];
     T b_Fx = af[A_FX][n], b_Fy = af[A_FY][n], b_drx = af[A_DRX][n], b_dry = af[A_DRY][n];
     T b_D = af[A_D][n], b_phi = af[A_PHI1][n];
@@ -395,17 +404,11 @@ template <typename T>
 __global__ __launch_bounds__(256) void k_adj_mu(const T* __restrict__ fphi, AF<T> af,
                                                 double* acc_part, Coef<T> c, Geom g) {
   double beta_acc = 0.0, kappa_acc = 0.0;
-  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
-       n += (int64_t)gridDim.x * 256) {
-    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-    const T b_mu = af[A_MU1][n] + stencil_T<T>(af[A_GMUX], af[A_GMUY], af[A_LMU], x, y, g);
+  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
+    const NodeIdx k = node_idx(n, g);
+    const T b_mu = af[A_MU1][n] + stencil_T<T, true, true>(af[A_GMUX], af[A_GMUY], af[A_LMU], k);
     T v[3][3], gx, gy, lapphi;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = fphi[row + wrap_x(x + dx, g.nx)];
-    }
+    load3x3(fphi, k, v);
     stencil(v, gx, gy, lapphi);
     const T ph = v[1][1];
     const T dbulk = c.beta4 * (T(3) * ph * ph - T(3) * ph + T(0.5));
@@ -419,20 +422,24 @@ __global__ __launch_bounds__(256) void k_adj_mu(const T* __restrict__ fphi, AF<T
 }
 
 // AK4: phi cotangent (grad^T of grad phi's, lap^T of lap phi's), then the
-// moments: gbar_i = direct + phibar, fbar_i = direct + Sbar + c_i.jbar.
+// moments: gbar_i = direct + phibar, fbar_i = direct + Sbar + c_i.jbar, with
+// the direct part (1 - 1/tau) times the post-collision cotangent gathered
+// from hat again.
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_final(const T* __restrict__ direct, AF<T> af,
-                                                   T* __restrict__ hat_out, Geom g) {
-  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
-       n += (int64_t)gridDim.x * 256) {
-    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-    const T b_phi = af[A_PHI3][n] + stencil_T<T>(af[A_GPHX], af[A_GPHY], af[A_LPHI], x, y, g);
+__global__ __launch_bounds__(256) void k_adj_final(const T* __restrict__ hat, AF<T> af,
+                                                   T* __restrict__ hat_out, Coef<T> c, Geom g) {
+  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
+    const NodeIdx k = node_idx(n, g);
+    const T b_phi = af[A_PHI3][n] + stencil_T<T, true, true>(af[A_GPHX], af[A_GPHY], af[A_LPHI], k);
     const T bS = af[A_S][n], bjx = af[A_JX][n], bjy = af[A_JY][n];
+    T fh[9], gh[9];
+    post_hat9<T>(hat, 0, k, g.Ns, fh);
+    post_hat9<T>(hat, 9, k, g.Ns, gh);
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
       hat_out[(int64_t)i * g.Ns + n] =
-          direct[(int64_t)i * g.Ns + n] + bS + T(CXS(i)) * bjx + T(CYS(i)) * bjy;
-      hat_out[(int64_t)(9 + i) * g.Ns + n] = direct[(int64_t)(9 + i) * g.Ns + n] + b_phi;
+          fh[i] * (T(1) - c.inv_tau_f) + bS + T(CXS(i)) * bjx + T(CYS(i)) * bjy;
+      hat_out[(int64_t)(9 + i) * g.Ns + n] = gh[i] * (T(1) - c.inv_tau_g) + b_phi;
     }
   }
 }
@@ -446,16 +453,10 @@ __global__ __launch_bounds__(256) void k_adj_init_local(const double* __restrict
                                                         double* __restrict__ phi_bar,
                                                         double* acc_part, Coef<double> c, Geom g) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
-       n += (int64_t)gridDim.x * 256) {
-    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
+  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
+    const NodeIdx k = node_idx(n, g);
     double v[3][3], gx, gy, lap;
-#pragma unroll
-    for (int dy = -1; dy <= 1; ++dy) {
-      const int64_t row = (int64_t)nbr_row(y + dy, g) * g.nx;
-#pragma unroll
-      for (int dx = -1; dx <= 1; ++dx) v[dy + 1][dx + 1] = phi0[row + wrap_x(x + dx, g.nx)];
-    }
+    load3x3(phi0, k, v);
     stencil(v, gx, gy, lap);
     const double ph = v[1][1];
     const double mu0 = mu_bulk(ph, c) - c.kappa * lap;
@@ -478,10 +479,9 @@ __global__ __launch_bounds__(256) void k_adj_init_local(const double* __restrict
 __global__ __launch_bounds__(256) void k_adj_init_final(const double* __restrict__ lphi_bar,
                                                         const double* __restrict__ phi_bar,
                                                         double* __restrict__ out, Geom g) {
-  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
-       n += (int64_t)gridDim.x * 256) {
-    const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-    out[n] = phi_bar[n] + stencil_T<double>(nullptr, nullptr, lphi_bar, x, y, g);
+  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
+    const NodeIdx k = node_idx(n, g);
+    out[n] = phi_bar[n] + stencil_T<double, false, true>(nullptr, nullptr, lphi_bar, k);
   }
 }
 
@@ -536,7 +536,7 @@ Coef<T> coef_of(const CtxView& v) {
 }
 
 struct AdjLayout {
-  size_t hat0, hat1, direct, fld, afld, part, acc, total;
+  size_t hat0, hat1, fld, afld, part, acc, total;
   int nred;
 };
 
@@ -550,8 +550,7 @@ AdjLayout adj_layout(const lbm_params* p) {
   const size_t pops = up(18 * (size_t)Ns * ts);
   L.hat0 = 0;
   L.hat1 = L.hat0 + pops;
-  L.direct = L.hat1 + pops;
-  L.fld = L.direct + pops;
+  L.fld = L.hat1 + pops;
   // the initial-state transpose uses two FP64 planes of the field area
   const size_t fb = up(3 * (size_t)Ns * (ts > 8 ? ts : 8));
   L.afld = L.fld + fb;
@@ -578,14 +577,13 @@ lbm_status adj_step_p(const CtxView& v, const void* fwd) {
   AF<T> af{(T*)a.afld, g.Ns};
   const T* hin = (const T*)a.hat[a.cur];
   T* hout = (T*)a.hat[a.cur ^ 1];
-  T* dir = (T*)a.direct;
   const dim3 grid(a.nred), blk(256);
   hipLaunchKernelGGL(k_adj_collide<P>, grid, blk, 0, v.stream, in, (const T*)phi, (const T*)mu,
-                     (const T*)p, hin, dir, af, a.part, k, g);
+                     (const T*)p, hin, af, a.part, k, g);
   hipLaunchKernelGGL(k_adj_macro<P>, grid, blk, 0, v.stream, in, (const T*)phi, (const T*)mu, af,
                      a.part, k, g);
   hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, (const T*)phi, af, a.part, k, g);
-  hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, (const T*)dir, af, hout, g);
+  hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);
   if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
   a.cur ^= 1;
   return LBM_OK;
@@ -642,7 +640,6 @@ lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* ws, size_t bytes, const double*
   a.hat[0] = a.ws + L.hat0;
   a.hat[1] = a.ws + L.hat1;
   a.cur = 0;
-  a.direct = a.ws + L.direct;
   a.fld = a.ws + L.fld;
   a.afld = a.ws + L.afld;
   a.part = (double*)(a.ws + L.part);

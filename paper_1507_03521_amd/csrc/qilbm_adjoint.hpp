@@ -35,7 +35,6 @@ struct AdjointState {
   size_t bytes = 0;
   char* hat[2] = {nullptr, nullptr};  // canonical adjoint populations, 18 planes
   int cur = 0;
-  char* direct = nullptr;             // direct (node-local) part, 18 planes
   char* fld = nullptr;                // forward phi, mu, p
   char* afld = nullptr;               // A_NFIELDS planes
   double* part = nullptr;             // 4 regions x nred x 4
