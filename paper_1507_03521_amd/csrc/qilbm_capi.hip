@@ -135,7 +135,7 @@ lbm_status step_p(lbm_ctx* c, int64_t n) {
   using T = typename PrecT<P>::T;
   const Coef<T> k = coef_t<T>(c);
   const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
-  const FusedShape sh = fused_shape(c->geom, c->seg_rows, c->resident);
+  const FusedShape sh = fused_shape<P>(c->geom, c->seg_rows, c->resident);
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e;
     if (unfused)
@@ -308,7 +308,11 @@ lbm_status lbm_set_launch(lbm_ctx* c, int32_t seg_rows) {
 
 lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
   if (!c || !out) return LBM_EINVAL;
-  const FusedShape sh = fused_shape(c->geom, c->seg_rows, c->resident);
+  const FusedShape sh =
+      c->prm.precision == LBM_FP64
+          ? fused_shape<P_F64>(c->geom, c->seg_rows, c->resident)
+          : (c->prm.precision == LBM_FP32 ? fused_shape<P_F32>(c->geom, c->seg_rows, c->resident)
+                                          : fused_shape<P_F16>(c->geom, c->seg_rows, c->resident));
   out[0] = sh.nstrips;
   out[1] = sh.nseg;
   out[2] = sh.seg_rows;

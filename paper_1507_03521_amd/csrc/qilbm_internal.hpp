@@ -33,6 +33,7 @@ struct FusedShape {
 
 // Launch shape for seg_rows rows per segment (0: automatic, from the number
 // of workgroups that can be resident at once, ``resident``).
+template <int P>
 FusedShape fused_shape(const Geom& g, int seg_rows, int resident);
 
 // Workgroups of the fused kernel that the current device holds at once.

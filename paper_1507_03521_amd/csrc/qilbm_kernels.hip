@@ -330,8 +330,8 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 }
 
 // ------------------------------------------------------ fused step kernel
-// One pass over the lattice per time step. A workgroup of FT lanes owns a
-// strip of at most FT - 2 FH columns plus FH halo columns on each side
+// One pass over the lattice per time step. A workgroup of NT lanes owns a
+// strip of at most NT - 2 FH columns plus FH halo columns on each side
 // (lane lc <-> column x0 - FH + lc) and a segment of rows, and sweeps the
 // rows in direction d (+1 or -1) keeping rings of recent rows of phi, mu,
 // p and the node state in LDS. In the iteration that brings in row r it
@@ -348,9 +348,7 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 // r+d, f of row r-d), so their latency overlaps the collision, the stores
 // and the barrier. Halo columns and the 3 rows of warm-up at each segment
 // end are recomputed by the neighbouring workgroups.
-constexpr int FT = 256;         // lanes per workgroup (4 wavefronts)
 constexpr int FH = 3;           // halo columns per side
-constexpr int FWMAX = FT - 2 * FH;
 constexpr int NM = 7;           // node values kept from C to D
 
 // Tiles handed out so that blocks that the hardware places on one XCD
@@ -633,17 +631,17 @@ __device__ __forceinline__ typename PrecT<P>::T as_val(typename BufT<P>::R w) {
   else return __builtin_bit_cast(float, w);
 }
 
-template <typename T>
+template <typename T, int NT>
 struct FusedLds {
-  T phi[8][FT];
-  int32_t phiq[8][FT];   // exact Q2.29 phi (fixed-point modes)
-  T mu[4][FT];
-  T p[4][FT];
-  T node[2][NM][FT];   // ux, uy, Fx, Fy, drx, dry, D
+  T phi[8][NT];
+  int32_t phiq[8][NT];   // exact Q2.29 phi (fixed-point modes)
+  T mu[4][NT];
+  T p[4][NT];
+  T node[2][NM][NT];   // ux, uy, Fx, Fy, drx, dry, D
 };
 
-template <typename T>
-__device__ __forceinline__ void lds3x3(const T (*ring)[FT], int mask, int v, int ny, int walls,
+template <typename T, int NT>
+__device__ __forceinline__ void lds3x3(const T (*ring)[NT], int mask, int v, int ny, int walls,
                                        int lc, T out[3][3]) {
   const int vm = (walls && v == 0) ? v : v - 1;
   const int vp = (walls && v == ny - 1) ? v : v + 1;
@@ -675,11 +673,11 @@ __device__ __forceinline__ bool need_p(const FusedCtx<P, BIG>& k, int q) {
   return k.act && k.lc >= 2 && k.lc < k.wi + 4 && q >= k.y0 - 1 && q < k.y1 + 1 && row_ok(q, k.g);
 }
 
-template <int P, bool BIG, int J>
+template <int P, bool BIG, int J, int NT>
 __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
                                            typename BufT<P>::R (&gb)[4][9],
                                            typename BufT<P>::R (&fb)[2][9],
-                                           FusedLds<typename PrecT<P>::T>& L) {
+                                           FusedLds<typename PrecT<P>::T, NT>& L) {
   using T = typename PrecT<P>::T;
   const Geom& g = k.g;
   const int lc = k.lc;
@@ -701,7 +699,7 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   const int b = r - k.d;
   if (k.act && lc >= 1 && lc < k.wi + 5 && b >= k.y0 - 2 && b < k.y1 + 2 && row_ok(b, g)) {
     T v[3][3], gx, gy, lap;
-    lds3x3<T>(L.phi, 7, b, g.ny, g.walls, lc, v);
+    lds3x3<T, NT>(L.phi, 7, b, g.ny, g.walls, lc, v);
     stencil(v, gx, gy, lap);
     L.mu[b & 3][lc] = mu_bulk(v[1][1], k.c) - k.c.kappa * lap;
   }
@@ -716,22 +714,22 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
     T S, jx, jy;
     moments9(fv, S, jx, jy);
     T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
-    lds3x3<T>(L.phi, 7, q, g.ny, g.walls, lc, v);
+    lds3x3<T, NT>(L.phi, 7, q, g.ny, g.walls, lc, v);
     stencil(v, gphx, gphy, lapphi);
     const T ph = v[1][1];
-    lds3x3<T>(L.mu, 3, q, g.ny, g.walls, lc, v);
+    lds3x3<T, NT>(L.mu, 3, q, g.ny, g.walls, lc, v);
     stencil(v, gmux, gmuy, lapmu);
     Macro<T> m;
     macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, k.c, m);
     L.p[q & 3][lc] = m.p;
     T* nd = &L.node[q & 1][0][0];
-    nd[0 * FT + lc] = m.ux;
-    nd[1 * FT + lc] = m.uy;
-    nd[2 * FT + lc] = m.Fx;
-    nd[3 * FT + lc] = m.Fy;
-    nd[4 * FT + lc] = m.drx;
-    nd[5 * FT + lc] = m.dry;
-    nd[6 * FT + lc] = m.D;
+    nd[0 * NT + lc] = m.ux;
+    nd[1 * NT + lc] = m.uy;
+    nd[2 * NT + lc] = m.Fx;
+    nd[3 * NT + lc] = m.Fy;
+    nd[4 * NT + lc] = m.drx;
+    nd[5 * NT + lc] = m.dry;
+    nd[6 * NT + lc] = m.D;
   }
   __syncthreads();
   // D: collide row r - 3d and store; meanwhile fetch the next iteration's rows
@@ -750,15 +748,15 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
     m.phi = L.phi[cr & 7][lc];
     m.mu = L.mu[cr & 3][lc];
     m.rho = k.c.rho_B + k.c.drho * m.phi;
-    m.ux = nd[0 * FT + lc];
-    m.uy = nd[1 * FT + lc];
-    m.Fx = nd[2 * FT + lc];
-    m.Fy = nd[3 * FT + lc];
-    m.drx = nd[4 * FT + lc];
-    m.dry = nd[5 * FT + lc];
-    m.D = nd[6 * FT + lc];
+    m.ux = nd[0 * NT + lc];
+    m.uy = nd[1 * NT + lc];
+    m.Fx = nd[2 * NT + lc];
+    m.Fy = nd[3 * NT + lc];
+    m.drx = nd[4 * NT + lc];
+    m.dry = nd[5 * NT + lc];
+    m.D = nd[6 * NT + lc];
     T v[3][3], dpx, dpy, lapp;
-    lds3x3<T>(L.p, 3, cr, g.ny, g.walls, lc, v);
+    lds3x3<T, NT>(L.p, 3, cr, g.ny, g.walls, lc, v);
     m.p = v[1][1];
     stencil(v, dpx, dpy, lapp);
     const int32_t phi_q = FixedG<P>::value ? L.phiq[cr & 7][lc] : 0;
@@ -775,12 +773,19 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
 template <int P> struct FusedWaves { static constexpr int value = QILBM_FUSED_WAVES32; };
 template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
 
+// Lanes per workgroup: 8 wavefronts (strips of up to 506 columns) for FP32,
+// 4 (up to 250 columns) for FP64 and FP16 storage -- measured best on MI355X
+// at 2048 x 8192 (FP32 +4 % with 512 lanes; FP16 storage -10 %, FP64 -3 %).
+template <int P> struct FusedThreads { static constexpr int value = 256; };
+template <> struct FusedThreads<P_F32> { static constexpr int value = 512; };
+
 template <int P, bool BIG>
-__global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
+__global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
                                                    Coef<typename PrecT<P>::T> c, Geom g, int width,
                                                    int nstrips, int seg_len) {
   using T = typename PrecT<P>::T;
-  __shared__ FusedLds<T> L;
+  constexpr int NT = FusedThreads<P>::value;
+  __shared__ FusedLds<T, NT> L;
   FusedCtx<P, BIG> k;
   k.in.init(in);
   k.out.init(out);
@@ -814,10 +819,10 @@ __global__ __launch_bounds__(FT, FusedWaves<P>::value) void k_step_fused(Pop<P> 
   // and is fetched by iteration 1)
   if (need_phi(k, r0)) pull_row<P, BIG, true>(k, phys_row(r0, g), gb[0]);
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, BIG, 0>(k, r0 + k.d * (it + 0), gb, fb, L);
-    fused_iter<P, BIG, 1>(k, r0 + k.d * (it + 1), gb, fb, L);
-    fused_iter<P, BIG, 2>(k, r0 + k.d * (it + 2), gb, fb, L);
-    fused_iter<P, BIG, 3>(k, r0 + k.d * (it + 3), gb, fb, L);
+    fused_iter<P, BIG, 0, NT>(k, r0 + k.d * (it + 0), gb, fb, L);
+    fused_iter<P, BIG, 1, NT>(k, r0 + k.d * (it + 1), gb, fb, L);
+    fused_iter<P, BIG, 2, NT>(k, r0 + k.d * (it + 2), gb, fb, L);
+    fused_iter<P, BIG, 3, NT>(k, r0 + k.d * (it + 3), gb, fb, L);
   }
 }
 
@@ -897,7 +902,9 @@ hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu,
   return hipGetLastError();
 }
 
+template <int P>
 FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
+  constexpr int NT = FusedThreads<P>::value, FWMAX = NT - 2 * FH;
   FusedShape sh;
   // strips of equal width (at most FWMAX interior columns) so that every
   // workgroup carries the same work
@@ -918,7 +925,7 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
   if (seg_rows > g.ny) seg_rows = g.ny;
   sh.seg_rows = seg_rows;
   sh.nseg = (g.ny + seg_rows - 1) / seg_rows;
-  sh.threads = FT;
+  sh.threads = NT;
   return sh;
 }
 
@@ -934,7 +941,8 @@ int fused_resident() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P, false>, FT, 0) != hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P, false>,
+                                                   FusedThreads<P>::value, 0) != hipSuccess)
     return 0;
   return cus * (per_cu > 0 ? per_cu : 1);
 }
@@ -944,10 +952,10 @@ hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename Pr
                              const Geom& g, const FusedShape& sh, hipStream_t s) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
   if (fused_big<P>(g))
-    hipLaunchKernelGGL((k_step_fused<P, true>), dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o,
+    hipLaunchKernelGGL((k_step_fused<P, true>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads), 0, s, i, o,
                        c, g, sh.width, sh.nstrips, sh.seg_rows);
   else
-    hipLaunchKernelGGL((k_step_fused<P, false>), dim3(sh.nstrips * sh.nseg), dim3(FT), 0, s, i, o,
+    hipLaunchKernelGGL((k_step_fused<P, false>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads), 0, s, i, o,
                        c, g, sh.width, sh.nstrips, sh.seg_rows);
   return hipGetLastError();
 }
@@ -987,6 +995,7 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
   template hipError_t launch_step_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,         \
                                            const Geom&, const FusedShape&, hipStream_t);         \
   template int fused_resident<P>();                                                              \
+  template FusedShape fused_shape<P>(const Geom&, int, int);                                     \
   template bool fused_big<P>(const Geom&);                                                       \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
                                      const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
