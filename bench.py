@@ -72,29 +72,29 @@ def run_precision(pb, phi0, precision, steps, warmup, seg_rows):
 
 
 def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
-    """Adjoint step time (and with its forward recompute and state save, as
-    checkpoint-recompute needs) over the forward step time."""
+    """Adjoint step time (from a step record) and, with the replay of the
+    forward step that writes the record (as checkpoint-recompute does), over
+    the forward step time."""
     import torch
     from paper_1507_03521_amd import Lattice
     lat = Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0")
     lat.step(5)
-    raw = lat.save_raw()
+    rec = lat.step_record()
     seed = torch.zeros((pb.ny, pb.nx), dtype=torch.float64, device="cuda:0")
     lat.adjoint_begin(seed)
-    lat.adjoint_step(raw)
+    lat.adjoint_step_record(rec)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
     start.record(lat.stream)
     for _ in range(nadj):
-        lat.adjoint_step(raw)
+        lat.adjoint_step_record(rec)
     stop.record(lat.stream)
     torch.cuda.synchronize()
     adj_ms = start.elapsed_time(stop) / nadj
     start.record(lat.stream)
     for _ in range(nadj):
-        lat.save_raw(raw)
-        lat.step(1)
+        lat.step_record(rec)
     stop.record(lat.stream)
     torch.cuda.synchronize()
     rec_ms = start.elapsed_time(stop) / nadj

@@ -147,6 +147,20 @@ lbm_status lbm_get_state(lbm_ctx* ctx, double* f_dev, double* g_dev);
  * values are rounded to the storage precision. Keeps the time counter. */
 lbm_status lbm_set_state(lbm_ctx* ctx, const double* f_dev, const double* g_dev);
 
+/* Size in bytes of one step record (see lbm_step_record). */
+size_t lbm_record_bytes(const lbm_ctx* ctx);
+
+/* Advances one step exactly like lbm_step(ctx, 1) and also writes the
+ * record of the state it started from: the forward quantities of Sec. III
+ * that the step computed on the way -- planes phi, mu, p, S = sum_i f_i,
+ * jx, jy = sum_i c_i f_i, in the compute type (binary64 for LBM_FP64,
+ * binary32 otherwise), each plane lbm_record_bytes / 6 bytes apart, node
+ * y * nx + x at element y * nx + x. record_dev: caller-owned device memory
+ * of lbm_record_bytes bytes, 256-byte aligned. The record is the input of
+ * lbm_adjoint_step_record and is a third of a raw state in size.
+ * Asynchronous. */
+lbm_status lbm_step_record(lbm_ctx* ctx, void* record_dev);
+
 /* Raw snapshot of the internal state buffer in the storage precision
  * (lbm_state_bytes bytes): exact save/restore for checkpointing.
  * lbm_load_raw also sets the time counter to t. Asynchronous. */
@@ -174,9 +188,11 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  * Reverse-mode derivative of a loss L(phi_K) of the final order parameter
  * with respect to sigma, M and the initial phi0 (not in the paper: a
  * hand-written transpose of every stage of the step above). The caller
- * drives checkpoint-and-recompute: it restores forward states with
- * lbm_load_raw / lbm_step and hands each forward state s_t to
- * lbm_adjoint_step in decreasing t. Parameter cotangents accumulate in FP64.
+ * drives checkpoint-and-recompute: it restores a checkpoint with
+ * lbm_load_raw, replays the segment with lbm_step_record keeping one
+ * record per step, and hands the records to lbm_adjoint_step_record in
+ * decreasing t (or hands raw states s_t to lbm_adjoint_step, which
+ * recomputes the record). Parameter cotangents accumulate in FP64.
  *
  * lbm_adjoint_workspace_bytes: device bytes for the adjoint (two adjoint
  *   population sets, forward/adjoint scratch fields, FP64 partials).
@@ -188,6 +204,9 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  *   of s_{t+1} by that of s_t = (d s_{t+1} / d s_t)^T applied to it, and
  *   adds (d s_{t+1} / d sigma)^T and (d s_{t+1} / d M)^T to the
  *   accumulators. Asynchronous.
+ * lbm_adjoint_step_record: the same step given the record of forward step
+ *   t written by lbm_step_record (256-byte aligned); no forward
+ *   recomputation. Asynchronous.
  * lbm_adjoint_init: pulls the cotangent of s_0 back through the initial
  *   state map phi0 -> (f = 0, g = H_i(phi0, mu0)) given the same phi0_dev
  *   (FP64 [ny][nx], device) that lbm_init received: writes dL/dphi0 (FP64
@@ -195,14 +214,15 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  *   Synchronises the stream.
  * The adjoint arithmetic runs in the compute type (FP64 for LBM_FP64,
  * FP32 otherwise); the parameter sums are FP64 and run-to-run reproducible.
- * lbm_adjoint_step and lbm_adjoint_init return LBM_ESTATE before
- * lbm_adjoint_begin.
+ * lbm_adjoint_step, lbm_adjoint_step_record and lbm_adjoint_init return
+ * LBM_ESTATE before lbm_adjoint_begin.
  */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* params);
 lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* adj_workspace_dev,
                              size_t adj_workspace_bytes,
                              const double* dL_dphi_dev);
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state_dev);
+lbm_status lbm_adjoint_step_record(lbm_ctx* ctx, const void* record_dev);
 lbm_status lbm_adjoint_init(lbm_ctx* ctx, const double* phi0_dev, double* dL_dphi0_dev,
                             double out[2]);
 

@@ -32,6 +32,8 @@ SIGNATURES = {
     "lbm_coefficients": (c_int32, [_P, _D]),
     "lbm_init": (c_int32, [POINTER(c_void_p), _P, c_void_p, c_size_t, c_void_p, c_void_p]),
     "lbm_step": (c_int32, [c_void_p, c_int64]),
+    "lbm_record_bytes": (c_size_t, [c_void_p]),
+    "lbm_step_record": (c_int32, [c_void_p, c_void_p]),
     "lbm_moments": (c_int32, [c_void_p] + [c_void_p] * 6),
     "lbm_mass": (c_int32, [c_void_p, _D]),
     "lbm_get_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
@@ -46,6 +48,7 @@ SIGNATURES = {
     "lbm_adjoint_workspace_bytes": (c_size_t, [_P]),
     "lbm_adjoint_begin": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
     "lbm_adjoint_step": (c_int32, [c_void_p, c_void_p]),
+    "lbm_adjoint_step_record": (c_int32, [c_void_p, c_void_p]),
     "lbm_adjoint_init": (c_int32, [c_void_p, c_void_p, c_void_p, _D]),
     "lbm_adjoint_set": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "lbm_adjoint_get": (c_int32, [c_void_p, c_void_p, c_void_p, _D]),

@@ -14,9 +14,11 @@ class PhaseFieldRun(torch.autograd.Function):
 
     Forward keeps a raw snapshot of the state every ``checkpoint`` steps
     (including t = 0). Backward walks the segments last to first: it restores
-    the segment's snapshot, recomputes and stores the segment's states, and
-    applies the adjoint step to each of them in reverse time order. Memory:
-    ceil(K / C) + C raw states of the storage precision.
+    the segment's snapshot, replays the segment with steps that also write
+    their records (the forward quantities phi, mu, p, S, j each adjoint step
+    needs), and applies the adjoint step to the records in reverse time
+    order. Memory: ceil(K / C) raw states plus C records (a record is a
+    third of a raw state).
     """
 
     @staticmethod
@@ -46,18 +48,16 @@ class PhaseFieldRun(torch.autograd.Function):
         (phi0,) = ctx.saved_tensors
         lat, snaps, C, K = ctx.lat, ctx.snaps, ctx.C, ctx.K
         lat.adjoint_begin(dphi.detach().to(torch.float64).contiguous())
-        seg_states = [torch.empty(lat.state_bytes, dtype=torch.uint8, device=phi0.device)
-                      for _ in range(min(C, max(K, 1)))]
+        records = [torch.empty(lat.record_bytes, dtype=torch.uint8, device=phi0.device)
+                   for _ in range(min(C, max(K, 1)))]
         for s in reversed(range(len(snaps))):
             t0 = s * C
             t1 = min(t0 + C, K)
             lat.load_raw(snaps[s], t0)
             for t in range(t0, t1):
-                lat.save_raw(seg_states[t - t0])
-                if t + 1 < t1:
-                    lat.step(1)
+                lat.step_record(records[t - t0])
             for t in reversed(range(t0, t1)):
-                lat.adjoint_step(seg_states[t - t0])
+                lat.adjoint_step_record(records[t - t0])
         dphi0, dsigma, dM = lat.adjoint_init(phi0)
         grads = []
         for val, meta in zip((dsigma, dM), ctx.param_meta):

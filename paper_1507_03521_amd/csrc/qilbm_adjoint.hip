@@ -13,8 +13,10 @@
 //   streaming (pull, bounce-back)             gather from the neighbour it fed
 //
 // The adjoint populations are kept in the canonical pre-collision layout
-// ([18][ny][nx], compute type); the forward state s_t is recomputed by the
-// caller and handed in raw (pull layout). The direct (diagonal) part of the
+// ([18][ny][nx], compute type). The forward step at t enters only through
+// its record: phi, mu, p, S = sum f, jx, jy of the state s_t (planes of the
+// compute type), written by the forward kernel itself (lbm_step_record) or
+// recomputed here from a raw state. The direct (diagonal) part of the
 // collision transpose, (1 - 1/tau) times the post-collision cotangent, is
 // recomputed where it is added rather than stored. Cotangents of beta, kappa, lambda,
 // alpha are summed in FP64 in a fixed block order (run-to-run reproducible)
@@ -270,58 +272,40 @@ __device__ __forceinline__ void collide_node_T(T fh[9], T gh[9], const Macro<T>&
   nb.uy = b_uy;
 }
 
-// Forward node state (same arithmetic as the forward kernels).
-template <int P>
-__device__ __forceinline__ void fwd_node(const Pop<P>& in, const typename PrecT<P>::T* phi,
-                                         const typename PrecT<P>::T* mu, const NodeIdx& k,
-                                         const Coef<typename PrecT<P>::T>& c, const Geom& g,
-                                         typename PrecT<P>::T f[9], Macro<typename PrecT<P>::T>& m,
-                                         typename PrecT<P>::T& S, typename PrecT<P>::T& jx,
-                                         typename PrecT<P>::T& jy, typename PrecT<P>::T& gmux,
-                                         typename PrecT<P>::T& gmuy, typename PrecT<P>::T& lapmu) {
-  using T = typename PrecT<P>::T;
-#define QILBM_PULLF(I)                   \
-  {                                      \
-    int plane;                           \
-    uint32_t idx;                        \
-    pull_src<I>(k.x, k.y, g, plane, idx); \
-    f[I] = in.ld(plane, idx);            \
-  }
-  QILBM_PULLF(0) QILBM_PULLF(1) QILBM_PULLF(2) QILBM_PULLF(3) QILBM_PULLF(4)
-  QILBM_PULLF(5) QILBM_PULLF(6) QILBM_PULLF(7) QILBM_PULLF(8)
-#undef QILBM_PULLF
-  S = f[0];
-#pragma unroll
-  for (int i = 1; i < 9; ++i) S += f[i];
-  jx = (f[1] - f[3]) + ((f[5] - f[6]) + (f[8] - f[7]));
-  jy = (f[2] - f[4]) + ((f[5] + f[6]) - (f[7] + f[8]));
+// Forward node state from the record of step t (same arithmetic as the
+// forward kernels). Record planes: 0 phi, 1 mu, 2 p, 3 S, 4 jx, 5 jy.
+enum RecPlane : int { R_PHI = 0, R_MU, R_P, R_S, R_JX, R_JY, R_NPLANES };
+
+template <typename T>
+__device__ __forceinline__ void fwd_node(const T* rec, const NodeIdx& k, const Coef<T>& c,
+                                         const Geom& g, Macro<T>& m, T& S, T& jx, T& jy,
+                                         T& gmux, T& gmuy, T& lapmu) {
+  S = rec[(int64_t)R_S * g.Ns + k.n];
+  jx = rec[(int64_t)R_JX * g.Ns + k.n];
+  jy = rec[(int64_t)R_JY * g.Ns + k.n];
   T v[3][3], gphx, gphy, lapphi;
-  load3x3(phi, k, v);
+  load3x3(rec + (int64_t)R_PHI * g.Ns, k, v);
   stencil(v, gphx, gphy, lapphi);
   const T ph = v[1][1];
-  load3x3(mu, k, v);
+  load3x3(rec + (int64_t)R_MU * g.Ns, k, v);
   stencil(v, gmux, gmuy, lapmu);
   macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
 }
 
 // AK1: collision transpose. Reads the cotangent of s_{t+1}; writes the
 // node-quantity cotangents (the direct population part is added by AK4).
-template <int P>
-__global__ __launch_bounds__(256) void k_adj_collide(Pop<P> in, const typename PrecT<P>::T* __restrict__ fphi,
-                                                     const typename PrecT<P>::T* __restrict__ fmu,
-                                                     const typename PrecT<P>::T* __restrict__ fp,
-                                                     const typename PrecT<P>::T* __restrict__ hat,
-                                                     AF<typename PrecT<P>::T> af, double* acc_part,
-                                                     Coef<typename PrecT<P>::T> c, Geom g) {
-  using T = typename PrecT<P>::T;
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_collide(const T* __restrict__ rec,
+                                                     const T* __restrict__ hat, AF<T> af,
+                                                     double* acc_part, Coef<T> c, Geom g) {
   double alpha_acc = 0.0;
   for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
     const NodeIdx k = node_idx(n, g);
-    T f[9], S, jx, jy, gmux, gmuy, lapmu;
+    T S, jx, jy, gmux, gmuy, lapmu;
     Macro<T> m;
-    fwd_node<P>(in, fphi, fmu, k, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
+    fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
     T v[3][3], dpx, dpy, lapp;
-    load3x3(fp, k, v);
+    load3x3(rec + (int64_t)R_P * g.Ns, k, v);
     stencil(v, dpx, dpy, lapp);
     T fh[9], gh[9];
     post_hat9<T>(hat, 0, k, g.Ns, fh);
@@ -348,18 +332,15 @@ __global__ __launch_bounds__(256) void k_adj_collide(Pop<P> in, const typename P
 
 // AK2: transposes of grad p (gathered), the pressure, velocity, force, D,
 // grad rho and rho definitions.
-template <int P>
-__global__ __launch_bounds__(256) void k_adj_macro(Pop<P> in, const typename PrecT<P>::T* __restrict__ fphi,
-                                                   const typename PrecT<P>::T* __restrict__ fmu,
-                                                   AF<typename PrecT<P>::T> af, double* acc_part,
-                                                   Coef<typename PrecT<P>::T> c, Geom g) {
-  using T = typename PrecT<P>::T;
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_macro(const T* __restrict__ rec, AF<T> af,
+                                                   double* acc_part, Coef<T> c, Geom g) {
   double lam_acc = 0.0;
   for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
     const NodeIdx k = node_idx(n, g);
-    T f[9], S, jx, jy, gmux, gmuy, lapmu;
+    T S, jx, jy, gmux, gmuy, lapmu;
     Macro<T> m;
-    fwd_node<P>(in, fphi, fmu, k, c, g, f, m, S, jx, jy, gmux, gmuy, lapmu);
+    fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
     T b_p = af[A_P][n] + stencil_T<T, true, false>(af[A_DPX], af[A_DPY], nullptr, k);
     T b_rho = af[A_RHO][n], b_ux = af[A_UX][n], b_uy = af[A_UY][n];
     T b_Fx = af[A_FX][n], b_Fy = af[A_FY][n], b_drx = af[A_DRX][n], b_dry = af[A_DRY][n];
@@ -551,8 +532,9 @@ AdjLayout adj_layout(const lbm_params* p) {
   L.hat0 = 0;
   L.hat1 = L.hat0 + pops;
   L.fld = L.hat1 + pops;
-  // the initial-state transpose uses two FP64 planes of the field area
-  const size_t fb = up(3 * (size_t)Ns * (ts > 8 ? ts : 8));
+  // the field area holds a record (6 planes of the compute type) recomputed
+  // from a raw state; the initial-state transpose uses two FP64 planes of it
+  const size_t fb = up((size_t)Ns * (6 * ts > 16 ? 6 * ts : 16));
   L.afld = L.fld + fb;
   L.part = L.afld + up((size_t)A_NFIELDS * Ns * ts);
   L.acc = L.part + up((size_t)L.nred * 4 * 8);
@@ -560,33 +542,41 @@ AdjLayout adj_layout(const lbm_params* p) {
   return L;
 }
 
+// One adjoint step from the record of forward step t.
+template <typename T>
+lbm_status adj_core(const CtxView& v, const T* rec) {
+  AdjointState& a = *v.adj;
+  const Geom& g = v.geom;
+  const Coef<T> k = coef_of<T>(v);
+  AF<T> af{(T*)a.afld, g.Ns};
+  const T* hin = (const T*)a.hat[a.cur];
+  T* hout = (T*)a.hat[a.cur ^ 1];
+  const dim3 grid(a.nred), blk(256);
+  hipLaunchKernelGGL(k_adj_collide<T>, grid, blk, 0, v.stream, rec, hin, af, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_macro<T>, grid, blk, 0, v.stream, rec, af, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, rec + (int64_t)R_PHI * g.Ns, af,
+                     a.part, k, g);
+  hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  a.cur ^= 1;
+  return LBM_OK;
+}
+
+// One adjoint step from a raw forward state: its record is recomputed into
+// the field area with the unfused forward kernels.
 template <int P>
 lbm_status adj_step_p(const CtxView& v, const void* fwd) {
   using T = typename PrecT<P>::T;
   AdjointState& a = *v.adj;
   const Geom& g = v.geom;
   const Coef<T> k = coef_of<T>(v);
-  T* phi = (T*)a.fld;
-  T* mu = phi + g.Ns;
-  T* p = mu + g.Ns;
-  hipError_t e = launch_fields<P>(fwd, phi, mu, k, g, v.stream);
+  T* rec = (T*)a.fld;
+  hipError_t e = launch_fields<P>(fwd, rec + R_PHI * g.Ns, rec + R_MU * g.Ns, k, g, v.stream);
   if (e != hipSuccess) return LBM_EDEVICE;
-  e = launch_macro<P>(fwd, phi, mu, p, MomentOut{}, k, g, v.stream);
+  e = launch_macro<P>(fwd, rec + R_PHI * g.Ns, rec + R_MU * g.Ns, rec + R_P * g.Ns,
+                      rec + R_S * g.Ns, MomentOut{}, k, g, v.stream);
   if (e != hipSuccess) return LBM_EDEVICE;
-  Pop<P> in{(char*)fwd, g.Ns};
-  AF<T> af{(T*)a.afld, g.Ns};
-  const T* hin = (const T*)a.hat[a.cur];
-  T* hout = (T*)a.hat[a.cur ^ 1];
-  const dim3 grid(a.nred), blk(256);
-  hipLaunchKernelGGL(k_adj_collide<P>, grid, blk, 0, v.stream, in, (const T*)phi, (const T*)mu,
-                     (const T*)p, hin, af, a.part, k, g);
-  hipLaunchKernelGGL(k_adj_macro<P>, grid, blk, 0, v.stream, in, (const T*)phi, (const T*)mu, af,
-                     a.part, k, g);
-  hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, (const T*)phi, af, a.part, k, g);
-  hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);
-  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
-  a.cur ^= 1;
-  return LBM_OK;
+  return adj_core<T>(v, rec);
 }
 
 template <typename T>
@@ -667,6 +657,15 @@ lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state) {
     case LBM_FP32: return adj_step_p<P_F32>(v, fwd_state);
     default: return adj_step_p<P_F16>(v, fwd_state);
   }
+}
+
+lbm_status lbm_adjoint_step_record(lbm_ctx* ctx, const void* record_dev) {
+  if (!ctx || !record_dev) return LBM_EINVAL;
+  if ((uintptr_t)record_dev % ALIGN != 0) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  if (!v.adj->active) return LBM_ESTATE;
+  if (v.prm->precision == LBM_FP64) return adj_core<double>(v, (const double*)record_dev);
+  return adj_core<float>(v, (const float*)record_dev);
 }
 
 lbm_status lbm_adjoint_init(lbm_ctx* ctx, const double* phi0, double* dphi0, double out[2]) {

@@ -130,19 +130,26 @@ char* phi_f(lbm_ctx* c) { return c->fields; }
 char* mu_f(lbm_ctx* c) { return c->fields + c->geom.Ns * 8; }
 char* p_f(lbm_ctx* c) { return c->fields + 2 * c->geom.Ns * 8; }
 
+// n steps; with rec (n = 1) the step also writes its record (planes phi, mu,
+// p, S, jx, jy of the compute type at stride Ns).
 template <int P>
-lbm_status step_p(lbm_ctx* c, int64_t n) {
+lbm_status step_p(lbm_ctx* c, int64_t n, void* rec) {
   using T = typename PrecT<P>::T;
   const Coef<T> k = coef_t<T>(c);
   const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
   const FusedShape sh = fused_shape<P>(c->geom, c->seg_rows, c->resident);
+  const int64_t pl = c->geom.Ns;
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e;
-    if (unfused)
-      e = launch_step_unfused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], phi_f(c), mu_f(c), p_f(c), k,
-                                 c->geom, c->stream);
+    if (unfused && rec)
+      e = launch_step_unfused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], (T*)rec, (T*)rec + pl,
+                                 (T*)rec + 2 * pl, (T*)rec + 3 * pl, k, c->geom, c->stream);
+    else if (unfused)
+      e = launch_step_unfused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], phi_f(c), mu_f(c), p_f(c),
+                                 nullptr, k, c->geom, c->stream);
     else
-      e = launch_step_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh, c->stream);
+      e = launch_step_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh, rec,
+                               c->stream);
     if (e != hipSuccess) return LBM_EDEVICE;
     c->cur ^= 1;
     c->t += 1;
@@ -156,7 +163,8 @@ lbm_status moments_p(lbm_ctx* c, const MomentOut& mo) {
   const Coef<T> k = coef_t<T>(c);
   hipError_t e = launch_fields<P>(c->pop[c->cur], phi_f(c), mu_f(c), k, c->geom, c->stream);
   if (e != hipSuccess) return LBM_EDEVICE;
-  return st(launch_macro<P>(c->pop[c->cur], phi_f(c), mu_f(c), nullptr, mo, k, c->geom, c->stream));
+  return st(launch_macro<P>(c->pop[c->cur], phi_f(c), mu_f(c), nullptr, nullptr, mo, k, c->geom,
+                            c->stream));
 }
 
 template <int P>
@@ -238,7 +246,18 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
-  return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps);
+  return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps, nullptr);
+}
+
+size_t lbm_record_bytes(const lbm_ctx* c) {
+  if (!c) return 0;
+  return up(6 * (size_t)c->geom.Ns * (c->prm.precision == LBM_FP64 ? 8 : 4));
+}
+
+lbm_status lbm_step_record(lbm_ctx* c, void* record_dev) {
+  if (!c || !record_dev) return LBM_EINVAL;
+  if ((uintptr_t)record_dev % ALIGN != 0) return LBM_EINVAL;
+  return QILBM_DISPATCH(c->prm.precision, step_p, c, 1, record_dev);
 }
 
 lbm_status lbm_moments(lbm_ctx* c, double* phi, double* rho, double* ux, double* uy, double* p,

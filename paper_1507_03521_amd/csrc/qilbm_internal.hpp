@@ -61,17 +61,22 @@ hipError_t launch_to_canonical(const void* pop, double* f, double* gg, const Geo
 template <int P>
 hipError_t launch_fields(const void* pop, void* phi, void* mu,
                          const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);
+// Pressure into p and, when sj is not null, S = sum f, jx, jy into the three
+// planes sj, sj + Ns, sj + 2 Ns (compute type); FP64 moments into mo.
 template <int P>
-hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* p,
+hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* p, void* sj,
                         const MomentOut& mo, const Coef<typename PrecT<P>::T>& c, const Geom& g,
                         hipStream_t s);
 template <int P>
 hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu, void* p,
-                               const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                               void* sj, const Coef<typename PrecT<P>::T>& c, const Geom& g,
                                hipStream_t s);
+// One fused step; when rec is not null it also writes the forward quantities
+// of the state it reads (the record: planes phi, mu, p, S, jx, jy of the
+// compute type at stride Ns).
 template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
-                             const Geom& g, const FusedShape& sh, hipStream_t s);
+                             const Geom& g, const FusedShape& sh, void* rec, hipStream_t s);
 template <int P>
 hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
                        const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);

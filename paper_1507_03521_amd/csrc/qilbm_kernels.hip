@@ -159,10 +159,11 @@ __device__ __forceinline__ void node_macro(const Pop<P>& in, const typename Prec
                                            const typename PrecT<P>::T* mu, int x, int y,
                                            const Coef<typename PrecT<P>::T>& c, const Geom& g,
                                            typename PrecT<P>::T f[9],
-                                           Macro<typename PrecT<P>::T>& m) {
+                                           Macro<typename PrecT<P>::T>& m,
+                                           typename PrecT<P>::T& S, typename PrecT<P>::T& jx,
+                                           typename PrecT<P>::T& jy) {
   using T = typename PrecT<P>::T;
   pull9<P, 0>(in, x, y, g, f);
-  T S, jx, jy;
   moments9(f, S, jx, jy);
   T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
   gather3x3(phi, x, y, g, v);
@@ -173,20 +174,27 @@ __device__ __forceinline__ void node_macro(const Pop<P>& in, const typename Prec
   macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
 }
 
-// Pressure field (and, optionally, the FP64 moment outputs).
+// Pressure field (and, optionally, S = sum f and j = sum c f into three
+// planes at sj, and the FP64 moment outputs).
 template <int P>
 __global__ __launch_bounds__(256) void k_macro(Pop<P> in, const typename PrecT<P>::T* __restrict__ phi,
                                                const typename PrecT<P>::T* __restrict__ mu,
                                                typename PrecT<P>::T* __restrict__ p,
+                                               typename PrecT<P>::T* __restrict__ sj,
                                                MomentOut mo, Coef<typename PrecT<P>::T> c, Geom g) {
   using T = typename PrecT<P>::T;
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= g.N) return;
   const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-  T f[9];
+  T f[9], S, jx, jy;
   Macro<T> m;
-  node_macro<P>(in, phi, mu, x, y, c, g, f, m);
+  node_macro<P>(in, phi, mu, x, y, c, g, f, m, S, jx, jy);
   if (p) p[n] = m.p;
+  if (sj) {
+    sj[n] = S;
+    sj[g.Ns + n] = jx;
+    sj[2 * g.Ns + n] = jy;
+  }
   if (mo.phi) mo.phi[n] = double(m.phi);
   if (mo.rho) mo.rho[n] = double(m.rho);
   if (mo.ux) mo.ux[n] = double(m.ux);
@@ -254,9 +262,9 @@ __global__ __launch_bounds__(256) void k_collide(Pop<P> in, Pop<P> out,
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= g.N) return;
   const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-  T f[9], gg[9];
+  T f[9], gg[9], S, jx, jy;
   Macro<T> m;
-  node_macro<P>(in, phi, mu, x, y, c, g, f, m);
+  node_macro<P>(in, phi, mu, x, y, c, g, f, m, S, jx, jy);
   pull9<P, 9>(in, x, y, g, gg);
   T v[3][3], dpx, dpy, lapp;
   gather3x3(p, x, y, g, v);
@@ -304,9 +312,9 @@ __global__ __launch_bounds__(256) void k_mass_partial(Pop<P> in,
   for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
        n += (int64_t)gridDim.x * 256) {
     const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-    T f[9];
+    T f[9], S, jx, jy;
     Macro<T> m;
-    node_macro<P>(in, phi, mu, x, y, c, g, f, m);
+    node_macro<P>(in, phi, mu, x, y, c, g, f, m, S, jx, jy);
     // phi and rho from the exact stored values (so that the totals show the
     // scheme's conservation rather than the rounding of the compute type)
     const double ph = pull_phi_exact<P>(in, x, y, g);
@@ -552,6 +560,15 @@ struct FusedCtx {
   int d;               // sweep direction: +1 upwards, -1 downwards
   uint32_t col[3];     // element columns x - 1, x, x + 1 (wrapped)
   bool act;
+  T* rec;              // record planes (phi, mu, p, S, jx, jy), or null
+  // this lane stores (and records) row v: an interior column of the strip
+  // and a row of the segment
+  __device__ __forceinline__ bool owns(int v) const {
+    return act && lc >= FH && lc < wi + FH && v >= y0 && v < y1;
+  }
+  __device__ __forceinline__ void record(int plane, int v, T val) const {
+    rec[(int64_t)plane * g.Ns + (int64_t)v * g.nx + x] = val;
+  }
 };
 
 // Pull row y (physical) of population set G.
@@ -673,7 +690,7 @@ __device__ __forceinline__ bool need_p(const FusedCtx<P, BIG>& k, int q) {
   return k.act && k.lc >= 2 && k.lc < k.wi + 4 && q >= k.y0 - 1 && q < k.y1 + 1 && row_ok(q, k.g);
 }
 
-template <int P, bool BIG, int J, int NT>
+template <int P, bool BIG, bool REC, int J, int NT>
 __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
                                            typename BufT<P>::R (&gb)[4][9],
                                            typename BufT<P>::R (&fb)[2][9],
@@ -684,15 +701,19 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   // A: phi at row r (its g was loaded by the previous iteration)
   if (need_phi(k, r)) {
     const int32_t q = decode_g<P>(gb[J]);
+    T ph;
     if constexpr (FixedG<P>::value) {
-      L.phi[r & 7][lc] = T(q) * T(GQI);
+      ph = T(q) * T(GQI);
       L.phiq[r & 7][lc] = q;
     } else {
       T v[9];
 #pragma unroll
       for (int i = 0; i < 9; ++i) v[i] = as_val<P>(gb[J][i]);
-      L.phi[r & 7][lc] = sum9(v);
+      ph = sum9(v);
     }
+    L.phi[r & 7][lc] = ph;
+    if constexpr (REC)
+      if (k.owns(r)) k.record(0, r, ph);
   }
   __syncthreads();
   // B: mu at row r - d
@@ -701,7 +722,10 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
     T v[3][3], gx, gy, lap;
     lds3x3<T, NT>(L.phi, 7, b, g.ny, g.walls, lc, v);
     stencil(v, gx, gy, lap);
-    L.mu[b & 3][lc] = mu_bulk(v[1][1], k.c) - k.c.kappa * lap;
+    const T mu = mu_bulk(v[1][1], k.c) - k.c.kappa * lap;
+    L.mu[b & 3][lc] = mu;
+    if constexpr (REC)
+      if (k.owns(b)) k.record(1, b, mu);
   }
   __syncthreads();
   // C: force, velocity, pressure at row r - 2d
@@ -722,6 +746,14 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
     Macro<T> m;
     macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, k.c, m);
     L.p[q & 3][lc] = m.p;
+    if constexpr (REC) {
+      if (k.owns(q)) {
+        k.record(2, q, m.p);
+        k.record(3, q, S);
+        k.record(4, q, jx);
+        k.record(5, q, jy);
+      }
+    }
     T* nd = &L.node[q & 1][0][0];
     nd[0 * NT + lc] = m.ux;
     nd[1 * NT + lc] = m.uy;
@@ -742,7 +774,7 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   }
   if (need_phi(k, r + k.d)) pull_row<P, BIG, true>(k, phys_row(r + k.d, g), gb[(J + 1) & 3]);
   if (need_p(k, r - k.d)) pull_row<P, BIG, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
-  if (k.act && lc >= FH && lc < k.wi + FH && cr >= k.y0 && cr < k.y1) {
+  if (k.owns(cr)) {
     Macro<T> m;
     const T* nd = &L.node[cr & 1][0][0];
     m.phi = L.phi[cr & 7][lc];
@@ -779,10 +811,11 @@ template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
 template <int P> struct FusedThreads { static constexpr int value = 256; };
 template <> struct FusedThreads<P_F32> { static constexpr int value = 512; };
 
-template <int P, bool BIG>
+template <int P, bool BIG, bool REC>
 __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
                                                    Coef<typename PrecT<P>::T> c, Geom g, int width,
-                                                   int nstrips, int seg_len) {
+                                                   int nstrips, int seg_len,
+                                                   typename PrecT<P>::T* rec) {
   using T = typename PrecT<P>::T;
   constexpr int NT = FusedThreads<P>::value;
   __shared__ FusedLds<T, NT> L;
@@ -791,6 +824,7 @@ __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void 
   k.out.init(out);
   k.c = c;
   k.g = g;
+  k.rec = rec;
   // tiles in row-band order: the strips of one segment are consecutive, so
   // they run together on one XCD and share their halo columns in its L2
   const int tile = xcd_tile(blockIdx.x, gridDim.x);
@@ -819,10 +853,10 @@ __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void 
   // and is fetched by iteration 1)
   if (need_phi(k, r0)) pull_row<P, BIG, true>(k, phys_row(r0, g), gb[0]);
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, BIG, 0, NT>(k, r0 + k.d * (it + 0), gb, fb, L);
-    fused_iter<P, BIG, 1, NT>(k, r0 + k.d * (it + 1), gb, fb, L);
-    fused_iter<P, BIG, 2, NT>(k, r0 + k.d * (it + 2), gb, fb, L);
-    fused_iter<P, BIG, 3, NT>(k, r0 + k.d * (it + 3), gb, fb, L);
+    fused_iter<P, BIG, REC, 0, NT>(k, r0 + k.d * (it + 0), gb, fb, L);
+    fused_iter<P, BIG, REC, 1, NT>(k, r0 + k.d * (it + 1), gb, fb, L);
+    fused_iter<P, BIG, REC, 2, NT>(k, r0 + k.d * (it + 2), gb, fb, L);
+    fused_iter<P, BIG, REC, 3, NT>(k, r0 + k.d * (it + 3), gb, fb, L);
   }
 }
 
@@ -877,24 +911,24 @@ hipError_t launch_fields(const void* pop, void* phi, void* mu,
 }
 
 template <int P>
-hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* p,
+hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* p, void* sj,
                         const MomentOut& mo, const Coef<typename PrecT<P>::T>& c, const Geom& g,
                         hipStream_t s) {
   using T = typename PrecT<P>::T;
   Pop<P> i{(char*)pop, g.Ns};
   hipLaunchKernelGGL(k_macro<P>, dim3(nblk(g.N, 256)), dim3(256), 0, s, i, (const T*)phi,
-                     (const T*)mu, (T*)p, mo, c, g);
+                     (const T*)mu, (T*)p, (T*)sj, mo, c, g);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu, void* p,
-                               const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                               void* sj, const Coef<typename PrecT<P>::T>& c, const Geom& g,
                                hipStream_t s) {
   using T = typename PrecT<P>::T;
   hipError_t e = launch_fields<P>(pin, phi, mu, c, g, s);
   if (e != hipSuccess) return e;
-  e = launch_macro<P>(pin, phi, mu, p, MomentOut{}, c, g, s);
+  e = launch_macro<P>(pin, phi, mu, p, sj, MomentOut{}, c, g, s);
   if (e != hipSuccess) return e;
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
   hipLaunchKernelGGL(k_collide<P>, dim3(nblk(g.N, 256)), dim3(256), 0, s, i, o, (const T*)phi,
@@ -941,22 +975,33 @@ int fused_resident() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P, false>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step_fused<P, false, false>,
                                                    FusedThreads<P>::value, 0) != hipSuccess)
     return 0;
   return cus * (per_cu > 0 ? per_cu : 1);
 }
 
+template <int P, bool BIG, bool REC>
+static void launch_fused_variant(const Pop<P>& i, const Pop<P>& o,
+                                 const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                                 const FusedShape& sh, void* rec, hipStream_t s) {
+  using T = typename PrecT<P>::T;
+  hipLaunchKernelGGL((k_step_fused<P, BIG, REC>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads), 0,
+                     s, i, o, c, g, sh.width, sh.nstrips, sh.seg_rows, (T*)rec);
+}
+
 template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
-                             const Geom& g, const FusedShape& sh, hipStream_t s) {
+                             const Geom& g, const FusedShape& sh, void* rec, hipStream_t s) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
-  if (fused_big<P>(g))
-    hipLaunchKernelGGL((k_step_fused<P, true>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads), 0, s, i, o,
-                       c, g, sh.width, sh.nstrips, sh.seg_rows);
-  else
-    hipLaunchKernelGGL((k_step_fused<P, false>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads), 0, s, i, o,
-                       c, g, sh.width, sh.nstrips, sh.seg_rows);
+  const bool big = fused_big<P>(g);
+  if (rec) {
+    if (big) launch_fused_variant<P, true, true>(i, o, c, g, sh, rec, s);
+    else launch_fused_variant<P, false, true>(i, o, c, g, sh, rec, s);
+  } else {
+    if (big) launch_fused_variant<P, true, false>(i, o, c, g, sh, rec, s);
+    else launch_fused_variant<P, false, false>(i, o, c, g, sh, rec, s);
+  }
   return hipGetLastError();
 }
 
@@ -987,13 +1032,13 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
                                              hipStream_t);                                       \
   template hipError_t launch_fields<P>(const void*, void*, void*,                                \
                                        const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);      \
-  template hipError_t launch_macro<P>(const void*, const void*, const void*, void*,              \
+  template hipError_t launch_macro<P>(const void*, const void*, const void*, void*, void*,     \
                                       const MomentOut&, const Coef<PrecT<P>::T>&, const Geom&,   \
                                       hipStream_t);                                              \
-  template hipError_t launch_step_unfused<P>(const void*, void*, void*, void*, void*,            \
+  template hipError_t launch_step_unfused<P>(const void*, void*, void*, void*, void*, void*,     \
                                              const Coef<PrecT<P>::T>&, const Geom&, hipStream_t); \
   template hipError_t launch_step_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,         \
-                                           const Geom&, const FusedShape&, hipStream_t);         \
+                                           const Geom&, const FusedShape&, void*, hipStream_t);  \
   template int fused_resident<P>();                                                              \
   template FusedShape fused_shape<P>(const Geom&, int, int);                                     \
   template bool fused_big<P>(const Geom&);                                                       \

@@ -61,6 +61,20 @@ class Lattice:
         _lib.check(self.lib.lbm_step(self.ctx, int(n)), "lbm_step")
 
     @property
+    def record_bytes(self) -> int:
+        return int(self.lib.lbm_record_bytes(self.ctx))
+
+    def step_record(self, out: torch.Tensor | None = None) -> torch.Tensor:
+        """One step that also writes the record of the state it started
+        from (phi, mu, p, S, jx, jy planes), the input of
+        :meth:`adjoint_step_record`."""
+        if out is None:
+            out = torch.empty(self.record_bytes, dtype=torch.uint8, device=self.device)
+        assert out.numel() >= self.record_bytes and out.is_contiguous()
+        _lib.check(self.lib.lbm_step_record(self.ctx, _ptr(out)), "lbm_step_record")
+        return out
+
+    @property
     def time(self) -> int:
         return int(self.lib.lbm_time(self.ctx))
 
@@ -131,6 +145,10 @@ class Lattice:
 
     def adjoint_step(self, fwd_raw: torch.Tensor) -> None:
         _lib.check(self.lib.lbm_adjoint_step(self.ctx, _ptr(fwd_raw)), "lbm_adjoint_step")
+
+    def adjoint_step_record(self, record: torch.Tensor) -> None:
+        _lib.check(self.lib.lbm_adjoint_step_record(self.ctx, _ptr(record)),
+                   "lbm_adjoint_step_record")
 
     def adjoint_init(self, phi0: torch.Tensor | None = None):
         phi0 = self.phi0 if phi0 is None else \

@@ -193,3 +193,63 @@ def test_two_droplets_512_full_size_gradients_vs_finite_differences():
         print(f"{name}: adjoint FP64 {a:.10e} FP32 {a32:.6e} (rel {abs(a32 - a) / abs(a):.1e}), "
               f"central difference {f:.10e} (rel {abs(a - f) / abs(f):.1e})", flush=True)
         assert a == pytest.approx(f, rel=1e-6)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("flags", [0, 2], ids=["fused", "unfused"])
+def test_step_record_matches_step_and_oracle(precision, flags):
+    """lbm_step_record advances the state exactly as lbm_step (raw state
+    bitwise equal) and its record holds the forward quantities of the state
+    it started from: phi, mu, p, S, jx, jy equal to the oracle's (FP64:
+    1e-12 of each field's largest magnitude; FP32 arithmetic: 1e-5)."""
+    from paper_1507_03521_amd import Lattice
+    nx, ny = 300, 41
+    pb = wl.droplet64().with_(nx=nx, ny=ny, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5)
+    f, g = wl.random_state(nx, ny, seed=8)
+    lats = []
+    for _ in range(2):
+        lat = Lattice(pb.as_dict(), np.full((ny, nx), 0.5), precision=precision, flags=flags,
+                      device="cuda:0")
+        lat.set_state(f, g)
+        lats.append(lat)
+    fs, gs = (t.cpu() for t in lats[0].get_state())   # stored (rounded) start state
+    rec = lats[0].step_record()
+    lats[1].step(1)
+    assert torch.equal(lats[0].save_raw(), lats[1].save_raw())
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    Ns = rec.numel() // (6 * (8 if precision == "fp64" else 4))
+    planes = rec.view(dt)[:6 * Ns].view(6, Ns)[:, :nx * ny].double().cpu().view(6, ny, nx)
+    m = O.macroscopic(fs, gs, O.coefficients_of(pb))
+    tol = 1e-12 if precision == "fp64" else 1e-5
+    for k, name in enumerate(("phi", "mu", "p", "S", "jx", "jy")):
+        assert _rel(planes[k], m[name]) <= tol, name
+
+
+def test_adjoint_step_from_record_matches_raw_state_path():
+    """One adjoint step from a record (lbm_step_record) equals the step from
+    the raw state (lbm_adjoint_step, which recomputes the record with the
+    unfused kernels): FP64 cotangents within 1e-13, sigma/M within 1e-12."""
+    from paper_1507_03521_amd import Lattice
+    nx, ny = 300, 41
+    pb = wl.droplet64().with_(nx=nx, ny=ny, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5)
+    f, g = wl.random_state(nx, ny, seed=9)
+    rng = np.random.default_rng(3)
+    fbar = rng.standard_normal((9, ny, nx))
+    gbar = rng.standard_normal((9, ny, nx))
+    zero = torch.zeros((ny, nx), dtype=torch.float64, device="cuda:0")
+    out = []
+    for use_record in (False, True):
+        lat = _lattice(pb, np.full((ny, nx), 0.5))
+        lat.set_state(f, g)
+        raw = lat.save_raw().clone()
+        rec = lat.step_record()
+        lat.adjoint_begin(zero)
+        lat.adjoint_set(fbar, gbar)
+        if use_record:
+            lat.adjoint_step_record(rec)
+        else:
+            lat.adjoint_step(raw)
+        out.append(lat.adjoint_get())
+    (f0, g0, s0, m0), (f1, g1, s1, m1) = out
+    assert _rel(f1, f0) <= 1e-13 and _rel(g1, g0) <= 1e-13
+    assert s1 == pytest.approx(s0, rel=1e-12) and m1 == pytest.approx(m0, rel=1e-12)
