@@ -292,90 +292,202 @@ __device__ __forceinline__ void fwd_node(const T* rec, const NodeIdx& k, const C
   macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
 }
 
-// AK1: collision transpose. Reads the cotangent of s_{t+1}; writes the
-// node-quantity cotangents (the direct population part is added by AK4).
+// AK1+2: collision transpose, then the transposes of grad p (gathered), the
+// pressure, velocity, force, D, grad rho and rho definitions, fused. A block
+// owns tiles of CM_TX x CM_TY nodes; the collision transpose runs on the
+// tile and a one-node ring around it (the ring only for its grad p
+// cotangent, which the gather of the tile's nodes needs), keeping that
+// cotangent in LDS and each interior node's other cotangents in registers
+// of the thread that owns the node in both phases.
+constexpr int CM_TX = 64, CM_TY = 8;
+constexpr int CM_HX = CM_TX + 2, CM_HY = CM_TY + 2;
+constexpr int CM_NI = CM_TX * CM_TY;               // interior nodes (2 per thread)
+constexpr int CM_NH = CM_HX * CM_HY - CM_NI;       // ring nodes (< 256)
+static_assert(CM_NI == 512 && CM_NH <= 256, "two interior nodes and one ring node per thread");
+
 template <typename T>
-__global__ __launch_bounds__(256) void k_adj_collide(const T* __restrict__ rec,
-                                                     const T* __restrict__ hat, AF<T> af,
-                                                     double* acc_part, Coef<T> c, Geom g) {
-  double alpha_acc = 0.0;
-  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
-    const NodeIdx k = node_idx(n, g);
-    T S, jx, jy, gmux, gmuy, lapmu;
-    Macro<T> m;
-    fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
-    T v[3][3], dpx, dpy, lapp;
-    load3x3(rec + (int64_t)R_P * g.Ns, k, v);
-    stencil(v, dpx, dpy, lapp);
-    T fh[9], gh[9];
-    post_hat9<T>(hat, 0, k, g.Ns, fh);
-    post_hat9<T>(hat, 9, k, g.Ns, gh);
-    NodeBar<T> nb;
-    collide_node_T(fh, gh, m, dpx, dpy, c, nb);
-    af[A_DPX][n] = nb.dpx;
-    af[A_DPY][n] = nb.dpy;
-    af[A_P][n] = nb.p;
-    af[A_RHO][n] = nb.rho;
-    af[A_UX][n] = nb.ux;
-    af[A_UY][n] = nb.uy;
-    af[A_FX][n] = nb.Fx;
-    af[A_FY][n] = nb.Fy;
-    af[A_DRX][n] = nb.drx;
-    af[A_DRY][n] = nb.dry;
-    af[A_D][n] = nb.D;
-    af[A_PHI1][n] = nb.phi;
-    af[A_MU1][n] = nb.mu;
-    alpha_acc += double(nb.alpha);
+struct CmLds {
+  T dpx[CM_HY][CM_HX];
+  T dpy[CM_HY][CM_HX];
+};
+
+// local position of ring node h: the full bottom and top rows, then the
+// left and right columns of the interior rows
+__device__ __forceinline__ void ring_pos(int h, int& ly, int& lx) {
+  if (h < CM_HX) {
+    ly = 0;
+    lx = h;
+  } else if (h < 2 * CM_HX) {
+    ly = CM_HY - 1;
+    lx = h - CM_HX;
+  } else {
+    h -= 2 * CM_HX;
+    ly = 1 + (h >> 1);
+    lx = (h & 1) ? CM_HX - 1 : 0;
   }
-  block_add(alpha_acc, AP_ALPHA, acc_part);
 }
 
-// AK2: transposes of grad p (gathered), the pressure, velocity, force, D,
-// grad rho and rho definitions.
-template <typename T>
-__global__ __launch_bounds__(256) void k_adj_macro(const T* __restrict__ rec, AF<T> af,
-                                                   double* acc_part, Coef<T> c, Geom g) {
-  double lam_acc = 0.0;
-  for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
-    const NodeIdx k = node_idx(n, g);
-    T S, jx, jy, gmux, gmuy, lapmu;
-    Macro<T> m;
-    fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
-    T b_p = af[A_P][n] + stencil_T<T, true, false>(af[A_DPX], af[A_DPY], nullptr, k);
-    T b_rho = af[A_RHO][n], b_ux = af[A_UX][n], b_uy = af[A_UY][n];
-    T b_Fx = af[A_FX][n], b_Fy = af[A_FY][n], b_drx = af[A_DRX][n], b_dry = af[A_DRY][n];
-    T b_D = af[A_D][n], b_phi = af[A_PHI1][n];
-    // p = S + (ux drx + uy dry - gamma rho D) / 6
-    const T b_S = b_p;
-    b_ux += b_p * m.drx * T(1.0 / 6.0);
-    b_uy += b_p * m.dry * T(1.0 / 6.0);
-    b_drx += b_p * m.ux * T(1.0 / 6.0);
-    b_dry += b_p * m.uy * T(1.0 / 6.0);
-    b_rho -= b_p * c.gamma * m.D * T(1.0 / 6.0);
-    b_D -= b_p * c.gamma * m.rho * T(1.0 / 6.0);
-    // u = (j + F / 6) * inv, inv = 3 / rho
-    const T inv = T(3) / m.rho;
-    const T b_jx = b_ux * inv, b_jy = b_uy * inv;
-    b_Fx += b_ux * inv * T(1.0 / 6.0);
-    b_Fy += b_uy * inv * T(1.0 / 6.0);
-    const T b_inv = b_ux * (jx + m.Fx * T(1.0 / 6.0)) + b_uy * (jy + m.Fy * T(1.0 / 6.0));
-    b_rho -= b_inv * inv / m.rho;
-    // F = -phi grad mu + (rho - rho_ref) g
-    b_phi -= b_Fx * gmux + b_Fy * gmuy;
-    const T b_gmux = -m.phi * b_Fx, b_gmuy = -m.phi * b_Fy;
-    b_rho += b_Fx * c.gx + b_Fy * c.gy;
-    // D = lambda lap mu; grad rho = drho grad phi; rho = rho_B + drho phi
-    lam_acc += double(b_D) * double(lapmu);
-    af[A_S][n] = b_S;
-    af[A_JX][n] = b_jx;
-    af[A_JY][n] = b_jy;
-    af[A_GMUX][n] = b_gmux;
-    af[A_GMUY][n] = b_gmuy;
-    af[A_LMU][n] = c.lam * b_D;
-    af[A_GPHX][n] = c.drho * b_drx;
-    af[A_GPHY][n] = c.drho * b_dry;
-    af[A_PHI2][n] = b_phi + c.drho * b_rho;
+// Node of local position (ly, lx) in the tile at (x0, y0): wrapped in x
+// (and in y when periodic); false beyond a wall.
+__device__ __forceinline__ bool cm_node(int x0, int y0, int ly, int lx, const Geom& g, int& n) {
+  int y = y0 - 1 + ly, x = x0 - 1 + lx;
+  if (g.walls) {
+    if (y < 0 || y >= g.ny) return false;
+  } else {
+    y %= g.ny;
+    if (y < 0) y += g.ny;
   }
+  x %= g.nx;
+  if (x < 0) x += g.nx;
+  n = y * g.nx + x;
+  return true;
+}
+
+template <typename T>
+__device__ __forceinline__ void collide_T_at(const T* rec, const T* hat, int n, const Coef<T>& c,
+                                             const Geom& g, NodeBar<T>& nb) {
+  const NodeIdx k = node_idx(n, g);
+  T S, jx, jy, gmux, gmuy, lapmu;
+  Macro<T> m;
+  fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+  T v[3][3], dpx, dpy, lapp;
+  load3x3(rec + (int64_t)R_P * g.Ns, k, v);
+  stencil(v, dpx, dpy, lapp);
+  T fh[9], gh[9];
+  post_hat9<T>(hat, 0, k, g.Ns, fh);
+  post_hat9<T>(hat, 9, k, g.Ns, gh);
+  collide_node_T(fh, gh, m, dpx, dpy, c, nb);
+}
+
+// grad^T of the grad p cotangent at interior position (ly, lx), global row
+// y, from the tile in LDS (same terms, same order as stencil_T).
+template <typename T, int I>
+__device__ __forceinline__ void gpT_term(const CmLds<T>& L, int ly, int lx, int y, const Geom& g,
+                                         T& acc) {
+  constexpr int cx = CXS(I), cy = CYS(I);
+  const T w3 = T(3.0 * WGT(I));
+  const int ys = y - cy;
+  if (!g.walls || (ys >= 0 && ys < g.ny))
+    acc += w3 * (T(cx) * L.dpx[ly - cy][lx - cx] + T(cy) * L.dpy[ly - cy][lx - cx]);
+  if (g.walls && ((cy == -1 && y == 0) || (cy == 1 && y == g.ny - 1)))
+    acc += w3 * (T(cx) * L.dpx[ly][lx - cx] + T(cy) * L.dpy[ly][lx - cx]);
+}
+
+template <typename T>
+__device__ __forceinline__ T gradT_p(const CmLds<T>& L, int ly, int lx, int y, const Geom& g) {
+  T acc = T(0);
+  gpT_term<T, 1>(L, ly, lx, y, g, acc);
+  gpT_term<T, 2>(L, ly, lx, y, g, acc);
+  gpT_term<T, 3>(L, ly, lx, y, g, acc);
+  gpT_term<T, 4>(L, ly, lx, y, g, acc);
+  gpT_term<T, 5>(L, ly, lx, y, g, acc);
+  gpT_term<T, 6>(L, ly, lx, y, g, acc);
+  gpT_term<T, 7>(L, ly, lx, y, g, acc);
+  gpT_term<T, 8>(L, ly, lx, y, g, acc);
+  return acc;
+}
+
+// Transposes of the pressure, velocity, force, D, grad rho and rho
+// definitions at node n given the full pressure cotangent b_p.
+template <typename T>
+__device__ __forceinline__ double macro_T_at(const T* rec, int n, const NodeBar<T>& nb, T b_p,
+                                             AF<T> af, const Coef<T>& c, const Geom& g) {
+  const NodeIdx k = node_idx(n, g);
+  T S, jx, jy, gmux, gmuy, lapmu;
+  Macro<T> m;
+  fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+  T b_rho = nb.rho, b_ux = nb.ux, b_uy = nb.uy;
+  T b_Fx = nb.Fx, b_Fy = nb.Fy, b_drx = nb.drx, b_dry = nb.dry;
+  T b_D = nb.D, b_phi = nb.phi;
+  // p = S + (ux drx + uy dry - gamma rho D) / 6
+  const T b_S = b_p;
+  b_ux += b_p * m.drx * T(1.0 / 6.0);
+  b_uy += b_p * m.dry * T(1.0 / 6.0);
+  b_drx += b_p * m.ux * T(1.0 / 6.0);
+  b_dry += b_p * m.uy * T(1.0 / 6.0);
+  b_rho -= b_p * c.gamma * m.D * T(1.0 / 6.0);
+  b_D -= b_p * c.gamma * m.rho * T(1.0 / 6.0);
+  // u = (j + F / 6) * inv, inv = 3 / rho
+  const T inv = T(3) / m.rho;
+  const T b_jx = b_ux * inv, b_jy = b_uy * inv;
+  b_Fx += b_ux * inv * T(1.0 / 6.0);
+  b_Fy += b_uy * inv * T(1.0 / 6.0);
+  const T b_inv = b_ux * (jx + m.Fx * T(1.0 / 6.0)) + b_uy * (jy + m.Fy * T(1.0 / 6.0));
+  b_rho -= b_inv * inv / m.rho;
+  // F = -phi grad mu + (rho - rho_ref) g
+  b_phi -= b_Fx * gmux + b_Fy * gmuy;
+  const T b_gmux = -m.phi * b_Fx, b_gmuy = -m.phi * b_Fy;
+  b_rho += b_Fx * c.gx + b_Fy * c.gy;
+  // D = lambda lap mu; grad rho = drho grad phi; rho = rho_B + drho phi
+  af[A_S][n] = b_S;
+  af[A_JX][n] = b_jx;
+  af[A_JY][n] = b_jy;
+  af[A_GMUX][n] = b_gmux;
+  af[A_GMUY][n] = b_gmuy;
+  af[A_LMU][n] = c.lam * b_D;
+  af[A_GPHX][n] = c.drho * b_drx;
+  af[A_GPHY][n] = c.drho * b_dry;
+  af[A_PHI2][n] = b_phi + c.drho * b_rho;
+  af[A_MU1][n] = nb.mu;
+  return double(b_D) * double(lapmu);   // lambda cotangent of this node
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
+                                                const T* __restrict__ hat, AF<T> af,
+                                                double* acc_part, Coef<T> c, Geom g) {
+  __shared__ CmLds<T> L;
+  const int tx = (g.nx + CM_TX - 1) / CM_TX, ty = (g.ny + CM_TY - 1) / CM_TY;
+  const int t = threadIdx.x;
+  double alpha_acc = 0.0, lam_acc = 0.0;
+  for (int tile = blockIdx.x; tile < tx * ty; tile += gridDim.x) {
+    const int y0 = (tile / tx) * CM_TY, x0 = (tile % tx) * CM_TX;
+    // phase 1: collision transpose on the two interior nodes of this thread
+    // (kept) and on one ring node (grad p cotangent only)
+    NodeBar<T> nb[2];
+    int own[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int i = t + 256 * q;
+      const int ly = 1 + i / CM_TX, lx = 1 + i % CM_TX;
+      int n = -1;
+      own[q] = -1;
+      if (cm_node(x0, y0, ly, lx, g, n)) {
+        collide_T_at<T>(rec, hat, n, c, g, nb[q]);
+        L.dpx[ly][lx] = nb[q].dpx;
+        L.dpy[ly][lx] = nb[q].dpy;
+        // the tile's own nodes (partial tiles hold wrapped copies beyond
+        // nx or ny, which are only read as neighbours)
+        if (x0 + lx - 1 < g.nx && y0 + ly - 1 < g.ny) {
+          own[q] = n;
+          alpha_acc += double(nb[q].alpha);
+        }
+      }
+    }
+    if (t < CM_NH) {
+      int ly, lx, n;
+      ring_pos(t, ly, lx);
+      if (cm_node(x0, y0, ly, lx, g, n)) {
+        NodeBar<T> r;
+        collide_T_at<T>(rec, hat, n, c, g, r);
+        L.dpx[ly][lx] = r.dpx;
+        L.dpy[ly][lx] = r.dpy;
+      }
+    }
+    __syncthreads();
+    // phase 2: full pressure cotangent and the macroscopic transposes
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      if (own[q] >= 0) {
+        const int i = t + 256 * q;
+        const int ly = 1 + i / CM_TX, lx = 1 + i % CM_TX;
+        const T b_p = nb[q].p + gradT_p<T>(L, ly, lx, y0 + ly - 1, g);
+        lam_acc += macro_T_at<T>(rec, own[q], nb[q], b_p, af, c, g);
+      }
+    }
+    __syncthreads();
+  }
+  block_add(alpha_acc, AP_ALPHA, acc_part);
   block_add(lam_acc, AP_LAMBDA, acc_part);
 }
 
@@ -552,8 +664,7 @@ lbm_status adj_core(const CtxView& v, const T* rec) {
   const T* hin = (const T*)a.hat[a.cur];
   T* hout = (T*)a.hat[a.cur ^ 1];
   const dim3 grid(a.nred), blk(256);
-  hipLaunchKernelGGL(k_adj_collide<T>, grid, blk, 0, v.stream, rec, hin, af, a.part, k, g);
-  hipLaunchKernelGGL(k_adj_macro<T>, grid, blk, 0, v.stream, rec, af, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_cm<T>, grid, blk, 0, v.stream, rec, hin, af, a.part, k, g);
   hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, rec + (int64_t)R_PHI * g.Ns, af,
                      a.part, k, g);
   hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);

@@ -12,12 +12,7 @@ namespace qilbm {
 
 // Planes of the adjoint scratch fields (compute type), one per node.
 enum AdjField : int {
-  A_DPX = 0, A_DPY,            // cotangent of grad p (from the collision)
-  A_P, A_RHO,                  // p, rho (collision part)
-  A_UX, A_UY, A_FX, A_FY,      // u, F (collision part)
-  A_DRX, A_DRY,                // grad rho (collision part)
-  A_D,                         // D = lambda lap mu (collision part)
-  A_PHI1, A_MU1,               // phi, mu (collision part)
+  A_MU1 = 0,                   // mu (collision part)
   A_S, A_JX, A_JY,             // S = sum f, j = sum c f
   A_GMUX, A_GMUY, A_LMU,       // grad mu, lap mu
   A_GPHX, A_GPHY,              // grad phi
