@@ -343,9 +343,11 @@ __device__ __forceinline__ bool cm_node(int x0, int y0, int ly, int lx, const Ge
   return true;
 }
 
+// Collision transpose at node n; fd receives the direct part of the f
+// cotangents, (1 - 1/tau_f) times the post-collision ones.
 template <typename T>
 __device__ __forceinline__ void collide_T_at(const T* rec, const T* hat, int n, const Coef<T>& c,
-                                             const Geom& g, NodeBar<T>& nb) {
+                                             const Geom& g, NodeBar<T>& nb, T fd[9]) {
   const NodeIdx k = node_idx(n, g);
   T S, jx, jy, gmux, gmuy, lapmu;
   Macro<T> m;
@@ -353,10 +355,10 @@ __device__ __forceinline__ void collide_T_at(const T* rec, const T* hat, int n, 
   T v[3][3], dpx, dpy, lapp;
   load3x3(rec + (int64_t)R_P * g.Ns, k, v);
   stencil(v, dpx, dpy, lapp);
-  T fh[9], gh[9];
-  post_hat9<T>(hat, 0, k, g.Ns, fh);
+  T gh[9];
+  post_hat9<T>(hat, 0, k, g.Ns, fd);
   post_hat9<T>(hat, 9, k, g.Ns, gh);
-  collide_node_T(fh, gh, m, dpx, dpy, c, nb);
+  collide_node_T(fd, gh, m, dpx, dpy, c, nb);
 }
 
 // grad^T of the grad p cotangent at interior position (ly, lx), global row
@@ -388,10 +390,12 @@ __device__ __forceinline__ T gradT_p(const CmLds<T>& L, int ly, int lx, int y, c
 }
 
 // Transposes of the pressure, velocity, force, D, grad rho and rho
-// definitions at node n given the full pressure cotangent b_p.
+// definitions at node n given the full pressure cotangent b_p; then the
+// node's f cotangents are complete: fd_i + Sbar + c_i.jbar into hat_out.
 template <typename T>
 __device__ __forceinline__ double macro_T_at(const T* rec, int n, const NodeBar<T>& nb, T b_p,
-                                             AF<T> af, const Coef<T>& c, const Geom& g) {
+                                             const T fd[9], T* hat_out, AF<T> af,
+                                             const Coef<T>& c, const Geom& g) {
   const NodeIdx k = node_idx(n, g);
   T S, jx, jy, gmux, gmuy, lapmu;
   Macro<T> m;
@@ -419,9 +423,9 @@ __device__ __forceinline__ double macro_T_at(const T* rec, int n, const NodeBar<
   const T b_gmux = -m.phi * b_Fx, b_gmuy = -m.phi * b_Fy;
   b_rho += b_Fx * c.gx + b_Fy * c.gy;
   // D = lambda lap mu; grad rho = drho grad phi; rho = rho_B + drho phi
-  af[A_S][n] = b_S;
-  af[A_JX][n] = b_jx;
-  af[A_JY][n] = b_jy;
+#pragma unroll
+  for (int i = 0; i < 9; ++i)
+    hat_out[(int64_t)i * g.Ns + n] = fd[i] + b_S + T(CXS(i)) * b_jx + T(CYS(i)) * b_jy;
   af[A_GMUX][n] = b_gmux;
   af[A_GMUY][n] = b_gmuy;
   af[A_LMU][n] = c.lam * b_D;
@@ -434,8 +438,8 @@ __device__ __forceinline__ double macro_T_at(const T* rec, int n, const NodeBar<
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
-                                                const T* __restrict__ hat, AF<T> af,
-                                                double* acc_part, Coef<T> c, Geom g) {
+                                                const T* __restrict__ hat, T* __restrict__ hat_out,
+                                                AF<T> af, double* acc_part, Coef<T> c, Geom g) {
   __shared__ CmLds<T> L;
   const int tx = (g.nx + CM_TX - 1) / CM_TX, ty = (g.ny + CM_TY - 1) / CM_TY;
   const int t = threadIdx.x;
@@ -445,6 +449,7 @@ __global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
     // phase 1: collision transpose on the two interior nodes of this thread
     // (kept) and on one ring node (grad p cotangent only)
     NodeBar<T> nb[2];
+    T fd[2][9];
     int own[2];
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
@@ -453,7 +458,7 @@ __global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
       int n = -1;
       own[q] = -1;
       if (cm_node(x0, y0, ly, lx, g, n)) {
-        collide_T_at<T>(rec, hat, n, c, g, nb[q]);
+        collide_T_at<T>(rec, hat, n, c, g, nb[q], fd[q]);
         L.dpx[ly][lx] = nb[q].dpx;
         L.dpy[ly][lx] = nb[q].dpy;
         // the tile's own nodes (partial tiles hold wrapped copies beyond
@@ -469,7 +474,8 @@ __global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
       ring_pos(t, ly, lx);
       if (cm_node(x0, y0, ly, lx, g, n)) {
         NodeBar<T> r;
-        collide_T_at<T>(rec, hat, n, c, g, r);
+        T rd[9];
+        collide_T_at<T>(rec, hat, n, c, g, r, rd);
         L.dpx[ly][lx] = r.dpx;
         L.dpy[ly][lx] = r.dpy;
       }
@@ -482,7 +488,7 @@ __global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
         const int i = t + 256 * q;
         const int ly = 1 + i / CM_TX, lx = 1 + i % CM_TX;
         const T b_p = nb[q].p + gradT_p<T>(L, ly, lx, y0 + ly - 1, g);
-        lam_acc += macro_T_at<T>(rec, own[q], nb[q], b_p, af, c, g);
+        lam_acc += macro_T_at<T>(rec, own[q], nb[q], b_p, fd[q], hat_out, af, c, g);
       }
     }
     __syncthreads();
@@ -515,25 +521,20 @@ __global__ __launch_bounds__(256) void k_adj_mu(const T* __restrict__ fphi, AF<T
 }
 
 // AK4: phi cotangent (grad^T of grad phi's, lap^T of lap phi's), then the
-// moments: gbar_i = direct + phibar, fbar_i = direct + Sbar + c_i.jbar, with
-// the direct part (1 - 1/tau) times the post-collision cotangent gathered
-// from hat again.
+// g cotangents gbar_i = direct + phibar, with the direct part (1 - 1/tau_g)
+// times the post-collision cotangent gathered from hat again (the f
+// cotangents are complete after AK1+2).
 template <typename T>
 __global__ __launch_bounds__(256) void k_adj_final(const T* __restrict__ hat, AF<T> af,
                                                    T* __restrict__ hat_out, Coef<T> c, Geom g) {
   for (int n = blockIdx.x * 256 + threadIdx.x; n < (int)g.N; n += gridDim.x * 256) {
     const NodeIdx k = node_idx(n, g);
     const T b_phi = af[A_PHI3][n] + stencil_T<T, true, true>(af[A_GPHX], af[A_GPHY], af[A_LPHI], k);
-    const T bS = af[A_S][n], bjx = af[A_JX][n], bjy = af[A_JY][n];
-    T fh[9], gh[9];
-    post_hat9<T>(hat, 0, k, g.Ns, fh);
+    T gh[9];
     post_hat9<T>(hat, 9, k, g.Ns, gh);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) {
-      hat_out[(int64_t)i * g.Ns + n] =
-          fh[i] * (T(1) - c.inv_tau_f) + bS + T(CXS(i)) * bjx + T(CYS(i)) * bjy;
+    for (int i = 0; i < 9; ++i)
       hat_out[(int64_t)(9 + i) * g.Ns + n] = gh[i] * (T(1) - c.inv_tau_g) + b_phi;
-    }
   }
 }
 
@@ -664,7 +665,7 @@ lbm_status adj_core(const CtxView& v, const T* rec) {
   const T* hin = (const T*)a.hat[a.cur];
   T* hout = (T*)a.hat[a.cur ^ 1];
   const dim3 grid(a.nred), blk(256);
-  hipLaunchKernelGGL(k_adj_cm<T>, grid, blk, 0, v.stream, rec, hin, af, a.part, k, g);
+  hipLaunchKernelGGL(k_adj_cm<T>, grid, blk, 0, v.stream, rec, hin, hout, af, a.part, k, g);
   hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, rec + (int64_t)R_PHI * g.Ns, af,
                      a.part, k, g);
   hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);

@@ -13,7 +13,6 @@ namespace qilbm {
 // Planes of the adjoint scratch fields (compute type), one per node.
 enum AdjField : int {
   A_MU1 = 0,                   // mu (collision part)
-  A_S, A_JX, A_JY,             // S = sum f, j = sum c f
   A_GMUX, A_GMUY, A_LMU,       // grad mu, lap mu
   A_GPHX, A_GPHY,              // grad phi
   A_PHI2,                      // phi after the velocity/force/pressure stage
