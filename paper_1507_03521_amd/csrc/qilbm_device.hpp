@@ -94,8 +94,11 @@ __host__ __device__ inline int64_t pop_bytes(int P, int64_t Ns) {
 }
 
 // Plane k in 0..17: f_0..f_8 are k = 0..8, g_0..g_8 are k = 9..17.
-// FP64: all binary64. FP32: f binary32, g Q2.29 int32. FP16 storage: f
-// planes (binary16), then g_0 (Q2.29 int32), then g_1..8 (binary16).
+// FP64: all binary64. FP32: f binary32, g Q2.29 int32. FP16 storage: the
+// f_0 plane (binary16), the g_0 plane (Q2.29 int32), then for i = 1..8 one
+// plane of 32-bit words holding f_i (low half) and g_i (high half) of a node:
+// f_i and g_i always move together (same pull source), so one 32-bit access
+// serves both.
 // A plane's base address is uniform across the wavefront; the per-lane part
 // is a 32-bit byte offset (lattices are capped so that it cannot overflow),
 // which lets the compiler use scalar-base + 32-bit-offset addressing.
@@ -113,8 +116,14 @@ struct Pop {
   __device__ __forceinline__ static void put(char* plane, uint32_t idx, S v) {
     *reinterpret_cast<S*>(plane + idx * (uint32_t)sizeof(S)) = v;
   }
-  __device__ __forceinline__ const char* half_plane(int k) const {
-    return k < 9 ? base + k * Ns * 2 : base + 22 * Ns + (k - 10) * Ns * 2;
+  // FP16 storage: address of the binary16 of plane k (k != 9) at idx
+  __device__ __forceinline__ char* half_at(int k, uint32_t idx) const {
+    if (k == 0) return base + idx * 2u;
+    const int i = k < 9 ? k : k - 9;
+    return base + 6 * Ns + (int64_t)(i - 1) * 4 * Ns + idx * 4u + (k < 9 ? 0 : 2);
+  }
+  __device__ __forceinline__ static __half half_ld(const char* a) {
+    return *reinterpret_cast<const __half*>(a);
   }
   __device__ __forceinline__ static int dir(int k) { return k < 9 ? k : k - 9; }
 
@@ -126,8 +135,8 @@ struct Pop {
       if (k < 9) return at<float>(base + k * Ns * 4, idx);
       return float(at<int32_t>(base + k * Ns * 4, idx)) * GQI;
     } else {
-      if (k == 9) return float(at<int32_t>(base + 18 * Ns, idx)) * GQI;
-      return __half2float(at<__half>(half_plane(k), idx)) * H_INV(dir(k));
+      if (k == 9) return float(at<int32_t>(base + 2 * Ns, idx)) * GQI;
+      return __half2float(half_ld(half_at(k, idx))) * H_INV(dir(k));
     }
   }
   // value of plane k at idx in binary64: exact for f planes and FP64; for g
@@ -139,7 +148,7 @@ struct Pop {
     } else {
       if (k >= 9) return double(ld_q(k, idx)) * GQI_D;
       if constexpr (P == P_F32) return double(at<float>(base + k * Ns * 4, idx));
-      else return double(__half2float(at<__half>(half_plane(k), idx))) * double(H_INV(k));
+      else return double(__half2float(half_ld(half_at(k, idx)))) * double(H_INV(k));
     }
   }
   // Q2.29 contribution of g plane k (9..17) at idx (fixed-point modes only)
@@ -147,8 +156,8 @@ struct Pop {
     if constexpr (P == P_F32) {
       return at<int32_t>(base + k * Ns * 4, idx);
     } else {
-      if (k == 9) return at<int32_t>(base + 18 * Ns, idx);
-      return __float2int_rn(__half2float(at<__half>(half_plane(k), idx)) * HQ(dir(k)));
+      if (k == 9) return at<int32_t>(base + 2 * Ns, idx);
+      return __float2int_rn(__half2float(half_ld(half_at(k, idx))) * HQ(dir(k)));
     }
   }
   // stores v into plane k; for g planes in the fixed-point modes returns the
@@ -168,18 +177,18 @@ struct Pop {
     } else {
       if (k == 9) {
         const int32_t q = __float2int_rn(v * GQ);
-        put<int32_t>(base + 18 * Ns, idx, q);
+        put<int32_t>(base + 2 * Ns, idx, q);
         return q;
       }
       const __half h = __float2half_rn(v * H_SCALE(dir(k)));
-      put<__half>(const_cast<char*>(half_plane(k)), idx, h);
+      *reinterpret_cast<__half*>(half_at(k, idx)) = h;
       return k < 9 ? 0 : __float2int_rn(__half2float(h) * HQ(dir(k)));
     }
   }
   // stores the Q2.29 word q into g_0 (fixed-point modes)
   __device__ __forceinline__ void st_g0_q(uint32_t idx, int32_t q) const {
     if constexpr (P == P_F32) put<int32_t>(base + 9 * Ns * 4, idx, q);
-    else if constexpr (P == P_F16) put<int32_t>(base + 18 * Ns, idx, q);
+    else if constexpr (P == P_F16) put<int32_t>(base + 2 * Ns, idx, q);
   }
 };
 

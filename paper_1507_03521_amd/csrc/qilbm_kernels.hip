@@ -380,7 +380,9 @@ typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned in
 template <int P> struct BufT;
 template <> struct BufT<P_F64> { using F = double; using G0 = double; using GR = double; using R = double; };
 template <> struct BufT<P_F32> { using F = float; using G0 = int32_t; using GR = int32_t; using R = uint32_t; };
-template <> struct BufT<P_F16> { using F = __half; using G0 = int32_t; using GR = __half; using R = uint32_t; };
+// FP16 storage: F is the f_0 plane's binary16; GR the 32-bit word that holds
+// f_i (low half) and g_i (high half), i >= 1.
+template <> struct BufT<P_F16> { using F = __half; using G0 = int32_t; using GR = uint32_t; using R = uint32_t; };
 
 template <typename S>
 __device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
@@ -425,8 +427,8 @@ struct BufPop {
     char *f, *g0, *gr;
     if constexpr (P == P_F16) {
       f = b;
-      g0 = b + 18 * Ns;
-      gr = b + 22 * Ns;
+      g0 = b + 2 * Ns;
+      gr = b + 6 * Ns;
     } else {
       f = b;
       g0 = b + 9 * Ns * (int64_t)sizeof(T);
@@ -438,7 +440,8 @@ struct BufPop {
     pg = (uint32_t)(Ns * sizeof(GR));
     rg0 = __builtin_amdgcn_make_buffer_rsrc(g0, 0, (int)(Ns * sizeof(G0)), BUF_WORD3);
     if constexpr (!BIG) {
-      rf = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)(9 * (int64_t)pf), BUF_WORD3);
+      rf = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)((P == P_F16 ? 1 : 9) * (int64_t)pf),
+                                             BUF_WORD3);
       rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)(8 * (int64_t)pg), BUF_WORD3);
     }
   }
@@ -470,7 +473,10 @@ struct BufPop {
   // raw word of f_I (G = false) or g_I (G = true) at element (row, col[dx+1])
   template <bool G, int I>
   __device__ __forceinline__ R ld(uint32_t elem_row, const uint32_t col[3], int dx) const {
-    if constexpr (!G) {
+    if constexpr (P == P_F16 && I >= 1) {
+      // the pair word of direction I (f_I low half, g_I high half)
+      return buf_ld<GR>(g_rsrc<I>(), col[dx + 1] * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
+    } else if constexpr (!G) {
       return raw(buf_ld<F>(f_rsrc<I>(), col[dx + 1] * (uint32_t)sizeof(F), f_soff<I>(elem_row)));
     } else if constexpr (I == 0) {
       return raw(buf_ld<G0>(rg0, col[dx + 1] * (uint32_t)sizeof(G0),
@@ -490,13 +496,13 @@ struct BufPop {
   __device__ __forceinline__ static T val_g(R w) {
     if constexpr (P == P_F64) return w;
     else if constexpr (P == P_F32 || I == 0) return float((int32_t)w) * GQI;
-    else return __half2float(__builtin_bit_cast(__half, (uint16_t)w)) * H_INV(I);
+    else return __half2float(__builtin_bit_cast(__half, (uint16_t)(w >> 16))) * H_INV(I);
   }
   // Q2.29 contribution of a raw g word (fixed-point modes)
   template <int I>
   __device__ __forceinline__ static int32_t q_g(R w) {
     if constexpr (P == P_F32 || I == 0) return (int32_t)w;
-    else return __float2int_rn(__half2float(__builtin_bit_cast(__half, (uint16_t)w)) * HQ(I));
+    else return __float2int_rn(__half2float(__builtin_bit_cast(__half, (uint16_t)(w >> 16))) * HQ(I));
   }
   template <int I>
   __device__ __forceinline__ void st_f(T v, uint32_t elem_row, uint32_t col) const {
@@ -521,6 +527,17 @@ struct BufPop {
       buf_st<GR>(h, g_rsrc<I>(), col * (uint32_t)sizeof(GR), so);
       return __float2int_rn(__half2float(h) * HQ(I));
     }
+  }
+  // FP16 storage: stores f_I and g_I (I >= 1) as one word; returns the
+  // Q2.29 contribution of the stored g_I
+  template <int I>
+  __device__ __forceinline__ int32_t st_pair(T fv, T gv, uint32_t elem_row, uint32_t col) const {
+    const __half hf = __float2half_rn(fv * H_SCALE(I));
+    const __half hg = __float2half_rn(gv * H_SCALE(I));
+    const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, hf) |
+                       ((uint32_t)__builtin_bit_cast(uint16_t, hg) << 16);
+    buf_st<GR>(w, g_rsrc<I>(), col * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
+    return __float2int_rn(__half2float(hg) * HQ(I));
   }
   __device__ __forceinline__ void st_g0(T v, int32_t q, uint32_t elem_row, uint32_t col) const {
     if constexpr (P == P_F64) buf_st<G0>(v, rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
@@ -590,6 +607,25 @@ __device__ __forceinline__ void pull_row(const FusedCtx<P, BIG>& k, int y, typen
     pull_row_dirs<P, BIG, G, 0>(k.in, rows, k.col, v);
 }
 
+// FP16 storage: the f_0 word of row y (direction 0 pulls from the node
+// itself, walls included).
+template <int P, bool BIG>
+__device__ __forceinline__ typename BufT<P>::R pull_f0(const FusedCtx<P, BIG>& k, int y) {
+  return k.in.template ld<false, 0>((uint32_t)(y * k.g.nx), k.col, 0);
+}
+
+template <int P, bool BIG, int I = 1>
+__device__ __forceinline__ int32_t store_pairs(const FusedCtx<P, BIG>& k, uint32_t row,
+                                               const typename PrecT<P>::T f[9],
+                                               const typename PrecT<P>::T gg[9]) {
+  if constexpr (I < 9) {
+    const int32_t q = k.out.template st_pair<I>(f[I], gg[I], row, k.col[1]);
+    return q + store_pairs<P, BIG, I + 1>(k, row, f, gg);
+  } else {
+    return 0;
+  }
+}
+
 template <int P, bool BIG, int I = 1>
 __device__ __forceinline__ int32_t store_g_rest(const FusedCtx<P, BIG>& k, uint32_t row,
                                               const typename PrecT<P>::T gg[9]) {
@@ -616,9 +652,15 @@ template <int P, bool BIG>
 __device__ __forceinline__ void store_row(const FusedCtx<P, BIG>& k, uint32_t row,
                                           const typename PrecT<P>::T f[9],
                                           const typename PrecT<P>::T gg[9], int32_t phi_q) {
-  store_f<P, BIG>(k, row, f);
-  const int32_t rest = store_g_rest<P, BIG>(k, row, gg);
-  k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
+  if constexpr (P == P_F16) {
+    k.out.template st_f<0>(f[0], row, k.col[1]);
+    const int32_t rest = store_pairs<P, BIG>(k, row, f, gg);
+    k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
+  } else {
+    store_f<P, BIG>(k, row, f);
+    const int32_t rest = store_g_rest<P, BIG>(k, row, gg);
+    k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
+  }
 }
 
 // Decodes raw words in place (R holds the bits of the compute-type value
@@ -646,6 +688,25 @@ template <int P>
 __device__ __forceinline__ typename PrecT<P>::T as_val(typename BufT<P>::R w) {
   if constexpr (P == P_F64) return w;
   else return __builtin_bit_cast(float, w);
+}
+
+// FP16 storage: exact Q2.29 sum of a pulled row's g (raw words left intact)
+template <int P, int I = 0>
+__device__ __forceinline__ int32_t qsum_g(const typename BufT<P>::R w[9]) {
+  if constexpr (I < 9) return BufPop<P>::template q_g<I>(w[I]) + qsum_g<P, I + 1>(w);
+  else return 0;
+}
+// FP16 storage: f (low halves, f_0 from its own word) and g (high halves,
+// g_0 Q2.29) of a pulled row
+template <int P, int I = 0>
+__device__ __forceinline__ void unpack_row(const typename BufT<P>::R w[9],
+                                           typename BufT<P>::R f0w, typename PrecT<P>::T f[9],
+                                           typename PrecT<P>::T g[9]) {
+  if constexpr (I < 9) {
+    f[I] = BufPop<P>::template val_f<I>(I == 0 ? f0w : w[I]);
+    g[I] = BufPop<P>::template val_g<I>(w[I]);
+    unpack_row<P, I + 1>(w, f0w, f, g);
+  }
 }
 
 template <typename T, int NT>
@@ -694,13 +755,19 @@ template <int P, bool BIG, bool REC, int J, int NT>
 __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
                                            typename BufT<P>::R (&gb)[4][9],
                                            typename BufT<P>::R (&fb)[2][9],
+                                           typename BufT<P>::R (&f0b)[4],
                                            FusedLds<typename PrecT<P>::T, NT>& L) {
   using T = typename PrecT<P>::T;
+  // FP16 storage loads f and g of a row together (paired words): the g ring
+  // then carries f too, and f0b the f_0 words; the f ring fb is unused
+  constexpr bool PAIR = P == P_F16;
   const Geom& g = k.g;
   const int lc = k.lc;
   // A: phi at row r (its g was loaded by the previous iteration)
   if (need_phi(k, r)) {
-    const int32_t q = decode_g<P>(gb[J]);
+    int32_t q;
+    if constexpr (PAIR) q = qsum_g<P>(gb[J]);
+    else q = decode_g<P>(gb[J]);
     T ph;
     if constexpr (FixedG<P>::value) {
       ph = T(q) * T(GQI);
@@ -731,10 +798,15 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   // C: force, velocity, pressure at row r - 2d
   const int q = r - 2 * k.d;
   if (need_p(k, q)) {
-    decode_f<P>(fb[J & 1]);
     T fv[9];
+    if constexpr (PAIR) {
+      T gv[9];
+      unpack_row<P>(gb[(J + 2) & 3], f0b[(J + 2) & 3], fv, gv);
+    } else {
+      decode_f<P>(fb[J & 1]);
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fv[i] = as_val<P>(fb[J & 1][i]);
+      for (int i = 0; i < 9; ++i) fv[i] = as_val<P>(fb[J & 1][i]);
+    }
     T S, jx, jy;
     moments9(fv, S, jx, jy);
     T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
@@ -767,13 +839,22 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   // D: collide row r - 3d and store; meanwhile fetch the next iteration's rows
   const int cr = r - 3 * k.d;
   T f[9], gg[9];
+  if constexpr (PAIR) {
+    unpack_row<P>(gb[(J + 1) & 3], f0b[(J + 1) & 3], f, gg);
+  } else {
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    f[i] = as_val<P>(fb[(J + 1) & 1][i]);
-    gg[i] = as_val<P>(gb[(J + 1) & 3][i]);
+    for (int i = 0; i < 9; ++i) {
+      f[i] = as_val<P>(fb[(J + 1) & 1][i]);
+      gg[i] = as_val<P>(gb[(J + 1) & 3][i]);
+    }
   }
-  if (need_phi(k, r + k.d)) pull_row<P, BIG, true>(k, phys_row(r + k.d, g), gb[(J + 1) & 3]);
-  if (need_p(k, r - k.d)) pull_row<P, BIG, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
+  if (need_phi(k, r + k.d)) {
+    const int y = phys_row(r + k.d, g);
+    pull_row<P, BIG, true>(k, y, gb[(J + 1) & 3]);
+    if constexpr (PAIR) f0b[(J + 1) & 3] = pull_f0(k, y);
+  }
+  if constexpr (!PAIR)
+    if (need_p(k, r - k.d)) pull_row<P, BIG, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
   if (k.owns(cr)) {
     Macro<T> m;
     const T* nd = &L.node[cr & 1][0][0];
@@ -847,16 +928,20 @@ __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void 
   k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
   typename BufT<P>::R gb[4][9];
   typename BufT<P>::R fb[2][9];
+  typename BufT<P>::R f0b[4];
   const int r0 = k.d > 0 ? k.y0 - 3 : k.y1 + 2;
   const int nit = (k.y1 - k.y0) + 6;
   // prologue: g of the first row (the first f row is needed 2 iterations later
   // and is fetched by iteration 1)
-  if (need_phi(k, r0)) pull_row<P, BIG, true>(k, phys_row(r0, g), gb[0]);
+  if (need_phi(k, r0)) {
+    pull_row<P, BIG, true>(k, phys_row(r0, g), gb[0]);
+    if constexpr (P == P_F16) f0b[0] = pull_f0(k, phys_row(r0, g));
+  }
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, BIG, REC, 0, NT>(k, r0 + k.d * (it + 0), gb, fb, L);
-    fused_iter<P, BIG, REC, 1, NT>(k, r0 + k.d * (it + 1), gb, fb, L);
-    fused_iter<P, BIG, REC, 2, NT>(k, r0 + k.d * (it + 2), gb, fb, L);
-    fused_iter<P, BIG, REC, 3, NT>(k, r0 + k.d * (it + 3), gb, fb, L);
+    fused_iter<P, BIG, REC, 0, NT>(k, r0 + k.d * (it + 0), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 1, NT>(k, r0 + k.d * (it + 1), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 2, NT>(k, r0 + k.d * (it + 2), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 3, NT>(k, r0 + k.d * (it + 3), gb, fb, f0b, L);
   }
 }
 
@@ -965,7 +1050,7 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
 
 template <int P>
 bool fused_big(const Geom& g) {
-  const int64_t f_group = 9 * g.Ns * (int64_t)sizeof(typename BufT<P>::F);
+  const int64_t f_group = (P == P_F16 ? 1 : 9) * g.Ns * (int64_t)sizeof(typename BufT<P>::F);
   const int64_t g_group = 8 * g.Ns * (int64_t)sizeof(typename BufT<P>::GR);
   return f_group > (int64_t)UINT32_MAX || g_group > (int64_t)UINT32_MAX;
 }
