@@ -180,8 +180,8 @@ lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t seg_rows);
 
 /* Current fused launch shape into out[4] (host): column strips (of equal
- * width, at most 506 columns in FP32 and 250 in FP64 / FP16 storage),
- * segments per strip, rows per segment, threads per workgroup. */
+ * width, at most 250 columns), segments per strip, rows per segment,
+ * threads per workgroup. */
 lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
 
 /* ---------------------------------------------------------------- adjoint

@@ -94,11 +94,13 @@ __host__ __device__ inline int64_t pop_bytes(int P, int64_t Ns) {
 }
 
 // Plane k in 0..17: f_0..f_8 are k = 0..8, g_0..g_8 are k = 9..17.
-// FP64: all binary64. FP32: f binary32, g Q2.29 int32. FP16 storage: the
-// f_0 plane (binary16), the g_0 plane (Q2.29 int32), then for i = 1..8 one
-// plane of 32-bit words holding f_i (low half) and g_i (high half) of a node:
-// f_i and g_i always move together (same pull source), so one 32-bit access
-// serves both.
+// f_i and g_i always move together (same pull source), so the 32-bit and
+// 16-bit modes store them side by side and one access serves both:
+// FP64: 18 binary64 planes. FP32: for i = 0..8 one plane of 64-bit words
+// holding f_i (low word, binary32) and g_i (high word, Q2.29 int32). FP16
+// storage: the f_0 plane (binary16), the g_0 plane (Q2.29 int32), then for
+// i = 1..8 one plane of 32-bit words holding f_i (low half) and g_i (high
+// half), both binary16.
 // A plane's base address is uniform across the wavefront; the per-lane part
 // is a 32-bit byte offset (lattices are capped so that it cannot overflow),
 // which lets the compiler use scalar-base + 32-bit-offset addressing.
@@ -125,6 +127,11 @@ struct Pop {
   __device__ __forceinline__ static __half half_ld(const char* a) {
     return *reinterpret_cast<const __half*>(a);
   }
+  // FP32: address of the binary32 f_k (k < 9) or Q2.29 g_{k-9} word at idx
+  __device__ __forceinline__ char* word_at(int k, uint32_t idx) const {
+    const int i = k < 9 ? k : k - 9;
+    return base + (int64_t)i * 8 * Ns + idx * 8u + (k < 9 ? 0 : 4);
+  }
   __device__ __forceinline__ static int dir(int k) { return k < 9 ? k : k - 9; }
 
   // value of plane k at idx
@@ -132,8 +139,8 @@ struct Pop {
     if constexpr (P == P_F64) {
       return at<double>(base + k * Ns * 8, idx);
     } else if constexpr (P == P_F32) {
-      if (k < 9) return at<float>(base + k * Ns * 4, idx);
-      return float(at<int32_t>(base + k * Ns * 4, idx)) * GQI;
+      if (k < 9) return *reinterpret_cast<const float*>(word_at(k, idx));
+      return float(*reinterpret_cast<const int32_t*>(word_at(k, idx))) * GQI;
     } else {
       if (k == 9) return float(at<int32_t>(base + 2 * Ns, idx)) * GQI;
       return __half2float(half_ld(half_at(k, idx))) * H_INV(dir(k));
@@ -147,14 +154,14 @@ struct Pop {
       return at<double>(base + k * Ns * 8, idx);
     } else {
       if (k >= 9) return double(ld_q(k, idx)) * GQI_D;
-      if constexpr (P == P_F32) return double(at<float>(base + k * Ns * 4, idx));
+      if constexpr (P == P_F32) return double(*reinterpret_cast<const float*>(word_at(k, idx)));
       else return double(__half2float(half_ld(half_at(k, idx)))) * double(H_INV(k));
     }
   }
   // Q2.29 contribution of g plane k (9..17) at idx (fixed-point modes only)
   __device__ __forceinline__ int32_t ld_q(int k, uint32_t idx) const {
     if constexpr (P == P_F32) {
-      return at<int32_t>(base + k * Ns * 4, idx);
+      return *reinterpret_cast<const int32_t*>(word_at(k, idx));
     } else {
       if (k == 9) return at<int32_t>(base + 2 * Ns, idx);
       return __float2int_rn(__half2float(half_ld(half_at(k, idx))) * HQ(dir(k)));
@@ -168,11 +175,11 @@ struct Pop {
       return 0;
     } else if constexpr (P == P_F32) {
       if (k < 9) {
-        put<float>(base + k * Ns * 4, idx, v);
+        *reinterpret_cast<float*>(word_at(k, idx)) = v;
         return 0;
       }
       const int32_t q = __float2int_rn(v * GQ);
-      put<int32_t>(base + k * Ns * 4, idx, q);
+      *reinterpret_cast<int32_t*>(word_at(k, idx)) = q;
       return q;
     } else {
       if (k == 9) {
@@ -187,7 +194,7 @@ struct Pop {
   }
   // stores the Q2.29 word q into g_0 (fixed-point modes)
   __device__ __forceinline__ void st_g0_q(uint32_t idx, int32_t q) const {
-    if constexpr (P == P_F32) put<int32_t>(base + 9 * Ns * 4, idx, q);
+    if constexpr (P == P_F32) *reinterpret_cast<int32_t*>(word_at(9, idx)) = q;
     else if constexpr (P == P_F16) put<int32_t>(base + 2 * Ns, idx, q);
   }
 };

@@ -379,7 +379,9 @@ typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned in
 
 template <int P> struct BufT;
 template <> struct BufT<P_F64> { using F = double; using G0 = double; using GR = double; using R = double; };
-template <> struct BufT<P_F32> { using F = float; using G0 = int32_t; using GR = int32_t; using R = uint32_t; };
+// FP32: GR is the 64-bit word that holds f_i (low word, binary32) and g_i
+// (high word, Q2.29), i = 0..8.
+template <> struct BufT<P_F32> { using F = float; using G0 = int32_t; using GR = uint64_t; using R = uint64_t; };
 // FP16 storage: F is the f_0 plane's binary16; GR the 32-bit word that holds
 // f_i (low half) and g_i (high half), i >= 1.
 template <> struct BufT<P_F16> { using F = __half; using G0 = int32_t; using GR = uint32_t; using R = uint32_t; };
@@ -417,9 +419,13 @@ struct BufPop {
   using G0 = typename BufT<P>::G0;
   using GR = typename BufT<P>::GR;
   using R = typename BufT<P>::R;
+  // paired layouts: FP32 keeps (f_i, g_i) in one 64-bit word for i = 0..8,
+  // FP16 storage in one 32-bit word for i = 1..8
+  static constexpr bool PAIRED = P != P_F64;
+  static constexpr int G_FIRST = P == P_F32 ? 0 : 1;   // first direction of the g group
   __amdgpu_buffer_rsrc_t rf, rg0, rgr;
-  uint32_t pf, pg;     // plane strides (bytes) of the f and g_1..8 planes
-  char *fp, *gp;       // first f plane and g_1 plane
+  uint32_t pf, pg;     // plane strides (bytes) of the f and g (or pair) planes
+  char *fp, *gp;       // first f plane and first g (or pair) plane
 
   __device__ __forceinline__ void init(const Pop<P>& p) {
     const int64_t Ns = p.Ns;
@@ -429,6 +435,10 @@ struct BufPop {
       f = b;
       g0 = b + 2 * Ns;
       gr = b + 6 * Ns;
+    } else if constexpr (P == P_F32) {
+      f = b;
+      g0 = b;
+      gr = b;
     } else {
       f = b;
       g0 = b + 9 * Ns * (int64_t)sizeof(T);
@@ -442,7 +452,7 @@ struct BufPop {
     if constexpr (!BIG) {
       rf = __builtin_amdgcn_make_buffer_rsrc(f, 0, (int)((P == P_F16 ? 1 : 9) * (int64_t)pf),
                                              BUF_WORD3);
-      rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)(8 * (int64_t)pg), BUF_WORD3);
+      rgr = __builtin_amdgcn_make_buffer_rsrc(gr, 0, (int)((9 - G_FIRST) * (int64_t)pg), BUF_WORD3);
     }
   }
   template <typename S>
@@ -463,18 +473,18 @@ struct BufPop {
   }
   template <int I>
   __device__ __forceinline__ __amdgpu_buffer_rsrc_t g_rsrc() const {
-    if constexpr (BIG) return __builtin_amdgcn_make_buffer_rsrc(gp + (int64_t)(I - 1) * pg, 0, (int)pg, BUF_WORD3);
+    if constexpr (BIG) return __builtin_amdgcn_make_buffer_rsrc(gp + (int64_t)(I - G_FIRST) * pg, 0, (int)pg, BUF_WORD3);
     else return rgr;
   }
   template <int I>
   __device__ __forceinline__ uint32_t g_soff(uint32_t elem_row) const {
-    return (BIG ? 0u : (I - 1) * pg) + elem_row * (uint32_t)sizeof(GR);
+    return (BIG ? 0u : (I - G_FIRST) * pg) + elem_row * (uint32_t)sizeof(GR);
   }
   // raw word of f_I (G = false) or g_I (G = true) at element (row, col[dx+1])
   template <bool G, int I>
   __device__ __forceinline__ R ld(uint32_t elem_row, const uint32_t col[3], int dx) const {
-    if constexpr (P == P_F16 && I >= 1) {
-      // the pair word of direction I (f_I low half, g_I high half)
+    if constexpr (P == P_F32 || (P == P_F16 && I >= 1)) {
+      // the pair word of direction I (f_I low part, g_I high part)
       return buf_ld<GR>(g_rsrc<I>(), col[dx + 1] * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
     } else if constexpr (!G) {
       return raw(buf_ld<F>(f_rsrc<I>(), col[dx + 1] * (uint32_t)sizeof(F), f_soff<I>(elem_row)));
@@ -489,19 +499,21 @@ struct BufPop {
   template <int I>
   __device__ __forceinline__ static T val_f(R w) {
     if constexpr (P == P_F64) return w;
-    else if constexpr (P == P_F32) return __builtin_bit_cast(float, w);
+    else if constexpr (P == P_F32) return __builtin_bit_cast(float, (uint32_t)w);
     else return __half2float(__builtin_bit_cast(__half, (uint16_t)w)) * H_INV(I);
   }
   template <int I>
   __device__ __forceinline__ static T val_g(R w) {
     if constexpr (P == P_F64) return w;
-    else if constexpr (P == P_F32 || I == 0) return float((int32_t)w) * GQI;
+    else if constexpr (P == P_F32) return float((int32_t)(uint32_t)(w >> 32)) * GQI;
+    else if constexpr (I == 0) return float((int32_t)w) * GQI;
     else return __half2float(__builtin_bit_cast(__half, (uint16_t)(w >> 16))) * H_INV(I);
   }
   // Q2.29 contribution of a raw g word (fixed-point modes)
   template <int I>
   __device__ __forceinline__ static int32_t q_g(R w) {
-    if constexpr (P == P_F32 || I == 0) return (int32_t)w;
+    if constexpr (P == P_F32) return (int32_t)(uint32_t)(w >> 32);
+    else if constexpr (I == 0) return (int32_t)w;
     else return __float2int_rn(__half2float(__builtin_bit_cast(__half, (uint16_t)(w >> 16))) * HQ(I));
   }
   template <int I>
@@ -528,16 +540,27 @@ struct BufPop {
       return __float2int_rn(__half2float(h) * HQ(I));
     }
   }
-  // FP16 storage: stores f_I and g_I (I >= 1) as one word; returns the
-  // Q2.29 contribution of the stored g_I
+  // paired layouts: stores f_I and g_I as one word; returns the Q2.29
+  // contribution of the stored g_I (FP32: I = 1..8; FP16 storage: I >= 1)
   template <int I>
   __device__ __forceinline__ int32_t st_pair(T fv, T gv, uint32_t elem_row, uint32_t col) const {
+    if constexpr (P == P_F32) {
+      const int32_t q = __float2int_rn(gv * GQ);
+      st_pair_q<I>(fv, q, elem_row, col);
+      return q;
+    }
     const __half hf = __float2half_rn(fv * H_SCALE(I));
     const __half hg = __float2half_rn(gv * H_SCALE(I));
     const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, hf) |
                        ((uint32_t)__builtin_bit_cast(uint16_t, hg) << 16);
     buf_st<GR>(w, g_rsrc<I>(), col * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
     return __float2int_rn(__half2float(hg) * HQ(I));
+  }
+  // FP32: stores f_I and the Q2.29 word q of g_I as one 64-bit word
+  template <int I>
+  __device__ __forceinline__ void st_pair_q(T fv, int32_t q, uint32_t elem_row, uint32_t col) const {
+    const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, fv) | ((uint64_t)(uint32_t)q << 32);
+    buf_st<GR>(w, g_rsrc<I>(), col * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
   }
   __device__ __forceinline__ void st_g0(T v, int32_t q, uint32_t elem_row, uint32_t col) const {
     if constexpr (P == P_F64) buf_st<G0>(v, rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
@@ -656,6 +679,9 @@ __device__ __forceinline__ void store_row(const FusedCtx<P, BIG>& k, uint32_t ro
     k.out.template st_f<0>(f[0], row, k.col[1]);
     const int32_t rest = store_pairs<P, BIG>(k, row, f, gg);
     k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
+  } else if constexpr (P == P_F32) {
+    const int32_t rest = store_pairs<P, BIG>(k, row, f, gg);
+    k.out.template st_pair_q<0>(f[0], phi_q - rest, row, k.col[1]);
   } else {
     store_f<P, BIG>(k, row, f);
     const int32_t rest = store_g_rest<P, BIG>(k, row, gg);
@@ -703,7 +729,7 @@ __device__ __forceinline__ void unpack_row(const typename BufT<P>::R w[9],
                                            typename BufT<P>::R f0w, typename PrecT<P>::T f[9],
                                            typename PrecT<P>::T g[9]) {
   if constexpr (I < 9) {
-    f[I] = BufPop<P>::template val_f<I>(I == 0 ? f0w : w[I]);
+    f[I] = BufPop<P>::template val_f<I>((I == 0 && P == P_F16) ? f0w : w[I]);
     g[I] = BufPop<P>::template val_g<I>(w[I]);
     unpack_row<P, I + 1>(w, f0w, f, g);
   }
@@ -758,9 +784,10 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
                                            typename BufT<P>::R (&f0b)[4],
                                            FusedLds<typename PrecT<P>::T, NT>& L) {
   using T = typename PrecT<P>::T;
-  // FP16 storage loads f and g of a row together (paired words): the g ring
-  // then carries f too, and f0b the f_0 words; the f ring fb is unused
-  constexpr bool PAIR = P == P_F16;
+  // FP32 and FP16 storage load f and g of a row together (paired words): the
+  // g ring then carries f too (FP16 storage: f0b the f_0 words); the f ring
+  // fb is unused
+  constexpr bool PAIR = BufPop<P>::PAIRED;
   const Geom& g = k.g;
   const int lc = k.lc;
   // A: phi at row r (its g was loaded by the previous iteration)
@@ -851,7 +878,7 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   if (need_phi(k, r + k.d)) {
     const int y = phys_row(r + k.d, g);
     pull_row<P, BIG, true>(k, y, gb[(J + 1) & 3]);
-    if constexpr (PAIR) f0b[(J + 1) & 3] = pull_f0(k, y);
+    if constexpr (P == P_F16) f0b[(J + 1) & 3] = pull_f0(k, y);
   }
   if constexpr (!PAIR)
     if (need_p(k, r - k.d)) pull_row<P, BIG, false>(k, phys_row(r - k.d, g), fb[(J + 1) & 1]);
@@ -878,19 +905,19 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   }
 }
 
-// Occupancy the register allocation targets (waves per SIMD): 4 for the
-// 32-bit compute paths (<= 128 VGPRs), 2 for FP64.
-#ifndef QILBM_FUSED_WAVES32
-#define QILBM_FUSED_WAVES32 4
-#endif
-template <int P> struct FusedWaves { static constexpr int value = QILBM_FUSED_WAVES32; };
+// Occupancy the register allocation targets (waves per SIMD): 4 for FP16
+// storage (<= 128 VGPRs), 3 for FP32 (its 64-bit f/g words fill a larger
+// register ring; 4 would spill), 2 for FP64.
+template <int P> struct FusedWaves { static constexpr int value = 4; };
+template <> struct FusedWaves<P_F32> { static constexpr int value = 3; };
 template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
 
-// Lanes per workgroup: 8 wavefronts (strips of up to 506 columns) for FP32,
-// 4 (up to 250 columns) for FP64 and FP16 storage -- measured best on MI355X
-// at 2048 x 8192 (FP32 +4 % with 512 lanes; FP16 storage -10 %, FP64 -3 %).
+// Lanes per workgroup: 4 wavefronts (strips of up to 250 columns). Measured
+// on MI355X at 2048 x 8192: 8 wavefronts were 3 % and 10 % slower for FP64
+// and FP16 storage, and for FP32 with 64-bit words (its best, 31.8 GLUPS,
+// is 256 lanes at 3 waves per SIMD; 512 lanes, which fit only one
+// workgroup per CU at that register count, gave 28.7).
 template <int P> struct FusedThreads { static constexpr int value = 256; };
-template <> struct FusedThreads<P_F32> { static constexpr int value = 512; };
 
 template <int P, bool BIG, bool REC>
 __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
@@ -1051,7 +1078,7 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
 template <int P>
 bool fused_big(const Geom& g) {
   const int64_t f_group = (P == P_F16 ? 1 : 9) * g.Ns * (int64_t)sizeof(typename BufT<P>::F);
-  const int64_t g_group = 8 * g.Ns * (int64_t)sizeof(typename BufT<P>::GR);
+  const int64_t g_group = (P == P_F32 ? 9 : 8) * g.Ns * (int64_t)sizeof(typename BufT<P>::GR);
   return f_group > (int64_t)UINT32_MAX || g_group > (int64_t)UINT32_MAX;
 }
 

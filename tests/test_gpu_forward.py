@@ -354,7 +354,8 @@ def _q229_total(raw, precision, nx, ny):
     # 17 of 2 bytes + 1 of 4 (FP16 storage)
     Ns = raw.numel() // (72 if precision == "fp32" else 38)
     if precision == "fp32":
-        words = raw[9 * Ns * 4:18 * Ns * 4].view(torch.int32).view(9, Ns)[:, :N]
+        # nine planes of 64-bit words, g_i (Q2.29) in the high 32 bits
+        words = raw[:72 * Ns].view(torch.int32).view(9, Ns, 2)[:, :N, 1]
         return int(words.to(torch.int64).sum())
     # FP16 storage: f_0 plane (2 B), g_0 plane (Q2.29 int32), then for
     # i = 1..8 a plane of 32-bit words with g_i in the high half
@@ -420,9 +421,9 @@ def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol):
         lat = Lattice(pb.as_dict(), phi0, precision=precision, flags=flags, device=dev)
         per_node = {"fp64": 144, "fp32": 72, "fp16": 38}[precision]
         Ns = lat.state_bytes // per_node
-        # largest plane group: nine f planes (FP64, FP32) or the eight
-        # 32-bit f/g word planes (FP16 storage)
-        group = {"fp64": 9 * 8, "fp32": 9 * 4, "fp16": 8 * 4}[precision] * Ns
+        # largest plane group: nine f planes (FP64), the nine 64-bit f/g
+        # word planes (FP32) or the eight 32-bit ones (FP16 storage)
+        group = {"fp64": 9 * 8, "fp32": 9 * 8, "fp16": 8 * 4}[precision] * Ns
         # the per-plane addressing is in use at the large sizes only
         assert (group > 2**32 - 1) == (nx * ny > 10**7)
         if precision != "fp64":
