@@ -202,6 +202,94 @@ def precision_study(pb, phi0, steps: int, every: int):
                 t_star=round(steps * t_unit, 4), **out)
 
 
+def adjoint_study(warm: int, window: int, C: int, precision: str = "fp64", h: float = 1e-6):
+    """The 4096 x 8192 rising-bubble problem: ``warm`` forward steps, then
+    the gradient of L = sum_x y (1 - phi_K) (the bubble's height moment)
+    over the last ``window`` steps with respect to sigma and M (the state at
+    the window start held fixed), by checkpoint-and-recompute with a raw
+    checkpoint every ``C`` steps and C step records; timed against the
+    plain forward window, and checked against central differences of the
+    forward with relative step ``h`` (meaningful in FP64: in FP32 the
+    rounding of L exceeds the differences)."""
+    import torch
+    import workloads as wl
+    from paper_1507_03521_amd import Lattice
+    pb = wl.bubble4096()
+    dev = "cuda:0"
+    lat = Lattice(pb.as_dict(), wl.phi0(pb), precision=precision, device=dev)
+    t0 = time.perf_counter()
+    done = 0
+    while done < warm:
+        n = min(5000, warm - done)
+        lat.step(n)
+        done += n
+        torch.cuda.synchronize()
+        log(f"  warm-up step {done}/{warm}, {time.perf_counter() - t0:.0f} s")
+    start_raw = lat.save_raw().clone()
+    y = torch.arange(pb.ny, device=dev, dtype=torch.float64)[:, None].expand(pb.ny, pb.nx)
+
+    def loss_of(l):
+        return float((y * (1.0 - l.moments(("phi",))["phi"])).sum())
+
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    # forward window with checkpoints
+    torch.cuda.synchronize()
+    ev0.record(lat.stream)
+    snaps = []
+    for t in range(window):
+        if t % C == 0:
+            snaps.append(lat.save_raw())
+        lat.step(1)
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1)
+    L = loss_of(lat)
+    # backward: replay each segment with records, adjoint steps in reverse
+    records = [torch.empty(lat.record_bytes, dtype=torch.uint8, device=dev) for _ in range(C)]
+    lat.adjoint_begin((-y).contiguous())
+    torch.cuda.synchronize()
+    ev0.record(lat.stream)
+    for sgm in reversed(range(len(snaps))):
+        a, b = sgm * C, min(sgm * C + C, window)
+        lat.load_raw(snaps[sgm], warm + a)
+        for t in range(a, b):
+            lat.step_record(records[t - a])
+        for t in reversed(range(a, b)):
+            lat.adjoint_step_record(records[t - a])
+    ev1.record(lat.stream)
+    torch.cuda.synchronize()
+    bwd_ms = ev0.elapsed_time(ev1)
+    _, _, dsig, dM = lat.adjoint_get()
+    peak_gb = torch.cuda.max_memory_allocated() / 1e9
+    del snaps, records
+    torch.cuda.empty_cache()
+
+    def window_loss(sigma=pb.sigma, M=pb.M):
+        l2 = Lattice(pb.with_(sigma=sigma, M=M).as_dict(), wl.phi0(pb), precision=precision,
+                     device=dev)
+        l2.load_raw(start_raw, warm)
+        l2.step(window)
+        v = loss_of(l2)
+        l2.close()
+        return v
+
+    N = pb.nx * pb.ny
+    out = dict(study="adjoint", workload=f"{pb.name} {pb.nx}x{pb.ny} rising bubble",
+               precision=precision, warm_steps=warm, window=window, checkpoint=C,
+               loss=L, dL_dsigma=dsig, dL_dM=dM)
+    if h > 0:
+        fd_sig = (window_loss(sigma=pb.sigma * (1 + h))
+                  - window_loss(sigma=pb.sigma * (1 - h))) / (2 * h * pb.sigma)
+        fd_M = (window_loss(M=pb.M * (1 + h)) - window_loss(M=pb.M * (1 - h))) / (2 * h * pb.M)
+        out.update(fd_step=h, fd_dL_dsigma=fd_sig, fd_dL_dM=fd_M,
+                   rel_dev_sigma=abs(dsig - fd_sig) / abs(fd_sig),
+                   rel_dev_M=abs(dM - fd_M) / abs(fd_M))
+    return dict(out, forward_window_ms=round(fwd_ms, 1), backward_ms=round(bwd_ms, 1),
+                backward_over_forward=round(bwd_ms / fwd_ms, 3),
+                forward_mlups=round(N * window / (fwd_ms * 1e-3) / 1e6, 1),
+                peak_device_memory_gb=round(peak_gb, 1))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -220,6 +308,14 @@ def main():
                     help="instead of timing: run STEPS steps in each precision and print "
                          "tip positions, mass drift and deviation from FP64 (one JSON line)")
     ap.add_argument("--study-every", type=int, default=5000)
+    ap.add_argument("--adjoint-study", type=int, nargs=3, default=None,
+                    metavar=("WARM", "WINDOW", "C"),
+                    help="instead of timing: 4096x8192 bubble, WARM forward steps, then the "
+                         "sigma/M gradient over the last WINDOW steps with checkpoints every C "
+                         "(one JSON line)")
+    ap.add_argument("--study-precision", choices=["fp64", "fp32", "fp16"], default="fp64")
+    ap.add_argument("--fd-step", type=float, default=1e-4,
+                    help="relative central-difference step of the adjoint study (0: none)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on exactly one GPU; --gpus {args.gpus} is not supported "
@@ -232,6 +328,10 @@ def main():
     pb = wl.rt2048()
     phi0 = wl.phi0(pb)
     N = pb.nx * pb.ny
+    if args.adjoint_study:
+        print(json.dumps(adjoint_study(*args.adjoint_study, precision=args.study_precision,
+                                       h=args.fd_step)), flush=True)
+        return
     if args.precision_study:
         print(json.dumps(precision_study(pb, phi0, args.precision_study, args.study_every)),
               flush=True)
