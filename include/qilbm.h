@@ -199,6 +199,8 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  * lbm_adjoint_begin: binds the adjoint workspace and seeds the cotangent of
  *   the state at the final time: gbar_i = dL/dphi_K (all i), fbar = 0;
  *   clears the sigma/M accumulators. dL_dphi_dev: FP64 [ny][nx].
+ * lbm_adjoint_seed: the same seeding with the workspace already bound (for
+ *   another loss or another run with the same workspace).
  * lbm_adjoint_step: given the raw forward state s_t (layout of
  *   lbm_save_raw, storage precision of the context) replaces the cotangent
  *   of s_{t+1} by that of s_t = (d s_{t+1} / d s_t)^T applied to it, and
@@ -214,13 +216,14 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  *   Synchronises the stream.
  * The adjoint arithmetic runs in the compute type (FP64 for LBM_FP64,
  * FP32 otherwise); the parameter sums are FP64 and run-to-run reproducible.
- * lbm_adjoint_step, lbm_adjoint_step_record and lbm_adjoint_init return
- * LBM_ESTATE before lbm_adjoint_begin.
+ * lbm_adjoint_seed, lbm_adjoint_step, lbm_adjoint_step_record and
+ * lbm_adjoint_init return LBM_ESTATE before lbm_adjoint_begin.
  */
 size_t lbm_adjoint_workspace_bytes(const lbm_params* params);
 lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* adj_workspace_dev,
                              size_t adj_workspace_bytes,
                              const double* dL_dphi_dev);
+lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const double* dL_dphi_dev);
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state_dev);
 lbm_status lbm_adjoint_step_record(lbm_ctx* ctx, const void* record_dev);
 lbm_status lbm_adjoint_init(lbm_ctx* ctx, const double* phi0_dev, double* dL_dphi0_dev,

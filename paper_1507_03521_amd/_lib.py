@@ -47,6 +47,7 @@ SIGNATURES = {
     "lbm_launch_info": (c_int32, [c_void_p, POINTER(c_int32)]),
     "lbm_adjoint_workspace_bytes": (c_size_t, [_P]),
     "lbm_adjoint_begin": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),
+    "lbm_adjoint_seed": (c_int32, [c_void_p, c_void_p]),
     "lbm_adjoint_step": (c_int32, [c_void_p, c_void_p]),
     "lbm_adjoint_step_record": (c_int32, [c_void_p, c_void_p]),
     "lbm_adjoint_init": (c_int32, [c_void_p, c_void_p, c_void_p, _D]),

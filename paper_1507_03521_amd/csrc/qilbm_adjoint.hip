@@ -756,6 +756,15 @@ lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* ws, size_t bytes, const double*
   a.acc = (double*)(a.ws + L.acc);
   a.nred = L.nred;
   a.active = true;
+  return lbm_adjoint_seed(ctx, dL_dphi);
+}
+
+lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const double* dL_dphi) {
+  if (!ctx || !dL_dphi) return LBM_EINVAL;
+  CtxView v = ctx_view(ctx);
+  AdjointState& a = *v.adj;
+  if (!a.active) return LBM_ESTATE;
+  a.cur = 0;
   const Geom& g = v.geom;
   hipLaunchKernelGGL(k_fill_zero, dim3(a.nred), dim3(256), 0, v.stream, a.part,
                      (int64_t)a.nred * 4);

@@ -143,6 +143,11 @@ class Lattice:
         _lib.check(self.lib.lbm_adjoint_begin(self.ctx, _ptr(self._adj_ws), nbytes,
                                               _ptr(self._seed)), "lbm_adjoint_begin")
 
+    def adjoint_seed(self, dL_dphi: torch.Tensor) -> None:
+        """Re-seeds the adjoint (workspace from :meth:`adjoint_begin`)."""
+        self._seed = torch.as_tensor(dL_dphi, dtype=torch.float64).to(self.device).contiguous()
+        _lib.check(self.lib.lbm_adjoint_seed(self.ctx, _ptr(self._seed)), "lbm_adjoint_seed")
+
     def adjoint_step(self, fwd_raw: torch.Tensor) -> None:
         _lib.check(self.lib.lbm_adjoint_step(self.ctx, _ptr(fwd_raw)), "lbm_adjoint_step")
 

@@ -82,6 +82,10 @@ def test_null_context_calls(lib):
     assert lib.lbm_time(None) == -1
     assert lib.lbm_state_bytes(None) == 0
     assert lib.lbm_adjoint_step(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_adjoint_seed(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_adjoint_step_record(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_step_record(None, None) == _lib.LBM_EINVAL
+    assert lib.lbm_record_bytes(None) == 0
     lib.lbm_destroy(None)
     assert lib.lbm_strerror(_lib.LBM_EDIVERGED).decode().startswith("non-finite")
 

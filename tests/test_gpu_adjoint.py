@@ -253,3 +253,40 @@ def test_adjoint_step_from_record_matches_raw_state_path():
     (f0, g0, s0, m0), (f1, g1, s1, m1) = out
     assert _rel(f1, f0) <= 1e-13 and _rel(g1, g0) <= 1e-13
     assert s1 == pytest.approx(s0, rel=1e-12) and m1 == pytest.approx(m0, rel=1e-12)
+
+
+def test_adjoint_seed_reuses_the_workspace():
+    """lbm_adjoint_seed restarts the adjoint with the bound workspace: a
+    second loss after re-seeding gives bitwise the same cotangents and
+    parameter sums as a fresh lbm_adjoint_begin with that loss; before any
+    lbm_adjoint_begin it reports LBM_ESTATE."""
+    from paper_1507_03521_amd import QilbmError
+    nx, ny = 40, 33
+    pb = wl.droplet64().with_(nx=nx, ny=ny, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5)
+    f, g = wl.random_state(nx, ny, seed=12)
+    rng = np.random.default_rng(4)
+    s1 = torch.tensor(rng.standard_normal((ny, nx)), device="cuda:0")
+    s2 = torch.tensor(rng.standard_normal((ny, nx)), device="cuda:0")
+
+    def run(lat, seeds):
+        lat.set_state(f, g)
+        recs = [lat.step_record() for _ in range(3)]
+        out = None
+        for k, sd in enumerate(seeds):
+            if k == 0:
+                lat.adjoint_begin(sd)
+            else:
+                lat.adjoint_seed(sd)
+            for rec in reversed(recs):
+                lat.adjoint_step_record(rec)
+            out = lat.adjoint_get()
+        return out
+
+    lat = _lattice(pb, np.full((ny, nx), 0.5))
+    with pytest.raises(QilbmError) as err:
+        lat.adjoint_seed(s1)
+    assert err.value.status == -5
+    a = run(lat, [s1, s2])
+    b = run(_lattice(pb, np.full((ny, nx), 0.5)), [s2])
+    assert torch.equal(a[0], b[0]) and torch.equal(a[1], b[1])
+    assert a[2] == b[2] and a[3] == b[3]
