@@ -368,6 +368,38 @@ __device__ __forceinline__ void collide_T_at(const T* rec, const T* hat, int n, 
   collide_node_T(fd, gh, m, dpx, dpy, c, nb);
 }
 
+// The grad p cotangent of node n alone: the only output of the collision
+// transpose a ring node contributes. It comes from the G_i terms only, so
+// the f cotangents and grad p itself are not needed; same operations, same
+// order as in collide_node_T.
+template <typename T>
+__device__ __forceinline__ void gradp_cot_at(const T* rec, const T* hat, int n, const Coef<T>& c,
+                                             const Geom& g, T& bx, T& by) {
+  const NodeIdx k = node_idx(n, g);
+  T S, jx, jy, gmux, gmuy, lapmu;
+  Macro<T> m;
+  fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+  T gh[9];
+  post_hat9<T>(hat, 9, k, g.Ns, gh);
+  const T usq = m.ux * m.ux + m.uy * m.uy;
+  const T gpre = -T(3) * m.phi / m.rho;
+  T b_hx = 0, b_hy = 0;
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T w = T(WGT(i));
+    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
+    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
+    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T gm = T(1) + s;
+    const T b2 = gh[i] * c.kg;
+    const T bE = b2 * gpre * w * gm;
+    b_hx += bE * cxu;
+    b_hy += bE * cyu;
+  }
+  bx = b_hx;
+  by = b_hy;
+}
+
 // grad^T of the grad p cotangent at interior position (ly, lx), global row
 // y, from the tile in LDS (same terms, same order as stencil_T).
 template <typename T, int I>
@@ -480,13 +512,7 @@ __global__ __launch_bounds__(256) void k_adj_cm(const T* __restrict__ rec,
     if (t < K::NH) {
       int ly, lx, n;
       ring_pos<K::HX, K::HY>(t, ly, lx);
-      if (cm_node(x0, y0, ly, lx, g, n)) {
-        NodeBar<T> r;
-        T rd[9];
-        collide_T_at<T>(rec, hat, n, c, g, r, rd);
-        L.dpx[ly][lx] = r.dpx;
-        L.dpy[ly][lx] = r.dpy;
-      }
+      if (cm_node(x0, y0, ly, lx, g, n)) gradp_cot_at<T>(rec, hat, n, c, g, L.dpx[ly][lx], L.dpy[ly][lx]);
     }
     __syncthreads();
     // phase 2: full pressure cotangent and the macroscopic transposes
