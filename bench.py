@@ -122,9 +122,7 @@ def traffic_from_profile(n_nodes):
         return None
 
 
-def cpu_baseline(pb, phi0, rows: int, steps: int):
-    """The oracle as it stands, on a crop of the same workload (all columns,
-    the middle ``rows`` rows between walls), FP64, timed on the host."""
+def _oracle_rate(pb, phi0, rows: int, steps: int):
     import torch
     from oracle import qilbm_oracle as O
     y0 = pb.ny // 2 - rows // 2
@@ -138,10 +136,27 @@ def cpu_baseline(pb, phi0, rows: int, steps: int):
         for _ in range(steps):
             f, g = O.step(f, g, co)
         dt = time.perf_counter() - t0
-    return dict(value=round(sub.nx * rows * steps / dt / 1e6, 4), unit="MLUPS",
-                cores=torch.get_num_threads(), kind="oracle",
-                sample=f"{steps} FP64 steps of a {sub.nx}x{rows} crop (middle rows, walls) "
-                       f"of the {pb.nx}x{pb.ny} Rayleigh-Taylor lattice, {dt:.1f} s")
+    return sub.nx * rows * steps / dt / 1e6, dt
+
+
+def cpu_baseline(pb, phi0, rows: int, steps: int):
+    """The oracle as it stands, on a crop of the same workload (all columns,
+    the middle ``rows`` rows between walls), FP64, timed on the host with all
+    torch threads, and on a smaller crop with one thread."""
+    import torch
+    cores = torch.get_num_threads()
+    rate, dt = _oracle_rate(pb, phi0, rows, steps)
+    torch.set_num_threads(1)
+    try:
+        rate1, dt1 = _oracle_rate(pb, phi0, max(rows // 8, 8), 2)
+    finally:
+        torch.set_num_threads(cores)
+    return dict(value=round(rate, 4), unit="MLUPS", cores=cores, kind="oracle",
+                sample=f"{steps} FP64 steps of a {pb.nx}x{rows} crop (middle rows, walls) "
+                       f"of the {pb.nx}x{pb.ny} Rayleigh-Taylor lattice, {dt:.1f} s",
+                single_thread=dict(value=round(rate1, 4), unit="MLUPS", cores=1,
+                                   sample=f"2 FP64 steps of a {pb.nx}x{max(rows // 8, 8)} crop, "
+                                          f"{dt1:.1f} s"))
 
 
 def interface_tips(phi, nx):
@@ -294,7 +309,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=1000)
-    ap.add_argument("--warmup", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--only", choices=["fp32", "fp64", "fp16"], default=None,
                     help="time one precision only (for profiler runs)")
