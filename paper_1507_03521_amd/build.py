@@ -46,7 +46,23 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     _run([HIPCC, "-shared", f"--offload-arch={ARCH}", "-o", tmp, *objs])
     os.replace(tmp, LIB)
+    build_c_example(objdir)
     return LIB
+
+
+C_EXAMPLE_SRC = os.path.join(os.path.dirname(HERE), "tests", "c", "abi_example.c")
+C_EXAMPLE = os.path.join(HERE, "_build", "abi_example")
+
+
+def build_c_example(objdir: str) -> str:
+    """A plain C11 program that uses the library through include/qilbm.h
+    only (host compiler, HIP runtime API for device memory)."""
+    rocm = os.path.dirname(os.path.dirname(os.path.realpath(HIPCC)))
+    _run(["gcc", "-std=c11", "-O2", "-Wall", "-D__HIP_PLATFORM_AMD__",
+          f"-I{rocm}/include", f"-I{os.path.join(os.path.dirname(HERE), 'include')}",
+          C_EXAMPLE_SRC, "-o", C_EXAMPLE, f"-L{HERE}", "-lqilbm", f"-L{rocm}/lib",
+          "-lamdhip64", "-lm", f"-Wl,-rpath,{rocm}/lib", "-Wl,-rpath,$ORIGIN/.."])
+    return C_EXAMPLE
 
 
 if __name__ == "__main__":
