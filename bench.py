@@ -99,8 +99,15 @@ def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
     torch.cuda.synchronize()
     rec_ms = start.elapsed_time(stop) / nadj
     del lat
+    # algorithmic bytes of one adjoint step per node: the record (phi, mu, p,
+    # S, jx, jy) read, the 18 population cotangents read and written
+    tb = 8 if precision == "fp64" else 4
+    alg = (6 + 18 + 18) * tb
+    n = pb.nx * pb.ny
     return dict(adjoint_ms_per_step=round(adj_ms, 4), ratio=round(adj_ms / fwd_ms, 3),
-                ratio_with_recompute=round((adj_ms + rec_ms) / fwd_ms, 3), precision=precision)
+                ratio_with_recompute=round((adj_ms + rec_ms) / fwd_ms, 3), precision=precision,
+                alg_bytes_per_lu=alg,
+                hbm_roofline_frac=round(alg * n / (adj_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4))
 
 
 def traffic_from_profile(n_nodes):
