@@ -225,10 +225,13 @@ def test_step_record_matches_step_and_oracle(precision, flags):
         assert _rel(planes[k], m[name]) <= tol, name
 
 
-def test_adjoint_step_from_record_matches_raw_state_path():
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-4), ("fp16", 1e-4)])
+def test_adjoint_step_from_record_matches_raw_state_path(precision, tol):
     """One adjoint step from a record (lbm_step_record) equals the step from
     the raw state (lbm_adjoint_step, which recomputes the record with the
-    unfused kernels): FP64 cotangents within 1e-13, sigma/M within 1e-12."""
+    unfused kernels): the two records differ only by the rounding of two
+    evaluation orders, so FP64 cotangents agree within 1e-13 (sigma/M 1e-12)
+    and FP32-arithmetic ones within 1e-4."""
     from paper_1507_03521_amd import Lattice
     nx, ny = 300, 41
     pb = wl.droplet64().with_(nx=nx, ny=ny, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5)
@@ -239,7 +242,7 @@ def test_adjoint_step_from_record_matches_raw_state_path():
     zero = torch.zeros((ny, nx), dtype=torch.float64, device="cuda:0")
     out = []
     for use_record in (False, True):
-        lat = _lattice(pb, np.full((ny, nx), 0.5))
+        lat = _lattice(pb, np.full((ny, nx), 0.5), precision=precision)
         lat.set_state(f, g)
         raw = lat.save_raw().clone()
         rec = lat.step_record()
@@ -251,8 +254,8 @@ def test_adjoint_step_from_record_matches_raw_state_path():
             lat.adjoint_step(raw)
         out.append(lat.adjoint_get())
     (f0, g0, s0, m0), (f1, g1, s1, m1) = out
-    assert _rel(f1, f0) <= 1e-13 and _rel(g1, g0) <= 1e-13
-    assert s1 == pytest.approx(s0, rel=1e-12) and m1 == pytest.approx(m0, rel=1e-12)
+    assert _rel(f1, f0) <= tol and _rel(g1, g0) <= tol
+    assert s1 == pytest.approx(s0, rel=10 * tol) and m1 == pytest.approx(m0, rel=10 * tol)
 
 
 def test_adjoint_seed_reuses_the_workspace():
