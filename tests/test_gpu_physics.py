@@ -171,3 +171,29 @@ def test_phase_separation_quasi_vs_incompressible_form():
         var[no_gamma] = float(lat.moments(("phi",))["phi"].var())
     print("phi variance after 1000 steps: quasi", var[False], "incompressible form", var[True], flush=True)
     assert var[False] > 1.05 * var[True]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_static_droplet_64_laplace_mass_spurious_velocity(precision):
+    """The 64x64 static droplet (R = 16, W = 4, sigma = 0.01, rho 1 / 0.1,
+    M = 0.1, tau = 0.8) after 2000 steps on the GPU: total phi conserved
+    (FP64 to 1e-12 relative, FP32 exactly in fixed point), the Laplace
+    pressure jump within 5 % of sigma / R (Sec. IV.B; R from the droplet
+    area, averaged over the last third of the run) and the largest spurious
+    velocity reported (bounded by 1e-3 lattice units)."""
+    pb = wl.droplet64()
+    lat = _lattice(pb, wl.phi0(pb), precision=precision)
+    m0 = lat.mass()
+    R, dP = _laplace_jump(lat, pb, pb.steps, every=100)
+    m1 = lat.mass()
+    mo = lat.moments(("ux", "uy"))
+    umax = float(torch.sqrt(mo["ux"] ** 2 + mo["uy"] ** 2).max())
+    print(f"{precision}: R {R:.3f}, dP {dP:.4e} vs sigma/R {pb.sigma / R:.4e} "
+          f"({dP * R / pb.sigma - 1:+.2%}), max |u| {umax:.2e}, "
+          f"mass drift {abs(m1[0] - m0[0]) / m0[0]:.1e}", flush=True)
+    if precision == "fp64":
+        assert abs(m1[0] - m0[0]) <= 1e-12 * abs(m0[0])
+    else:
+        assert m1[0] == m0[0]
+    assert dP == pytest.approx(pb.sigma / R, rel=0.05)
+    assert umax <= 1e-3
