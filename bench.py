@@ -4,7 +4,8 @@ Workload: the 2048 x 8192 Rayleigh-Taylor problem between bounce-back walls
 (Atwood 0.5, Re 3000, Pe 1000, W 4), synthetic initial interface, no
 datasets. A step is one coupled f+g update of the whole lattice (moments,
 chemical potential, gradients, force, velocity, pressure, both collisions,
-streaming) -- one launch of the fused kernel.
+streaming). FP32 runs two steps per launch of the fused kernel (the state
+between them stays on chip); FP64 and FP16 storage one step per launch.
 
 Printed: ONE JSON line. ``value`` is the FP32 rate in MLUPS (million lattice
 updates per second); the line also carries the FP64 and FP16-storage rates
@@ -26,7 +27,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (coupled f+g) FP64 vs FP32 at stated error; adjoint/forward step ratio"
 PEAK_HBM_GBS = 8000.0
 BYTES_PER_LU = {"fp64": 288, "fp32": 144, "fp16": 76}
-PROFILE_TRAFFIC = os.path.join(ROOT, "profiles", "fused_step_rt2048_fp32_pmc.txt")
+PROFILE_TRAFFIC = {1: os.path.join(ROOT, "profiles", "fused_step_rt2048_fp32_pmc.txt"),
+                   2: os.path.join(ROOT, "profiles", "fused_step2_rt2048_fp32_pmc.txt")}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_1507_03521_amd", "csrc", f)
                   for f in ("qilbm_kernels.hip", "qilbm_device.hpp")]
 
@@ -54,19 +56,21 @@ def timed_steps(lat, steps: int, warmup: int):
     lat.step(steps)
     stop.record(lat.stream)
     torch.cuda.synchronize()
-    return start.elapsed_time(stop) / steps          # ms per step (= per fused launch)
+    return start.elapsed_time(stop) / steps          # ms per step
 
 
-def run_precision(pb, phi0, precision, steps, warmup, seg_rows):
+def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
     from paper_1507_03521_amd import Lattice
     lat = Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0")
-    if seg_rows:
+    if pass_steps:
+        lat.set_pass(pass_steps, seg_rows if pass_steps == 2 else 0)
+    if seg_rows and lat.pass_info()["steps"] == 1:
         lat.set_launch(seg_rows)
     m0 = lat.mass()
     ms = timed_steps(lat, steps, warmup)
     m1 = lat.mass()
     phi = lat.moments(("phi",))["phi"]
-    info = lat.launch_info()
+    info = lat.pass_info()
     del lat
     return ms, phi, m0, m1, info
 
@@ -110,13 +114,15 @@ def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
                 hbm_roofline_frac=round(alg * n / (adj_ms * 1e-3) / 1e9 / PEAK_HBM_GBS, 4))
 
 
-def traffic_from_profile(n_nodes):
-    """HBM bytes per fused launch from the committed PMC summary, if it was
-    taken on the current kernel source; else None."""
-    if not os.path.exists(PROFILE_TRAFFIC):
+def traffic_from_profile(pass_steps):
+    """HBM bytes per launch of the fused kernel (one or two steps per pass)
+    from the committed PMC summary, if it was taken on the current kernel
+    source; else None."""
+    path = PROFILE_TRAFFIC[pass_steps]
+    if not os.path.exists(path):
         return None
     kv = {}
-    with open(PROFILE_TRAFFIC) as fh:
+    with open(path) as fh:
         for line in fh:
             if "=" in line and not line.startswith("#"):
                 k, v = line.split("=", 1)
@@ -318,6 +324,9 @@ def main():
     ap.add_argument("--steps", type=int, default=1000)
     ap.add_argument("--warmup", type=int, default=100)
     ap.add_argument("--seg-rows", type=int, default=0)
+    ap.add_argument("--pass-steps", type=int, choices=[1, 2], default=0,
+                    help="time steps per fused launch (default: the library's choice per "
+                         "precision: 2 for fp32, 1 otherwise)")
     ap.add_argument("--only", choices=["fp32", "fp64", "fp16"], default=None,
                     help="time one precision only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -371,13 +380,15 @@ def main():
     for prec in precisions:
         log(f"timing {prec}: {args.steps} steps after {args.warmup} warm-up")
         ms, phi, m0, m1, info = run_precision(pb, phi0, prec, args.steps, args.warmup,
-                                              args.seg_rows)
+                                              args.seg_rows,
+                                              args.pass_steps if prec != "fp64" else 0)
         res[prec] = dict(ms=ms, phi=phi, m0=m0, m1=m1, info=info)
         log(f"  {prec}: {ms:.4f} ms/step, {N / ms / 1e3:.1f} MLUPS, launch {info}")
 
     def entry(prec):
         r = res[prec]
         out = dict(mlups=round(N / r["ms"] / 1e3, 2), ms_per_step=round(r["ms"], 5),
+                   steps_per_launch=r["info"]["steps"],
                    hbm_roofline_frac=round(BYTES_PER_LU[prec] * N / (r["ms"] * 1e-3) / 1e9
                                            / PEAK_HBM_GBS, 4),
                    mass_drift_rel=abs(r["m1"][1] - r["m0"][1]) / abs(r["m0"][1]))
@@ -387,9 +398,14 @@ def main():
 
     main_prec = args.only or "fp32"
     ms = res[main_prec]["ms"]
-    alg_bytes = BYTES_PER_LU[main_prec] * N
-    achieved = alg_bytes / (ms * 1e-3) / 1e9
-    traffic = traffic_from_profile(N) if main_prec == "fp32" else None
+    # per launch of the fused kernel: it advances the lattice by `per` steps;
+    # algorithmic bytes = B/LU x nodes x steps (what `per` one-step launches
+    # would move), over the launch's average duration
+    per = res[main_prec]["info"]["steps"]
+    alg_bytes = BYTES_PER_LU[main_prec] * N * per
+    achieved = alg_bytes / (ms * per * 1e-3) / 1e9
+    traffic = traffic_from_profile(per) if main_prec == "fp32" else None
+    kname = "k_step2_fused" if per == 2 else "k_step_fused"
     line = {
         "metric": METRIC,
         "value": round(N / ms / 1e3, 2),
@@ -407,11 +423,15 @@ def main():
                                "Re 3000, Pe 1000, W 4",
                    "nx": pb.nx, "ny": pb.ny, "precision": main_prec,
                    "launch": res[main_prec]["info"]},
-        "roofline": {"bound": "hbm", "kernel": f"k_step_fused<{main_prec}>",
+        "roofline": {"bound": "hbm", "kernel": f"{kname}<{main_prec}>",
                      "achieved": round(achieved, 1), "peak": PEAK_HBM_GBS, "unit": "GB/s",
                      "frac": round(achieved / PEAK_HBM_GBS, 4),
+                     "steps_per_launch": per,
+                     "ms_per_launch": round(ms * per, 5),
                      "alg_bytes_per_launch": alg_bytes,
-                     "traffic": None if traffic is None else round(traffic, 0)},
+                     "traffic": None if traffic is None else round(traffic, 0),
+                     "moved_gbps": None if traffic is None
+                     else round(traffic / (ms * per * 1e-3) / 1e9, 1)},
     }
     for prec in res:
         line[{"fp64": "fp64", "fp32": "fp32", "fp16": "fp16_store"}[prec]] = entry(prec)

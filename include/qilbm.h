@@ -123,7 +123,13 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params,
 
 /* Advances nsteps >= 0 coupled time steps (Sec. III: moments, chemical
  * potential, force, velocity, pressure, both BGK collisions with their
- * source terms, streaming). Asynchronous. */
+ * source terms, streaming). Asynchronous. Every kernel launch reads one of
+ * the context's two population buffers and writes the other, and the
+ * context then switches to the other buffer (host-side state). A caller
+ * that captures lbm_step in a HIP graph for repeated replay must capture an
+ * even number of launches, so that each replay starts from the buffer the
+ * previous one ended in: with one step per launch an even nsteps, with two
+ * steps per launch (lbm_set_pass) a multiple of 4. */
 lbm_status lbm_step(lbm_ctx* ctx, int64_t nsteps);
 
 /* Macroscopic fields at the current time t (Sec. III moments): phi, rho,
@@ -176,15 +182,37 @@ int64_t lbm_time(const lbm_ctx* ctx);
 /* Rebinds the context to another HIP stream. */
 lbm_status lbm_set_stream(lbm_ctx* ctx, void* stream);
 
-/* Launch shape of the fused step kernel: rows per workgroup segment
+/* Launch shape of the one-step fused kernel: rows per workgroup segment
  * (0 = automatic: about 2.25 workgroups per resident slot, 16..32 rows).
  * Results do not depend on it. */
 lbm_status lbm_set_launch(lbm_ctx* ctx, int32_t seg_rows);
 
-/* Current fused launch shape into out[4] (host): column strips (of equal
- * width, at most 250 columns), segments per strip, rows per segment,
- * threads per workgroup. */
+/* Current one-step fused launch shape into out[4] (host): column strips (of
+ * equal width, at most 250 columns), segments per strip, rows per segment,
+ * threads per workgroup. lbm_step_record always uses this kernel. */
 lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
+
+/* Time steps per pass of the fused kernel in lbm_step (temporal blocking,
+ * an implementation choice; the scheme is Sec. III's step applied twice).
+ * steps = 2 (the default for LBM_FP32; available for LBM_FP16_STORE)
+ * advances the lattice by two steps per launch: the first step's
+ * post-collision words stay in on-chip memory and feed the second step, so
+ * the populations cross HBM once per two steps; an odd last step of an
+ * lbm_step call runs alone. The intermediate state is kept in the storage
+ * format, so results agree with steps = 1 (one launch per step) to
+ * rounding: the two kernels evaluate the same expressions, but the compiler
+ * may fuse multiply-adds differently in each. The exact integer invariant
+ * of the stored g holds in both. seg_rows: rows per workgroup
+ * segment of the two-step kernel (0 = automatic: one round of workgroups).
+ * LBM_EINVAL for steps other than 1 and 2, steps = 2 with LBM_FP64, or
+ * seg_rows < 0. Applies to lbm_step only (not lbm_step_record, not
+ * LBM_FLAG_UNFUSED). */
+lbm_status lbm_set_pass(lbm_ctx* ctx, int32_t steps, int32_t seg_rows);
+
+/* Shape of the kernel lbm_step launches for a pair of steps, into out[5]
+ * (host): steps per pass, column strips (at most 242 columns for two steps),
+ * segments per strip, rows per segment, threads per workgroup. */
+lbm_status lbm_pass_info(const lbm_ctx* ctx, int32_t out[5]);
 
 /* ---------------------------------------------------------------- adjoint
  * Reverse-mode derivative of a loss L(phi_K) of the final order parameter

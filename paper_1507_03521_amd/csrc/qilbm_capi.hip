@@ -27,6 +27,9 @@ struct lbm_ctx {
   int64_t t;
   int seg_rows;
   int resident;       // fused workgroups resident at once on this device
+  int pass_steps;     // time steps per pass of the fused kernel (1 or 2)
+  int pass_seg_rows;  // rows per segment of the two-step kernel (0: automatic)
+  int resident2;      // two-step workgroups resident at once
   int64_t pbytes;
   AdjointState adj;
 };
@@ -139,6 +142,17 @@ lbm_status step_p(lbm_ctx* c, int64_t n, void* rec) {
   const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
   const FusedShape sh = fused_shape<P>(c->geom, c->seg_rows, c->resident);
   const int64_t pl = c->geom.Ns;
+  if (!unfused && !rec && c->pass_steps == 2) {
+    // pairs of steps in one pass each; an odd last step runs alone
+    const FusedShape sh2 = fused2_shape<P>(c->geom, c->pass_seg_rows, c->resident2);
+    for (; n >= 2; n -= 2) {
+      if (launch_step2_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh2, c->stream) !=
+          hipSuccess)
+        return LBM_EDEVICE;
+      c->cur ^= 1;
+      c->t += 2;
+    }
+  }
   for (int64_t s = 0; s < n; ++s) {
     hipError_t e;
     if (unfused && rec)
@@ -228,6 +242,12 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
   c->t = 0;
   c->seg_rows = 0;
   c->resident = QILBM_DISPATCH(params->precision, fused_resident);
+  // two steps per pass where it is the faster kernel (FP32); FP16 storage
+  // keeps one (its two-step kernel measured slower: the binary16
+  // conversions of the intermediate state make it arithmetic-bound)
+  c->pass_steps = params->precision == LBM_FP32 ? 2 : 1;
+  c->pass_seg_rows = 0;
+  c->resident2 = QILBM_DISPATCH(params->precision, fused2_resident);
   c->pbytes = pop_bytes(params->precision, c->geom.Ns);
   Coef<double> k = coef_t<double>(c);
   // both population buffers start zeroed, padding included, so that raw
@@ -336,6 +356,35 @@ lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
   out[1] = sh.nseg;
   out[2] = sh.seg_rows;
   out[3] = sh.threads;
+  return LBM_OK;
+}
+
+lbm_status lbm_set_pass(lbm_ctx* c, int32_t steps, int32_t seg_rows) {
+  if (!c || seg_rows < 0 || (steps != 1 && steps != 2)) return LBM_EINVAL;
+  if (steps == 2 && c->prm.precision == LBM_FP64) return LBM_EINVAL;
+  c->pass_steps = steps;
+  c->pass_seg_rows = seg_rows;
+  return LBM_OK;
+}
+
+lbm_status lbm_pass_info(const lbm_ctx* c, int32_t out[5]) {
+  if (!c || !out) return LBM_EINVAL;
+  FusedShape sh;
+  if (c->pass_steps == 2)
+    sh = c->prm.precision == LBM_FP32
+             ? fused2_shape<P_F32>(c->geom, c->pass_seg_rows, c->resident2)
+             : fused2_shape<P_F16>(c->geom, c->pass_seg_rows, c->resident2);
+  else
+    sh = c->prm.precision == LBM_FP64
+             ? fused_shape<P_F64>(c->geom, c->seg_rows, c->resident)
+             : (c->prm.precision == LBM_FP32
+                    ? fused_shape<P_F32>(c->geom, c->seg_rows, c->resident)
+                    : fused_shape<P_F16>(c->geom, c->seg_rows, c->resident));
+  out[0] = c->pass_steps;
+  out[1] = sh.nstrips;
+  out[2] = sh.nseg;
+  out[3] = sh.seg_rows;
+  out[4] = sh.threads;
   return LBM_OK;
 }
 

@@ -972,6 +972,340 @@ __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void 
   }
 }
 
+// --------------------------------------------- fused kernel, two steps a pass
+// The pipeline above run twice within one sweep, so that a pass over the
+// populations advances the lattice by two time steps. The first step's
+// stages (A1..D1) load the populations from memory as above, but its
+// collision puts the post-collision words into a three-row ring in LDS
+// instead of memory; the second step's stages (A2..D2) pull from that ring
+// and store to memory. The state between the two steps never leaves the
+// chip: per two steps the populations are read once and written once. The
+// ring holds exactly the storage words a single step would have written
+// (binary32 f with Q2.29 g and the exact g_0 closure, or the binary16
+// pairs), so a pass computes what two single steps compute.
+//
+// Halo: the second collision at the owned columns needs the first step's
+// output 4 columns (and rows) beyond them (its own stencils reach 3, the
+// pull 1 more), and that output needs 3 more columns of the first step's
+// stencils: FH2 = 7 halo columns per side and 7 warm-up rows per segment
+// end. Stage s (A1 = 0, B1 = 1, ..., D1 = 3, A2 = 4, ..., D2 = 7) runs on
+// lanes [s, wi + 14 - s) and rows [y0 - 7 + s, y1 + 7 - s).
+//
+// Iteration with A1 at row r (direction d), a barrier after each phase:
+//   A: A1 phi(r) from the loaded words; A2 phi(r - 5d) from the words pulled
+//      out of the ring (rows r - 6d .. r - 4d, put there by D1 in the three
+//      previous iterations)
+//   B: mu of rows r - d and r - 6d
+//   C: force, velocity and pressure of rows r - 2d and r - 7d
+//   D: D1 collides row r - 3d into the ring slot of row r - 6d (consumed in
+//      A) and loads the words of row r + d; D2 collides row r - 8d and stores
+//      it.
+// The fourth barrier lets every LDS ring be four rows deep (three for the
+// ring of words) and D read phi and mu of its row straight from the rings.
+constexpr int FH2 = 7;
+
+template <typename T, int NT>
+struct StageRings {
+  T phi[4][NT];
+  T mu[4][NT];
+  T p[4][NT];
+};
+
+// Storage words of three rows of the first step's output, direction-major.
+template <int P, int NT> struct MidRing;
+template <int NT> struct MidRing<P_F32, NT> {
+  uint64_t w[3][9][NT];    // f_i (low word) and the Q2.29 g_i (high word)
+};
+template <int NT> struct MidRing<P_F16, NT> {
+  uint32_t w[3][9][NT];    // [0]: Q2.29 g_0; [i >= 1]: f_i low half, g_i high half
+  uint16_t f0[3][NT];      // binary16 f_0
+};
+
+template <int P, int NT>
+struct Fused2Lds {
+  StageRings<typename PrecT<P>::T, NT> s1, s2;
+  MidRing<P, NT> mid;
+};
+
+template <int P, bool BIG>
+__device__ __forceinline__ bool in_stage(const FusedCtx<P, BIG>& k, int v, int s) {
+  return k.act && k.lc >= s && k.lc < k.wi + 2 * FH2 - s && v >= k.y0 - FH2 + s &&
+         v < k.y1 + FH2 - s && row_ok(v, k.g);
+}
+
+// Storage words of a node's post-collision populations: what store_row
+// writes, g_0 closing the node's Q2.29 sum at phi_q.
+template <int P>
+__device__ __forceinline__ void pack_row(const typename PrecT<P>::T f[9],
+                                         const typename PrecT<P>::T gg[9], int32_t phi_q,
+                                         typename BufT<P>::R w[9], typename BufT<P>::R& f0w) {
+  int32_t rest = 0;
+  if constexpr (P == P_F32) {
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const int32_t q = __float2int_rn(gg[i] * GQ);
+      rest += q;
+      w[i] = (uint64_t)__builtin_bit_cast(uint32_t, f[i]) | ((uint64_t)(uint32_t)q << 32);
+    }
+    w[0] = (uint64_t)__builtin_bit_cast(uint32_t, f[0]) |
+           ((uint64_t)(uint32_t)(phi_q - rest) << 32);
+    f0w = 0;
+  } else {
+    f0w = (uint32_t)__builtin_bit_cast(uint16_t, __float2half_rn(f[0] * H_SCALE(0)));
+#pragma unroll
+    for (int i = 1; i < 9; ++i) {
+      const __half hf = __float2half_rn(f[i] * H_SCALE(i));
+      const __half hg = __float2half_rn(gg[i] * H_SCALE(i));
+      rest += __float2int_rn(__half2float(hg) * HQ(i));
+      w[i] = (uint32_t)__builtin_bit_cast(uint16_t, hf) |
+             ((uint32_t)__builtin_bit_cast(uint16_t, hg) << 16);
+    }
+    w[0] = (uint32_t)(phi_q - rest);
+  }
+}
+
+// Stores packed words of one node at (row, own column).
+template <int P, bool BIG, int I = 0>
+__device__ __forceinline__ void store_words(const FusedCtx<P, BIG>& k, uint32_t row,
+                                            const typename BufT<P>::R w[9],
+                                            typename BufT<P>::R f0w) {
+  using GR = typename BufT<P>::GR;
+  if constexpr (I < 9) {
+    const uint32_t col = k.col[1];
+    if constexpr (P == P_F16 && I == 0) {
+      buf_st<__half>(__builtin_bit_cast(__half, (uint16_t)f0w), k.out.template f_rsrc<0>(),
+                     col * 2u, k.out.template f_soff<0>(row));
+      buf_st<int32_t>((int32_t)w[0], k.out.rg0, col * 4u, row * 4u);
+    } else {
+      buf_st<GR>(w[I], k.out.template g_rsrc<I>(), col * (uint32_t)sizeof(GR),
+                 k.out.template g_soff<I>(row));
+    }
+    store_words<P, BIG, I + 1>(k, row, w, f0w);
+  }
+}
+
+// Pulls row v's words out of the ring: sl[1 + dy] is the slot of row v + dy.
+// WALL as in pull_row_dirs.
+template <int P, int NT, int WALL, int I = 0>
+__device__ __forceinline__ void pull_mid_dirs(const MidRing<P, NT>& M, const int sl[3], int lc,
+                                              typename BufT<P>::R v[9]) {
+  if constexpr (I < 9) {
+    constexpr int cx = CXS(I), cy = CYS(I);
+    if constexpr ((WALL == -1 && cy == 1) || (WALL == 1 && cy == -1))
+      v[I] = M.w[sl[1]][OPP(I)][lc];
+    else
+      v[I] = M.w[sl[1 - cy]][I][lc - cx];
+    pull_mid_dirs<P, NT, WALL, I + 1>(M, sl, lc, v);
+  }
+}
+
+template <int P, int NT>
+__device__ __forceinline__ void pull_mid(const MidRing<P, NT>& M, const int sl[3], int v,
+                                         const Geom& g, int lc, typename BufT<P>::R w[9],
+                                         typename BufT<P>::R& f0w) {
+  if (g.walls && v == 0)
+    pull_mid_dirs<P, NT, -1>(M, sl, lc, w);
+  else if (g.walls && v == g.ny - 1)
+    pull_mid_dirs<P, NT, 1>(M, sl, lc, w);
+  else
+    pull_mid_dirs<P, NT, 0>(M, sl, lc, w);
+  if constexpr (P == P_F16) f0w = M.f0[sl[1]][lc];
+}
+
+// Stage B of one pipeline: mu at row b.
+template <typename T, int NT>
+__device__ __forceinline__ void stage_mu(StageRings<T, NT>& S, int b, const Geom& g, int lc,
+                                         const Coef<T>& c) {
+  T v[3][3], gx, gy, lap;
+  lds3x3<T, NT>(S.phi, 3, b, g.ny, g.walls, lc, v);
+  stencil(v, gx, gy, lap);
+  S.mu[b & 3][lc] = mu_bulk(v[1][1], c) - c.kappa * lap;
+}
+
+// Stage C of one pipeline: force, velocity and pressure at row q from its
+// pulled words; p into the ring, the rest into nd.
+template <int P, int NT>
+__device__ __forceinline__ void stage_macro(StageRings<typename PrecT<P>::T, NT>& S,
+                                            const typename BufT<P>::R w[9],
+                                            typename BufT<P>::R f0w, int q, const Geom& g, int lc,
+                                            const Coef<typename PrecT<P>::T>& c,
+                                            typename PrecT<P>::T nd[NM]) {
+  using T = typename PrecT<P>::T;
+  T fv[9], gv[9];
+  unpack_row<P>(w, f0w, fv, gv);
+  T Sm, jx, jy;
+  moments9(fv, Sm, jx, jy);
+  T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
+  lds3x3<T, NT>(S.phi, 3, q, g.ny, g.walls, lc, v);
+  stencil(v, gphx, gphy, lapphi);
+  const T ph = v[1][1];
+  lds3x3<T, NT>(S.mu, 3, q, g.ny, g.walls, lc, v);
+  stencil(v, gmux, gmuy, lapmu);
+  Macro<T> m;
+  macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, Sm, jx, jy, c, m);
+  S.p[q & 3][lc] = m.p;
+  nd[0] = m.ux;
+  nd[1] = m.uy;
+  nd[2] = m.Fx;
+  nd[3] = m.Fy;
+  nd[4] = m.drx;
+  nd[5] = m.dry;
+  nd[6] = m.D;
+}
+
+// Stage D of one pipeline: collision of row cr (f, gg hold its pulled
+// populations on entry, the post-collision ones on exit).
+template <typename T, int NT>
+__device__ __forceinline__ void stage_collide(const StageRings<T, NT>& S, int cr, const Geom& g,
+                                              int lc, const Coef<T>& c, const T nd[NM], T f[9],
+                                              T gg[9]) {
+  Macro<T> m;
+  m.phi = S.phi[cr & 3][lc];
+  m.mu = S.mu[cr & 3][lc];
+  m.rho = c.rho_B + c.drho * m.phi;
+  m.ux = nd[0];
+  m.uy = nd[1];
+  m.Fx = nd[2];
+  m.Fy = nd[3];
+  m.drx = nd[4];
+  m.dry = nd[5];
+  m.D = nd[6];
+  T v[3][3], dpx, dpy, lapp;
+  lds3x3<T, NT>(S.p, 3, cr, g.ny, g.walls, lc, v);
+  m.p = v[1][1];
+  stencil(v, dpx, dpy, lapp);
+  collide_node(f, gg, m, dpx, dpy, c);
+}
+
+template <int P, bool BIG, int J, int NT>
+__device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, int s,
+                                            typename BufT<P>::R (&gb1)[4][9],
+                                            typename BufT<P>::R (&f0b1)[4],
+                                            typename BufT<P>::R (&gb2)[4][9],
+                                            typename BufT<P>::R (&f0b2)[4],
+                                            typename PrecT<P>::T (&nd1)[2][NM],
+                                            typename PrecT<P>::T (&nd2)[2][NM],
+                                            Fused2Lds<P, NT>& L) {
+  using T = typename PrecT<P>::T;
+  using R = typename BufT<P>::R;
+  const Geom& g = k.g;
+  const int lc = k.lc, d = k.d;
+  const int r2 = r - 5 * d;
+  // A
+  if (in_stage(k, r, 0)) L.s1.phi[r & 3][lc] = T(qsum_g<P>(gb1[J])) * T(GQI);
+  if (in_stage(k, r2, 4)) {
+    // slots of rows r2 - 1, r2, r2 + 1: the row D1 wrote i iterations ago
+    // sits in slot (s - i) mod 3, and rows r2 - d, r2, r2 + d were written
+    // 3, 2 and 1 iterations ago
+    const int s1 = s == 0 ? 2 : s - 1, s2 = s == 2 ? 0 : s + 1;
+    const int sl[3] = {d > 0 ? s : s1, s2, d > 0 ? s1 : s};
+    pull_mid<P, NT>(L.mid, sl, r2, g, lc, gb2[J], f0b2[J]);
+    L.s2.phi[r2 & 3][lc] = T(qsum_g<P>(gb2[J])) * T(GQI);
+  }
+  __syncthreads();
+  // B
+  if (in_stage(k, r - d, 1)) stage_mu<T, NT>(L.s1, r - d, g, lc, k.c);
+  if (in_stage(k, r2 - d, 5)) stage_mu<T, NT>(L.s2, r2 - d, g, lc, k.c);
+  __syncthreads();
+  // C
+  if (in_stage(k, r - 2 * d, 2))
+    stage_macro<P, NT>(L.s1, gb1[(J + 2) & 3], f0b1[(J + 2) & 3], r - 2 * d, g, lc, k.c, nd1[J & 1]);
+  if (in_stage(k, r2 - 2 * d, 6))
+    stage_macro<P, NT>(L.s2, gb2[(J + 2) & 3], f0b2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c,
+                       nd2[J & 1]);
+  __syncthreads();
+  // D1: row r - 3d into the ring; the words of row r + d into the freed slot
+  {
+    const int cr = r - 3 * d;
+    T f[9], gg[9];
+    const int32_t phi_q = qsum_g<P>(gb1[(J + 1) & 3]);
+    unpack_row<P>(gb1[(J + 1) & 3], f0b1[(J + 1) & 3], f, gg);
+    if (in_stage(k, r + d, 0)) {
+      const int y = phys_row(r + d, g);
+      pull_row<P, BIG, true>(k, y, gb1[(J + 1) & 3]);
+      if constexpr (P == P_F16) f0b1[(J + 1) & 3] = pull_f0(k, y);
+    }
+    if (in_stage(k, cr, 3)) {
+      stage_collide<T, NT>(L.s1, cr, g, lc, k.c, nd1[(J + 1) & 1], f, gg);
+      R w[9], f0w;
+      pack_row<P>(f, gg, phi_q, w, f0w);
+#pragma unroll
+      for (int i = 0; i < 9; ++i) L.mid.w[s][i][lc] = w[i];
+      if constexpr (P == P_F16) L.mid.f0[s][lc] = (uint16_t)f0w;
+    }
+  }
+  // D2: row r - 8d to memory
+  {
+    const int cr = r2 - 3 * d;
+    if (in_stage(k, cr, 7)) {
+      T f[9], gg[9];
+      const int32_t phi_q = qsum_g<P>(gb2[(J + 1) & 3]);
+      unpack_row<P>(gb2[(J + 1) & 3], f0b2[(J + 1) & 3], f, gg);
+      stage_collide<T, NT>(L.s2, cr, g, lc, k.c, nd2[(J + 1) & 1], f, gg);
+      R w[9], f0w;
+      pack_row<P>(f, gg, phi_q, w, f0w);
+      store_words<P, BIG>(k, (uint32_t)(cr * g.nx), w, f0w);
+    }
+  }
+  __syncthreads();
+}
+
+// Two resident workgroups per CU: the LDS (78 KB for FP32, 53 KB for FP16
+// storage) and the two register rings allow no more.
+template <int P> struct Fused2Waves { static constexpr int value = 2; };
+
+template <int P, bool BIG>
+__global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
+    Pop<P> in, Pop<P> out, Coef<typename PrecT<P>::T> c, Geom g, int width, int nstrips,
+    int seg_len) {
+  using T = typename PrecT<P>::T;
+  using R = typename BufT<P>::R;
+  constexpr int NT = 256;
+  __shared__ Fused2Lds<P, NT> L;
+  FusedCtx<P, BIG> k;
+  k.in.init(in);
+  k.out.init(out);
+  k.c = c;
+  k.g = g;
+  k.rec = nullptr;
+  const int tile = xcd_tile(blockIdx.x, gridDim.x);
+  const int seg = tile / nstrips, strip = tile - seg * nstrips;
+  const int x0 = strip * width;
+  k.wi = min(width, g.nx - x0);
+  k.y0 = seg * seg_len;
+  k.y1 = min(g.ny, k.y0 + seg_len);
+  k.d = (seg & 1) ? -1 : 1;
+  const int t = threadIdx.x;
+  k.act = t < k.wi + 2 * FH2;
+  k.lc = k.act ? t : FH2;
+  // the halo reaches 7 columns beyond the strip: wrap with a full modulo
+  // (lattices may be narrower than the halo)
+  int xv = (x0 - FH2 + k.lc) % g.nx;
+  k.x = xv < 0 ? xv + g.nx : xv;
+  k.col[0] = (uint32_t)wrap_x(k.x - 1, g.nx);
+  k.col[1] = (uint32_t)k.x;
+  k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
+  R gb1[4][9], gb2[4][9], f0b1[4], f0b2[4];
+  T nd1[2][NM], nd2[2][NM];
+  const int r0 = k.d > 0 ? k.y0 - FH2 : k.y1 + FH2 - 1;
+  const int nit = (k.y1 - k.y0) + 2 * FH2 + 1;
+  if (in_stage(k, r0, 0)) {
+    pull_row<P, BIG, true>(k, phys_row(r0, g), gb1[0]);
+    if constexpr (P == P_F16) f0b1[0] = pull_f0(k, phys_row(r0, g));
+  }
+  int s = 0;   // ring slot D1 writes in this iteration: iteration index mod 3
+  for (int it = 0; it < nit; it += 4) {
+    fused2_iter<P, BIG, 0, NT>(k, r0 + k.d * (it + 0), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    s = s == 2 ? 0 : s + 1;
+    fused2_iter<P, BIG, 1, NT>(k, r0 + k.d * (it + 1), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    s = s == 2 ? 0 : s + 1;
+    fused2_iter<P, BIG, 2, NT>(k, r0 + k.d * (it + 2), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    s = s == 2 ? 0 : s + 1;
+    fused2_iter<P, BIG, 3, NT>(k, r0 + k.d * (it + 3), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    s = s == 2 ? 0 : s + 1;
+  }
+}
+
 // --------------------------------------------------------------- launchers
 static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
@@ -1118,6 +1452,62 @@ hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename Pr
 }
 
 template <int P>
+FusedShape fused2_shape(const Geom& g, int seg_rows, int resident) {
+  constexpr int NT = 256, FWMAX = NT - 2 * FH2;
+  FusedShape sh;
+  sh.nstrips = (g.nx + FWMAX - 1) / FWMAX;
+  sh.width = (g.nx + sh.nstrips - 1) / sh.nstrips;
+  if (seg_rows <= 0) {
+    // one round of workgroups: as many segments as resident slots allow,
+    // since every segment end costs 7 warm-up rows of both steps
+    if (resident < 1) resident = 512;
+    int nseg = resident / sh.nstrips;
+    if (nseg < 1) nseg = 1;
+    seg_rows = (g.ny + nseg - 1) / nseg;
+    if (seg_rows < 16) seg_rows = 16;
+  }
+  if (seg_rows > g.ny) seg_rows = g.ny;
+  sh.seg_rows = seg_rows;
+  sh.nseg = (g.ny + seg_rows - 1) / seg_rows;
+  sh.threads = NT;
+  return sh;
+}
+
+template <int P>
+int fused2_resident() {
+  if constexpr (P == P_F64) {
+    return 0;
+  } else {
+    int dev = 0, cus = 0, per_cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+      return 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2_fused<P, false>, 256, 0) !=
+        hipSuccess)
+      return 0;
+    return cus * (per_cu > 0 ? per_cu : 1);
+  }
+}
+
+template <int P>
+hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
+                              const Geom& g, const FusedShape& sh, hipStream_t s) {
+  if constexpr (P == P_F64) {
+    return hipErrorInvalidValue;
+  } else {
+    Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
+    const dim3 grid(sh.nstrips * sh.nseg), block(sh.threads);
+    if (fused_big<P>(g))
+      hipLaunchKernelGGL((k_step2_fused<P, true>), grid, block, 0, s, i, o, c, g, sh.width,
+                         sh.nstrips, sh.seg_rows);
+    else
+      hipLaunchKernelGGL((k_step2_fused<P, false>), grid, block, 0, s, i, o, c, g, sh.width,
+                         sh.nstrips, sh.seg_rows);
+    return hipGetLastError();
+  }
+}
+
+template <int P>
 hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
                        const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s) {
   using T = typename PrecT<P>::T;
@@ -1154,6 +1544,10 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
   template int fused_resident<P>();                                                              \
   template FusedShape fused_shape<P>(const Geom&, int, int);                                     \
   template bool fused_big<P>(const Geom&);                                                       \
+  template FusedShape fused2_shape<P>(const Geom&, int, int);                                    \
+  template int fused2_resident<P>();                                                             \
+  template hipError_t launch_step2_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,        \
+                                            const Geom&, const FusedShape&, hipStream_t);        \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
                                      const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
 

@@ -134,6 +134,16 @@ class Lattice:
         _lib.check(self.lib.lbm_launch_info(self.ctx, out), "lbm_launch_info")
         return dict(zip(("strips", "segments", "seg_rows", "threads"), list(out)))
 
+    def set_pass(self, steps: int, seg_rows: int = 0) -> None:
+        """Time steps per fused launch in step() (2: temporal blocking, the
+        default for fp32 and fp16 storage; 1: one launch per step)."""
+        _lib.check(self.lib.lbm_set_pass(self.ctx, int(steps), int(seg_rows)), "lbm_set_pass")
+
+    def pass_info(self) -> dict:
+        out = (c_int32 * 5)()
+        _lib.check(self.lib.lbm_pass_info(self.ctx, out), "lbm_pass_info")
+        return dict(zip(("steps", "strips", "segments", "seg_rows", "threads"), list(out)))
+
     # ------------------------------------------------------------ adjoint
     def adjoint_begin(self, dL_dphi: torch.Tensor) -> None:
         nbytes = self.lib.lbm_adjoint_workspace_bytes(byref(self.params))

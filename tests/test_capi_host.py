@@ -4,7 +4,7 @@ any device work."""
 import ctypes
 import os
 import re
-from ctypes import byref, c_double, c_void_p
+from ctypes import c_int32, byref, c_double, c_void_p
 
 import pytest
 
@@ -86,6 +86,10 @@ def test_null_context_calls(lib):
     assert lib.lbm_adjoint_step_record(None, None) == _lib.LBM_EINVAL
     assert lib.lbm_step_record(None, None) == _lib.LBM_EINVAL
     assert lib.lbm_record_bytes(None) == 0
+    assert lib.lbm_set_launch(None, 0) == _lib.LBM_EINVAL
+    assert lib.lbm_launch_info(None, (c_int32 * 4)()) == _lib.LBM_EINVAL
+    assert lib.lbm_set_pass(None, 2, 0) == _lib.LBM_EINVAL
+    assert lib.lbm_pass_info(None, (c_int32 * 5)()) == _lib.LBM_EINVAL
     lib.lbm_destroy(None)
     assert lib.lbm_strerror(_lib.LBM_EDIVERGED).decode().startswith("non-finite")
 

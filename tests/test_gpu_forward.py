@@ -25,6 +25,7 @@ import torch
 
 import workloads as wl
 from oracle import qilbm_oracle as O
+from q229 import q229_total as _q229_total
 
 pytestmark = pytest.mark.gpu
 
@@ -345,29 +346,6 @@ def test_full_size_from_initial_state(name, precision):
     torch.cuda.empty_cache()
 
 
-def _q229_total(raw, precision, nx, ny):
-    """Exact integer total of the stored order-parameter populations in a raw
-    state buffer (Q2.29 words; binary16 g_1..8 mapped to Q2.29 the way the
-    kernels map them)."""
-    N = nx * ny
-    # plane stride from the buffer size: 18 planes of 4 bytes (FP32) or
-    # 17 of 2 bytes + 1 of 4 (FP16 storage)
-    Ns = raw.numel() // (72 if precision == "fp32" else 38)
-    if precision == "fp32":
-        # nine planes of 64-bit words, g_i (Q2.29) in the high 32 bits
-        words = raw[:72 * Ns].view(torch.int32).view(9, Ns, 2)[:, :N, 1]
-        return int(words.to(torch.int64).sum())
-    # FP16 storage: f_0 plane (2 B), g_0 plane (Q2.29 int32), then for
-    # i = 1..8 a plane of 32-bit words with g_i in the high half
-    g0 = raw[2 * Ns:6 * Ns].view(torch.int32)[:N]
-    tot = int(g0.to(torch.int64).sum())
-    halves = raw[6 * Ns:38 * Ns].view(torch.float16).view(8, Ns, 2)[:, :N, 1].float()
-    for i in range(8):
-        scale = 4096.0 if i < 4 else 1024.0
-        tot += int(torch.round(halves[i] * scale).to(torch.int64).sum())
-    return tot
-
-
 @pytest.mark.parametrize("precision", ["fp32", "fp16"])
 @pytest.mark.parametrize("bc", [wl.PERIODIC, wl.WALLS_Y])
 def test_reduced_precision_conserves_mass_exactly(precision, bc):
@@ -453,10 +431,12 @@ def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol):
 @pytest.mark.parametrize("precision", ["fp64", "fp32"])
 def test_steps_captured_in_a_hip_graph(precision):
     """lbm_step enqueues kernel launches only (no allocation, no memset), so
-    a caller can capture it in a HIP graph: two steps captured on the
-    lattice's stream and replayed three times, with eager work between the
-    replays, give raw states bitwise equal to eager stepping after every
-    replay. (The host-side time counter advances only during capture.)"""
+    a caller can capture it in a HIP graph: an even number of launches (two
+    one-step launches in FP64, two two-step launches in FP32) captured on
+    the lattice's stream and replayed three times, with eager work between
+    the replays, give raw states bitwise equal to eager stepping after every
+    replay. (The host-side time counter and buffer index advance only
+    during capture; an even number of buffer swaps returns to the start.)"""
     from paper_1507_03521_amd import Lattice
     pb = wl.droplet64().with_(nx=100, ny=70, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5,
                               meta=dict(R=15.0, xc=50.0, yc=35.0))
@@ -464,12 +444,13 @@ def test_steps_captured_in_a_hip_graph(precision):
     s = torch.cuda.Stream()
     lat_g = Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0", stream=s)
     lat_e = Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0")
+    n = 2 * lat_g.pass_info()["steps"]     # two launches
     lat_g.step(1)
     lat_e.step(1)
     torch.cuda.synchronize()
     graph = torch.cuda.CUDAGraph()
     with torch.cuda.graph(graph, stream=s):
-        lat_g.step(2)            # captured, not executed
+        lat_g.step(n)            # captured, not executed
 
     def same():
         a, b = lat_g.save_raw(), lat_e.save_raw()   # copies on the two lattices' streams
@@ -480,7 +461,7 @@ def test_steps_captured_in_a_hip_graph(precision):
     assert same()
     for _ in range(3):
         graph.replay()
-        lat_e.step(2)
+        lat_e.step(n)
         torch.cuda.synchronize()
         lat_g.moments(("phi",))  # eager work between replays
         assert same()
