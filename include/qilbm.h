@@ -194,7 +194,8 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
 
 /* Time steps per pass of the fused kernel in lbm_step (temporal blocking,
  * an implementation choice; the scheme is Sec. III's step applied twice).
- * steps = 2 (the default for LBM_FP32; available for LBM_FP16_STORE)
+ * steps = 2 (the default for LBM_FP64 and LBM_FP32; available for
+ * LBM_FP16_STORE, whose default is 1)
  * advances the lattice by two steps per launch: the first step's
  * post-collision words stay in on-chip memory and feed the second step, so
  * the populations cross HBM once per two steps; an odd last step of an
@@ -204,8 +205,7 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  * may fuse multiply-adds differently in each. The exact integer invariant
  * of the stored g holds in both. seg_rows: rows per workgroup
  * segment of the two-step kernel (0 = automatic: one round of workgroups).
- * LBM_EINVAL for steps other than 1 and 2, steps = 2 with LBM_FP64, or
- * seg_rows < 0. Applies to lbm_step only (not lbm_step_record, not
+ * LBM_EINVAL for steps other than 1 and 2, or seg_rows < 0. Applies to lbm_step only (not lbm_step_record, not
  * LBM_FLAG_UNFUSED). */
 lbm_status lbm_set_pass(lbm_ctx* ctx, int32_t steps, int32_t seg_rows);
 

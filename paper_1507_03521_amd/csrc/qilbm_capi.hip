@@ -242,10 +242,10 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
   c->t = 0;
   c->seg_rows = 0;
   c->resident = QILBM_DISPATCH(params->precision, fused_resident);
-  // two steps per pass where it is the faster kernel (FP32); FP16 storage
-  // keeps one (its two-step kernel measured slower: the binary16
+  // two steps per pass where it is the faster kernel (FP32, FP64); FP16
+  // storage keeps one (its two-step kernel measured slower: the binary16
   // conversions of the intermediate state make it arithmetic-bound)
-  c->pass_steps = params->precision == LBM_FP32 ? 2 : 1;
+  c->pass_steps = params->precision == LBM_FP16_STORE ? 1 : 2;
   c->pass_seg_rows = 0;
   c->resident2 = QILBM_DISPATCH(params->precision, fused2_resident);
   c->pbytes = pop_bytes(params->precision, c->geom.Ns);
@@ -361,7 +361,6 @@ lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
 
 lbm_status lbm_set_pass(lbm_ctx* c, int32_t steps, int32_t seg_rows) {
   if (!c || seg_rows < 0 || (steps != 1 && steps != 2)) return LBM_EINVAL;
-  if (steps == 2 && c->prm.precision == LBM_FP64) return LBM_EINVAL;
   c->pass_steps = steps;
   c->pass_seg_rows = seg_rows;
   return LBM_OK;
@@ -371,9 +370,11 @@ lbm_status lbm_pass_info(const lbm_ctx* c, int32_t out[5]) {
   if (!c || !out) return LBM_EINVAL;
   FusedShape sh;
   if (c->pass_steps == 2)
-    sh = c->prm.precision == LBM_FP32
-             ? fused2_shape<P_F32>(c->geom, c->pass_seg_rows, c->resident2)
-             : fused2_shape<P_F16>(c->geom, c->pass_seg_rows, c->resident2);
+    sh = c->prm.precision == LBM_FP64
+             ? fused2_shape<P_F64>(c->geom, c->pass_seg_rows, c->resident2)
+             : (c->prm.precision == LBM_FP32
+                    ? fused2_shape<P_F32>(c->geom, c->pass_seg_rows, c->resident2)
+                    : fused2_shape<P_F16>(c->geom, c->pass_seg_rows, c->resident2));
   else
     sh = c->prm.precision == LBM_FP64
              ? fused_shape<P_F64>(c->geom, c->seg_rows, c->resident)

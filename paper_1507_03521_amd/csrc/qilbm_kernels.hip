@@ -1011,7 +1011,20 @@ struct StageRings {
   T p[4][NT];
 };
 
-// Storage words of three rows of the first step's output, direction-major.
+// The storage words of one row at one lane, as loaded from memory or pulled
+// from the ring: FP32 the nine (f_i, g_i) pair words; FP16 storage the g_0
+// word and the eight pair words, plus the f_0 half; FP64 the nine f and the
+// nine g values.
+template <int P> struct Row {
+  typename BufT<P>::R w[9];
+  typename BufT<P>::R f0;
+};
+template <> struct Row<P_F64> {
+  double f[9];
+  double g[9];
+};
+
+// Three rows of the first step's output, direction-major.
 template <int P, int NT> struct MidRing;
 template <int NT> struct MidRing<P_F32, NT> {
   uint64_t w[3][9][NT];    // f_i (low word) and the Q2.29 g_i (high word)
@@ -1019,6 +1032,10 @@ template <int NT> struct MidRing<P_F32, NT> {
 template <int NT> struct MidRing<P_F16, NT> {
   uint32_t w[3][9][NT];    // [0]: Q2.29 g_0; [i >= 1]: f_i low half, g_i high half
   uint16_t f0[3][NT];      // binary16 f_0
+};
+template <int NT> struct MidRing<P_F64, NT> {
+  double f[3][9][NT];
+  double g[3][9][NT];
 };
 
 template <int P, int NT>
@@ -1033,8 +1050,8 @@ __device__ __forceinline__ bool in_stage(const FusedCtx<P, BIG>& k, int v, int s
          v < k.y1 + FH2 - s && row_ok(v, k.g);
 }
 
-// Storage words of a node's post-collision populations: what store_row
-// writes, g_0 closing the node's Q2.29 sum at phi_q.
+// Storage words of a node's post-collision populations (fixed-point modes):
+// what store_row writes, g_0 closing the node's Q2.29 sum at phi_q.
 template <int P>
 __device__ __forceinline__ void pack_row(const typename PrecT<P>::T f[9],
                                          const typename PrecT<P>::T gg[9], int32_t phi_q,
@@ -1064,7 +1081,7 @@ __device__ __forceinline__ void pack_row(const typename PrecT<P>::T f[9],
   }
 }
 
-// Stores packed words of one node at (row, own column).
+// Stores packed words of one node at (row, own column) (fixed-point modes).
 template <int P, bool BIG, int I = 0>
 __device__ __forceinline__ void store_words(const FusedCtx<P, BIG>& k, uint32_t row,
                                             const typename BufT<P>::R w[9],
@@ -1084,32 +1101,120 @@ __device__ __forceinline__ void store_words(const FusedCtx<P, BIG>& k, uint32_t 
   }
 }
 
+// Row y's words from memory (pull streaming as in pull_row).
+template <int P, bool BIG>
+__device__ __forceinline__ void load_row(const FusedCtx<P, BIG>& k, int y, Row<P>& row) {
+  if constexpr (P == P_F64) {
+    pull_row<P, BIG, false>(k, y, row.f);
+    pull_row<P, BIG, true>(k, y, row.g);
+  } else {
+    pull_row<P, BIG, true>(k, y, row.w);
+    if constexpr (P == P_F16) row.f0 = pull_f0(k, y);
+  }
+}
+
+// phi of a row (and, in the fixed-point modes, its exact Q2.29 sum q), as
+// the one-step kernel forms it.
+template <int P>
+__device__ __forceinline__ typename PrecT<P>::T row_phi(const Row<P>& row, int32_t& q) {
+  using T = typename PrecT<P>::T;
+  if constexpr (P == P_F64) {
+    q = 0;
+    return sum9(row.g);
+  } else {
+    q = qsum_g<P>(row.w);
+    return T(q) * T(GQI);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void row_unpack(const Row<P>& row, typename PrecT<P>::T f[9],
+                                           typename PrecT<P>::T g[9]) {
+  if constexpr (P == P_F64) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      f[i] = row.f[i];
+      g[i] = row.g[i];
+    }
+  } else {
+    unpack_row<P>(row.w, row.f0, f, g);
+  }
+}
+
+template <int P>
+__device__ __forceinline__ void row_pack(const typename PrecT<P>::T f[9],
+                                         const typename PrecT<P>::T g[9], int32_t phi_q,
+                                         Row<P>& row) {
+  if constexpr (P == P_F64) {
+#pragma unroll
+    for (int i = 0; i < 9; ++i) {
+      row.f[i] = f[i];
+      row.g[i] = g[i];
+    }
+  } else {
+    pack_row<P>(f, g, phi_q, row.w, row.f0);
+  }
+}
+
+// Stores a node's post-collision populations to memory.
+template <int P, bool BIG>
+__device__ __forceinline__ void store_node2(const FusedCtx<P, BIG>& k, uint32_t rowoff,
+                                            const typename PrecT<P>::T f[9],
+                                            const typename PrecT<P>::T g[9], int32_t phi_q) {
+  if constexpr (P == P_F64) {
+    store_row<P, BIG>(k, rowoff, f, g, 0);
+  } else {
+    Row<P> o;
+    pack_row<P>(f, g, phi_q, o.w, o.f0);
+    store_words<P, BIG>(k, rowoff, o.w, o.f0);
+  }
+}
+
+template <int P, int NT>
+__device__ __forceinline__ void ring_put(MidRing<P, NT>& M, int s, int lc, const Row<P>& row) {
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    if constexpr (P == P_F64) {
+      M.f[s][i][lc] = row.f[i];
+      M.g[s][i][lc] = row.g[i];
+    } else {
+      M.w[s][i][lc] = row.w[i];
+    }
+  }
+  if constexpr (P == P_F16) M.f0[s][lc] = (uint16_t)row.f0;
+}
+
 // Pulls row v's words out of the ring: sl[1 + dy] is the slot of row v + dy.
 // WALL as in pull_row_dirs.
 template <int P, int NT, int WALL, int I = 0>
 __device__ __forceinline__ void pull_mid_dirs(const MidRing<P, NT>& M, const int sl[3], int lc,
-                                              typename BufT<P>::R v[9]) {
+                                              Row<P>& row) {
   if constexpr (I < 9) {
     constexpr int cx = CXS(I), cy = CYS(I);
-    if constexpr ((WALL == -1 && cy == 1) || (WALL == 1 && cy == -1))
-      v[I] = M.w[sl[1]][OPP(I)][lc];
-    else
-      v[I] = M.w[sl[1 - cy]][I][lc - cx];
-    pull_mid_dirs<P, NT, WALL, I + 1>(M, sl, lc, v);
+    constexpr bool bounce = (WALL == -1 && cy == 1) || (WALL == 1 && cy == -1);
+    constexpr int src = bounce ? OPP(I) : I;
+    const int s = bounce ? sl[1] : sl[1 - cy];
+    const int l = bounce ? lc : lc - cx;
+    if constexpr (P == P_F64) {
+      row.f[I] = M.f[s][src][l];
+      row.g[I] = M.g[s][src][l];
+    } else {
+      row.w[I] = M.w[s][src][l];
+    }
+    pull_mid_dirs<P, NT, WALL, I + 1>(M, sl, lc, row);
   }
 }
 
 template <int P, int NT>
 __device__ __forceinline__ void pull_mid(const MidRing<P, NT>& M, const int sl[3], int v,
-                                         const Geom& g, int lc, typename BufT<P>::R w[9],
-                                         typename BufT<P>::R& f0w) {
+                                         const Geom& g, int lc, Row<P>& row) {
   if (g.walls && v == 0)
-    pull_mid_dirs<P, NT, -1>(M, sl, lc, w);
+    pull_mid_dirs<P, NT, -1>(M, sl, lc, row);
   else if (g.walls && v == g.ny - 1)
-    pull_mid_dirs<P, NT, 1>(M, sl, lc, w);
+    pull_mid_dirs<P, NT, 1>(M, sl, lc, row);
   else
-    pull_mid_dirs<P, NT, 0>(M, sl, lc, w);
-  if constexpr (P == P_F16) f0w = M.f0[sl[1]][lc];
+    pull_mid_dirs<P, NT, 0>(M, sl, lc, row);
+  if constexpr (P == P_F16) row.f0 = M.f0[sl[1]][lc];
 }
 
 // Stage B of one pipeline: mu at row b.
@@ -1123,16 +1228,15 @@ __device__ __forceinline__ void stage_mu(StageRings<T, NT>& S, int b, const Geom
 }
 
 // Stage C of one pipeline: force, velocity and pressure at row q from its
-// pulled words; p into the ring, the rest into nd.
+// pulled populations; p into the ring, the rest into nd.
 template <int P, int NT>
 __device__ __forceinline__ void stage_macro(StageRings<typename PrecT<P>::T, NT>& S,
-                                            const typename BufT<P>::R w[9],
-                                            typename BufT<P>::R f0w, int q, const Geom& g, int lc,
+                                            const Row<P>& row, int q, const Geom& g, int lc,
                                             const Coef<typename PrecT<P>::T>& c,
                                             typename PrecT<P>::T nd[NM]) {
   using T = typename PrecT<P>::T;
   T fv[9], gv[9];
-  unpack_row<P>(w, f0w, fv, gv);
+  row_unpack<P>(row, fv, gv);
   T Sm, jx, jy;
   moments9(fv, Sm, jx, jy);
   T v[3][3], gphx, gphy, lapphi, gmux, gmuy, lapmu;
@@ -1179,28 +1283,25 @@ __device__ __forceinline__ void stage_collide(const StageRings<T, NT>& S, int cr
 
 template <int P, bool BIG, int J, int NT>
 __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, int s,
-                                            typename BufT<P>::R (&gb1)[4][9],
-                                            typename BufT<P>::R (&f0b1)[4],
-                                            typename BufT<P>::R (&gb2)[4][9],
-                                            typename BufT<P>::R (&f0b2)[4],
+                                            Row<P> (&rb1)[4], Row<P> (&rb2)[4],
                                             typename PrecT<P>::T (&nd1)[2][NM],
                                             typename PrecT<P>::T (&nd2)[2][NM],
                                             Fused2Lds<P, NT>& L) {
   using T = typename PrecT<P>::T;
-  using R = typename BufT<P>::R;
   const Geom& g = k.g;
   const int lc = k.lc, d = k.d;
   const int r2 = r - 5 * d;
+  int32_t q;
   // A
-  if (in_stage(k, r, 0)) L.s1.phi[r & 3][lc] = T(qsum_g<P>(gb1[J])) * T(GQI);
+  if (in_stage(k, r, 0)) L.s1.phi[r & 3][lc] = row_phi<P>(rb1[J], q);
   if (in_stage(k, r2, 4)) {
     // slots of rows r2 - 1, r2, r2 + 1: the row D1 wrote i iterations ago
     // sits in slot (s - i) mod 3, and rows r2 - d, r2, r2 + d were written
     // 3, 2 and 1 iterations ago
     const int s1 = s == 0 ? 2 : s - 1, s2 = s == 2 ? 0 : s + 1;
     const int sl[3] = {d > 0 ? s : s1, s2, d > 0 ? s1 : s};
-    pull_mid<P, NT>(L.mid, sl, r2, g, lc, gb2[J], f0b2[J]);
-    L.s2.phi[r2 & 3][lc] = T(qsum_g<P>(gb2[J])) * T(GQI);
+    pull_mid<P, NT>(L.mid, sl, r2, g, lc, rb2[J]);
+    L.s2.phi[r2 & 3][lc] = row_phi<P>(rb2[J], q);
   }
   __syncthreads();
   // B
@@ -1209,29 +1310,23 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
   __syncthreads();
   // C
   if (in_stage(k, r - 2 * d, 2))
-    stage_macro<P, NT>(L.s1, gb1[(J + 2) & 3], f0b1[(J + 2) & 3], r - 2 * d, g, lc, k.c, nd1[J & 1]);
+    stage_macro<P, NT>(L.s1, rb1[(J + 2) & 3], r - 2 * d, g, lc, k.c, nd1[J & 1]);
   if (in_stage(k, r2 - 2 * d, 6))
-    stage_macro<P, NT>(L.s2, gb2[(J + 2) & 3], f0b2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c,
-                       nd2[J & 1]);
+    stage_macro<P, NT>(L.s2, rb2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c, nd2[J & 1]);
   __syncthreads();
   // D1: row r - 3d into the ring; the words of row r + d into the freed slot
   {
     const int cr = r - 3 * d;
     T f[9], gg[9];
-    const int32_t phi_q = qsum_g<P>(gb1[(J + 1) & 3]);
-    unpack_row<P>(gb1[(J + 1) & 3], f0b1[(J + 1) & 3], f, gg);
-    if (in_stage(k, r + d, 0)) {
-      const int y = phys_row(r + d, g);
-      pull_row<P, BIG, true>(k, y, gb1[(J + 1) & 3]);
-      if constexpr (P == P_F16) f0b1[(J + 1) & 3] = pull_f0(k, y);
-    }
+    int32_t phi_q;
+    row_phi<P>(rb1[(J + 1) & 3], phi_q);
+    row_unpack<P>(rb1[(J + 1) & 3], f, gg);
+    if (in_stage(k, r + d, 0)) load_row<P, BIG>(k, phys_row(r + d, g), rb1[(J + 1) & 3]);
     if (in_stage(k, cr, 3)) {
       stage_collide<T, NT>(L.s1, cr, g, lc, k.c, nd1[(J + 1) & 1], f, gg);
-      R w[9], f0w;
-      pack_row<P>(f, gg, phi_q, w, f0w);
-#pragma unroll
-      for (int i = 0; i < 9; ++i) L.mid.w[s][i][lc] = w[i];
-      if constexpr (P == P_F16) L.mid.f0[s][lc] = (uint16_t)f0w;
+      Row<P> o;
+      row_pack<P>(f, gg, phi_q, o);
+      ring_put<P, NT>(L.mid, s, lc, o);
     }
   }
   // D2: row r - 8d to memory
@@ -1239,27 +1334,27 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     const int cr = r2 - 3 * d;
     if (in_stage(k, cr, 7)) {
       T f[9], gg[9];
-      const int32_t phi_q = qsum_g<P>(gb2[(J + 1) & 3]);
-      unpack_row<P>(gb2[(J + 1) & 3], f0b2[(J + 1) & 3], f, gg);
+      int32_t phi_q;
+      row_phi<P>(rb2[(J + 1) & 3], phi_q);
+      row_unpack<P>(rb2[(J + 1) & 3], f, gg);
       stage_collide<T, NT>(L.s2, cr, g, lc, k.c, nd2[(J + 1) & 1], f, gg);
-      R w[9], f0w;
-      pack_row<P>(f, gg, phi_q, w, f0w);
-      store_words<P, BIG>(k, (uint32_t)(cr * g.nx), w, f0w);
+      store_node2<P, BIG>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
     }
   }
   __syncthreads();
 }
 
-// Two resident workgroups per CU: the LDS (78 KB for FP32, 53 KB for FP16
-// storage) and the two register rings allow no more.
+// Resident workgroups per CU (waves per SIMD with 4-wave workgroups): two
+// for FP32 and FP16 storage (LDS 78 KB / 53 KB, 242 / 181 VGPRs), one for
+// FP64 (LDS 156 KB: the ring of 18 binary64 words per node is 108 KB).
 template <int P> struct Fused2Waves { static constexpr int value = 2; };
+template <> struct Fused2Waves<P_F64> { static constexpr int value = 1; };
 
 template <int P, bool BIG>
 __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
     Pop<P> in, Pop<P> out, Coef<typename PrecT<P>::T> c, Geom g, int width, int nstrips,
     int seg_len) {
   using T = typename PrecT<P>::T;
-  using R = typename BufT<P>::R;
   constexpr int NT = 256;
   __shared__ Fused2Lds<P, NT> L;
   FusedCtx<P, BIG> k;
@@ -1285,23 +1380,20 @@ __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
   k.col[0] = (uint32_t)wrap_x(k.x - 1, g.nx);
   k.col[1] = (uint32_t)k.x;
   k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
-  R gb1[4][9], gb2[4][9], f0b1[4], f0b2[4];
+  Row<P> rb1[4], rb2[4];
   T nd1[2][NM], nd2[2][NM];
   const int r0 = k.d > 0 ? k.y0 - FH2 : k.y1 + FH2 - 1;
   const int nit = (k.y1 - k.y0) + 2 * FH2 + 1;
-  if (in_stage(k, r0, 0)) {
-    pull_row<P, BIG, true>(k, phys_row(r0, g), gb1[0]);
-    if constexpr (P == P_F16) f0b1[0] = pull_f0(k, phys_row(r0, g));
-  }
+  if (in_stage(k, r0, 0)) load_row<P, BIG>(k, phys_row(r0, g), rb1[0]);
   int s = 0;   // ring slot D1 writes in this iteration: iteration index mod 3
   for (int it = 0; it < nit; it += 4) {
-    fused2_iter<P, BIG, 0, NT>(k, r0 + k.d * (it + 0), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    fused2_iter<P, BIG, 0, NT>(k, r0 + k.d * (it + 0), s, rb1, rb2, nd1, nd2, L);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, 1, NT>(k, r0 + k.d * (it + 1), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    fused2_iter<P, BIG, 1, NT>(k, r0 + k.d * (it + 1), s, rb1, rb2, nd1, nd2, L);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, 2, NT>(k, r0 + k.d * (it + 2), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    fused2_iter<P, BIG, 2, NT>(k, r0 + k.d * (it + 2), s, rb1, rb2, nd1, nd2, L);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, 3, NT>(k, r0 + k.d * (it + 3), s, gb1, f0b1, gb2, f0b2, nd1, nd2, L);
+    fused2_iter<P, BIG, 3, NT>(k, r0 + k.d * (it + 3), s, rb1, rb2, nd1, nd2, L);
     s = s == 2 ? 0 : s + 1;
   }
 }
@@ -1475,36 +1567,28 @@ FusedShape fused2_shape(const Geom& g, int seg_rows, int resident) {
 
 template <int P>
 int fused2_resident() {
-  if constexpr (P == P_F64) {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  } else {
-    int dev = 0, cus = 0, per_cu = 0;
-    if (hipGetDevice(&dev) != hipSuccess) return 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
-      return 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2_fused<P, false>, 256, 0) !=
-        hipSuccess)
-      return 0;
-    return cus * (per_cu > 0 ? per_cu : 1);
-  }
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2_fused<P, false>, 256, 0) !=
+      hipSuccess)
+    return 0;
+  return cus * (per_cu > 0 ? per_cu : 1);
 }
 
 template <int P>
 hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
                               const Geom& g, const FusedShape& sh, hipStream_t s) {
-  if constexpr (P == P_F64) {
-    return hipErrorInvalidValue;
-  } else {
-    Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
-    const dim3 grid(sh.nstrips * sh.nseg), block(sh.threads);
-    if (fused_big<P>(g))
-      hipLaunchKernelGGL((k_step2_fused<P, true>), grid, block, 0, s, i, o, c, g, sh.width,
-                         sh.nstrips, sh.seg_rows);
-    else
-      hipLaunchKernelGGL((k_step2_fused<P, false>), grid, block, 0, s, i, o, c, g, sh.width,
-                         sh.nstrips, sh.seg_rows);
-    return hipGetLastError();
-  }
+  Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
+  const dim3 grid(sh.nstrips * sh.nseg), block(sh.threads);
+  if (fused_big<P>(g))
+    hipLaunchKernelGGL((k_step2_fused<P, true>), grid, block, 0, s, i, o, c, g, sh.width,
+                       sh.nstrips, sh.seg_rows);
+  else
+    hipLaunchKernelGGL((k_step2_fused<P, false>), grid, block, 0, s, i, o, c, g, sh.width,
+                       sh.nstrips, sh.seg_rows);
+  return hipGetLastError();
 }
 
 template <int P>

@@ -80,6 +80,7 @@ def test_fused_segment_lengths(seg_rows):
     pb = _problem(300, 41, wl.WALLS_Y, -1e-5)
     f, g = wl.random_state(300, 41, seed=5)
     lat = _lattice(pb, np.full((41, 300), 0.5))
+    lat.set_pass(1)                  # the one-step kernel, whose shape set_launch sets
     lat.set_launch(seg_rows)
     lat.set_state(f, g)
     lat.step(2)
@@ -378,13 +379,14 @@ BIG_SHAPES = [("fp64", 4000, 15000, (1e-12, 1e-12)), ("fp32", 8000, 15000, (2e-3
               ("fp16", 300, 41, (4e-3, 1e-5))]
 
 
+@pytest.mark.parametrize("per_pass", [1, 2])
 @pytest.mark.parametrize("precision,nx,ny,tol", BIG_SHAPES)
-def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol):
+def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol, per_pass):
     """At sizes where nine planes of populations span more than 4 GiB (and,
-    for comparison, at a small size), two fused steps (walls and gravity on)
-    agree with two steps of the unfused kernels, which address memory with
-    64-bit pointers; in the fixed-point modes both conserve the exact
-    integer total of g."""
+    for comparison, at a small size), two fused steps (walls and gravity on;
+    two one-step launches or one two-step launch) agree with two steps of
+    the unfused kernels, which address memory with 64-bit pointers; in the
+    fixed-point modes both conserve the exact integer total of g."""
     from paper_1507_03521_amd import LBM_FLAG_UNFUSED, Lattice
     pb = wl.rt2048().with_(nx=nx, ny=ny)
     dev = torch.device("cuda:0")
@@ -397,6 +399,8 @@ def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol):
     first_raw = None
     for flags in (0, LBM_FLAG_UNFUSED):
         lat = Lattice(pb.as_dict(), phi0, precision=precision, flags=flags, device=dev)
+        if not flags:
+            lat.set_pass(per_pass)
         per_node = {"fp64": 144, "fp32": 72, "fp16": 38}[precision]
         Ns = lat.state_bytes // per_node
         # largest plane group: nine f planes (FP64), the nine 64-bit f/g
@@ -423,7 +427,8 @@ def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol):
     (f0, g0), (f1, g1) = states
     ef = float((f0 - f1).abs().max() / f1.abs().max())
     eg = float((g0 - g1).abs().max() / g1.abs().max())
-    print(f"{precision} {nx}x{ny}: fused vs unfused rel f {ef:.2e} g {eg:.2e}, "
+    print(f"{precision} {nx}x{ny} ({per_pass} step(s) per pass): fused vs unfused "
+          f"rel f {ef:.2e} g {eg:.2e}, "
           f"raw bitwise equal: {raws_equal}", flush=True)
     assert ef <= tol[0] and eg <= tol[1]
 
