@@ -77,7 +77,7 @@ def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
 
 def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
     """Adjoint step time (from a step record) and, with the replay of the
-    forward step that writes the record (as checkpoint-recompute does), over
+    forward steps that write the records (as checkpoint-recompute does), over
     the forward step time."""
     import torch
     from paper_1507_03521_amd import Lattice
@@ -96,12 +96,18 @@ def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
     stop.record(lat.stream)
     torch.cuda.synchronize()
     adj_ms = start.elapsed_time(stop) / nadj
+    # the replay as checkpoint-and-recompute runs it: nadj steps with one
+    # record each, pairs of steps per launch where the forward uses them
+    recs = [torch.empty(lat.record_bytes, dtype=torch.uint8, device="cuda:0")
+            for _ in range(nadj)]
+    lat.step_records(recs)
+    torch.cuda.synchronize()
     start.record(lat.stream)
-    for _ in range(nadj):
-        lat.step_record(rec)
+    lat.step_records(recs)
     stop.record(lat.stream)
     torch.cuda.synchronize()
     rec_ms = start.elapsed_time(stop) / nadj
+    del recs
     del lat
     # algorithmic bytes of one adjoint step per node: the record (phi, mu, p,
     # S, jx, jy) read, the 18 population cotangents read and written
@@ -264,10 +270,9 @@ def adjoint_study(warm: int, window: int, C: int, precision: str = "fp64", h: fl
     torch.cuda.synchronize()
     ev0.record(lat.stream)
     snaps = []
-    for t in range(window):
-        if t % C == 0:
-            snaps.append(lat.save_raw())
-        lat.step(1)
+    for t0 in range(0, window, C):
+        snaps.append(lat.save_raw())
+        lat.step(min(C, window - t0))
     ev1.record(lat.stream)
     torch.cuda.synchronize()
     fwd_ms = ev0.elapsed_time(ev1)
@@ -280,8 +285,7 @@ def adjoint_study(warm: int, window: int, C: int, precision: str = "fp64", h: fl
     for sgm in reversed(range(len(snaps))):
         a, b = sgm * C, min(sgm * C + C, window)
         lat.load_raw(snaps[sgm], warm + a)
-        for t in range(a, b):
-            lat.step_record(records[t - a])
+        lat.step_records(records[:b - a])
         for t in reversed(range(a, b)):
             lat.adjoint_step_record(records[t - a])
     ev1.record(lat.stream)

@@ -169,6 +169,14 @@ size_t lbm_record_bytes(const lbm_ctx* ctx);
  * Asynchronous. */
 lbm_status lbm_step_record(lbm_ctx* ctx, void* record_dev);
 
+/* Advances nsteps steps like lbm_step and writes the record of the state
+ * each step starts from: step k's into records[k] (records: a host array of
+ * nsteps device pointers, each as for lbm_step_record). With two steps per
+ * pass (lbm_set_pass) a pair of steps is one launch that writes both records,
+ * so a checkpoint replay follows the same kernels as lbm_step. LBM_EINVAL for
+ * nsteps < 0, a null array, or a null or misaligned record. Asynchronous. */
+lbm_status lbm_step_records(lbm_ctx* ctx, int64_t nsteps, void* const* records);
+
 /* Raw snapshot of the internal state buffer in the storage precision
  * (lbm_state_bytes bytes): exact save/restore for checkpointing.
  * lbm_load_raw also sets the time counter to t. Asynchronous. */

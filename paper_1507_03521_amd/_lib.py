@@ -46,6 +46,7 @@ SIGNATURES = {
     "lbm_set_launch": (c_int32, [c_void_p, c_int32]),
     "lbm_launch_info": (c_int32, [c_void_p, POINTER(c_int32)]),
     "lbm_set_pass": (c_int32, [c_void_p, c_int32, c_int32]),
+    "lbm_step_records": (c_int32, [c_void_p, c_int64, POINTER(c_void_p)]),
     "lbm_pass_info": (c_int32, [c_void_p, POINTER(c_int32)]),
     "lbm_adjoint_workspace_bytes": (c_size_t, [_P]),
     "lbm_adjoint_begin": (c_int32, [c_void_p, c_void_p, c_size_t, c_void_p]),

@@ -13,12 +13,16 @@ class PhaseFieldRun(torch.autograd.Function):
     sigma and M.
 
     Forward keeps a raw snapshot of the state every ``checkpoint`` steps
-    (including t = 0). Backward walks the segments last to first: it restores
-    the segment's snapshot, replays the segment with steps that also write
-    their records (the forward quantities phi, mu, p, S, j each adjoint step
-    needs), and applies the adjoint step to the records in reverse time
-    order. Memory: ceil(K / C) raw states plus C records (a record is a
-    third of a raw state).
+    (including t = 0) and advances each segment with one library call.
+    Backward walks the segments last to first: it restores the segment's
+    snapshot, replays the segment with one call that also writes the records
+    (the forward quantities phi, mu, p, S, j each adjoint step needs) -- the
+    same launches as the forward segment, pairs of steps included -- and
+    applies the adjoint step to the records in reverse time order. Memory:
+    ceil(K / C) raw states plus C records (a record is a third of a raw
+    state). With two steps per kernel pass, an even C keeps the launches of
+    a run without checkpoints (pairs from even t), so the gradients do not
+    depend on C bitwise; an odd C moves the pairs and changes only rounding.
     """
 
     @staticmethod
@@ -30,10 +34,9 @@ class PhaseFieldRun(torch.autograd.Function):
         lat = Lattice(p, phi0.detach(), precision=precision, flags=flags, device=phi0.device)
         C = max(1, int(checkpoint))
         snaps = []
-        for t in range(int(nsteps)):
-            if t % C == 0:
-                snaps.append(lat.save_raw())
-            lat.step(1)
+        for t0 in range(0, int(nsteps), C):
+            snaps.append(lat.save_raw())
+            lat.step(min(C, int(nsteps) - t0))
         phi = lat.moments(("phi",))["phi"]
         ctx.lat = lat
         ctx.param_meta = [(x.device, x.dtype) if torch.is_tensor(x) else None for x in (sigma, M)]
@@ -54,8 +57,7 @@ class PhaseFieldRun(torch.autograd.Function):
             t0 = s * C
             t1 = min(t0 + C, K)
             lat.load_raw(snaps[s], t0)
-            for t in range(t0, t1):
-                lat.step_record(records[t - t0])
+            lat.step_records(records[:t1 - t0])
             for t in reversed(range(t0, t1)):
                 lat.adjoint_step_record(records[t - t0])
         dphi0, dsigma, dM = lat.adjoint_init(phi0)

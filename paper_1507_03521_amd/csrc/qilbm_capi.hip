@@ -133,27 +133,32 @@ char* phi_f(lbm_ctx* c) { return c->fields; }
 char* mu_f(lbm_ctx* c) { return c->fields + c->geom.Ns * 8; }
 char* p_f(lbm_ctx* c) { return c->fields + 2 * c->geom.Ns * 8; }
 
-// n steps; with rec (n = 1) the step also writes its record (planes phi, mu,
-// p, S, jx, jy of the compute type at stride Ns).
+// n steps; with recs not null, step k also writes the record of the state it
+// starts from into recs[k] (planes phi, mu, p, S, jx, jy of the compute type
+// at stride Ns). Pairs of steps run as one two-step launch when the context
+// uses two steps per pass (a pair's records come from that launch).
 template <int P>
-lbm_status step_p(lbm_ctx* c, int64_t n, void* rec) {
+lbm_status step_p(lbm_ctx* c, int64_t n, void* const* recs) {
   using T = typename PrecT<P>::T;
   const Coef<T> k = coef_t<T>(c);
   const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
-  const FusedShape sh = fused_shape<P>(c->geom, c->seg_rows, c->resident);
   const int64_t pl = c->geom.Ns;
-  if (!unfused && !rec && c->pass_steps == 2) {
-    // pairs of steps in one pass each; an odd last step runs alone
+  int64_t done = 0;
+  if (!unfused && c->pass_steps == 2 && n >= 2) {
     const FusedShape sh2 = fused2_shape<P>(c->geom, c->pass_seg_rows, c->resident2);
-    for (; n >= 2; n -= 2) {
-      if (launch_step2_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh2, c->stream) !=
-          hipSuccess)
+    for (; n - done >= 2; done += 2) {
+      void* r0 = recs ? recs[done] : nullptr;
+      void* r1 = recs ? recs[done + 1] : nullptr;
+      if (launch_step2_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh2, r0, r1,
+                                c->stream) != hipSuccess)
         return LBM_EDEVICE;
       c->cur ^= 1;
       c->t += 2;
     }
   }
-  for (int64_t s = 0; s < n; ++s) {
+  const FusedShape sh = fused_shape<P>(c->geom, c->seg_rows, c->resident);
+  for (; done < n; ++done) {
+    void* rec = recs ? recs[done] : nullptr;
     hipError_t e;
     if (unfused && rec)
       e = launch_step_unfused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], (T*)rec, (T*)rec + pl,
@@ -266,7 +271,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
 
 lbm_status lbm_step(lbm_ctx* c, int64_t nsteps) {
   if (!c || nsteps < 0) return LBM_EINVAL;
-  return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps, nullptr);
+  return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps, (void* const*)nullptr);
 }
 
 size_t lbm_record_bytes(const lbm_ctx* c) {
@@ -277,7 +282,15 @@ size_t lbm_record_bytes(const lbm_ctx* c) {
 lbm_status lbm_step_record(lbm_ctx* c, void* record_dev) {
   if (!c || !record_dev) return LBM_EINVAL;
   if ((uintptr_t)record_dev % ALIGN != 0) return LBM_EINVAL;
-  return QILBM_DISPATCH(c->prm.precision, step_p, c, 1, record_dev);
+  void* const recs[1] = {record_dev};
+  return QILBM_DISPATCH(c->prm.precision, step_p, c, 1, recs);
+}
+
+lbm_status lbm_step_records(lbm_ctx* c, int64_t nsteps, void* const* records) {
+  if (!c || nsteps < 0 || (nsteps > 0 && !records)) return LBM_EINVAL;
+  for (int64_t k = 0; k < nsteps; ++k)
+    if (!records[k] || (uintptr_t)records[k] % ALIGN != 0) return LBM_EINVAL;
+  return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps, records);
 }
 
 lbm_status lbm_moments(lbm_ctx* c, double* phi, double* rho, double* ux, double* uy, double* p,

@@ -77,16 +77,18 @@ hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu,
 template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
                              const Geom& g, const FusedShape& sh, void* rec, hipStream_t s);
-// Two steps per launch (FP32 and FP16 storage; FP64 returns
-// hipErrorInvalidValue): the state between the two steps stays on chip.
-// Its shape, for seg_rows rows per segment (0: one round of workgroups).
+// Two steps per launch: the state between the two steps stays on chip.
+// With rec0 and rec1 not null it also writes the records of the state it
+// reads (rec0) and of the state after the first step (rec1). Its shape, for
+// seg_rows rows per segment (0: one round of workgroups).
 template <int P>
 FusedShape fused2_shape(const Geom& g, int seg_rows, int resident);
 template <int P>
 int fused2_resident();
 template <int P>
 hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
-                              const Geom& g, const FusedShape& sh, hipStream_t s);
+                              const Geom& g, const FusedShape& sh, void* rec0, void* rec1,
+                              hipStream_t s);
 template <int P>
 hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
                        const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);

@@ -1050,6 +1050,15 @@ __device__ __forceinline__ bool in_stage(const FusedCtx<P, BIG>& k, int v, int s
          v < k.y1 + FH2 - s && row_ok(v, k.g);
 }
 
+// Record planes (phi, mu, p, S, jx, jy) of the state a step starts from, for
+// the nodes this lane owns (interior column of the strip, row of the segment).
+template <int P, bool BIG>
+__device__ __forceinline__ void record2(const FusedCtx<P, BIG>& k, typename PrecT<P>::T* rec,
+                                        int plane, int v, typename PrecT<P>::T val) {
+  if (k.lc >= FH2 && k.lc < k.wi + FH2 && v >= k.y0 && v < k.y1)
+    rec[(int64_t)plane * k.g.Ns + (int64_t)v * k.g.nx + k.x] = val;
+}
+
 // Storage words of a node's post-collision populations (fixed-point modes):
 // what store_row writes, g_0 closing the node's Q2.29 sum at phi_q.
 template <int P>
@@ -1219,12 +1228,14 @@ __device__ __forceinline__ void pull_mid(const MidRing<P, NT>& M, const int sl[3
 
 // Stage B of one pipeline: mu at row b.
 template <typename T, int NT>
-__device__ __forceinline__ void stage_mu(StageRings<T, NT>& S, int b, const Geom& g, int lc,
-                                         const Coef<T>& c) {
+__device__ __forceinline__ T stage_mu(StageRings<T, NT>& S, int b, const Geom& g, int lc,
+                                      const Coef<T>& c) {
   T v[3][3], gx, gy, lap;
   lds3x3<T, NT>(S.phi, 3, b, g.ny, g.walls, lc, v);
   stencil(v, gx, gy, lap);
-  S.mu[b & 3][lc] = mu_bulk(v[1][1], c) - c.kappa * lap;
+  const T mu = mu_bulk(v[1][1], c) - c.kappa * lap;
+  S.mu[b & 3][lc] = mu;
+  return mu;
 }
 
 // Stage C of one pipeline: force, velocity and pressure at row q from its
@@ -1233,7 +1244,8 @@ template <int P, int NT>
 __device__ __forceinline__ void stage_macro(StageRings<typename PrecT<P>::T, NT>& S,
                                             const Row<P>& row, int q, const Geom& g, int lc,
                                             const Coef<typename PrecT<P>::T>& c,
-                                            typename PrecT<P>::T nd[NM]) {
+                                            typename PrecT<P>::T nd[NM],
+                                            typename PrecT<P>::T rv[4]) {
   using T = typename PrecT<P>::T;
   T fv[9], gv[9];
   row_unpack<P>(row, fv, gv);
@@ -1248,6 +1260,10 @@ __device__ __forceinline__ void stage_macro(StageRings<typename PrecT<P>::T, NT>
   Macro<T> m;
   macro_node(ph, v[1][1], gphx, gphy, gmux, gmuy, lapmu, Sm, jx, jy, c, m);
   S.p[q & 3][lc] = m.p;
+  rv[0] = m.p;
+  rv[1] = Sm;
+  rv[2] = jx;
+  rv[3] = jy;
   nd[0] = m.ux;
   nd[1] = m.uy;
   nd[2] = m.Fx;
@@ -1281,19 +1297,25 @@ __device__ __forceinline__ void stage_collide(const StageRings<T, NT>& S, int cr
   collide_node(f, gg, m, dpx, dpy, c);
 }
 
-template <int P, bool BIG, int J, int NT>
+template <int P, bool BIG, bool REC, int J, int NT>
 __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, int s,
                                             Row<P> (&rb1)[4], Row<P> (&rb2)[4],
                                             typename PrecT<P>::T (&nd1)[2][NM],
                                             typename PrecT<P>::T (&nd2)[2][NM],
-                                            Fused2Lds<P, NT>& L) {
+                                            Fused2Lds<P, NT>& L, typename PrecT<P>::T* rec0,
+                                            typename PrecT<P>::T* rec1) {
   using T = typename PrecT<P>::T;
   const Geom& g = k.g;
   const int lc = k.lc, d = k.d;
   const int r2 = r - 5 * d;
   int32_t q;
+  T rv[4];
   // A
-  if (in_stage(k, r, 0)) L.s1.phi[r & 3][lc] = row_phi<P>(rb1[J], q);
+  if (in_stage(k, r, 0)) {
+    const T ph = row_phi<P>(rb1[J], q);
+    L.s1.phi[r & 3][lc] = ph;
+    if constexpr (REC) record2(k, rec0, 0, r, ph);
+  }
   if (in_stage(k, r2, 4)) {
     // slots of rows r2 - 1, r2, r2 + 1: the row D1 wrote i iterations ago
     // sits in slot (s - i) mod 3, and rows r2 - d, r2, r2 + d were written
@@ -1301,18 +1323,36 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     const int s1 = s == 0 ? 2 : s - 1, s2 = s == 2 ? 0 : s + 1;
     const int sl[3] = {d > 0 ? s : s1, s2, d > 0 ? s1 : s};
     pull_mid<P, NT>(L.mid, sl, r2, g, lc, rb2[J]);
-    L.s2.phi[r2 & 3][lc] = row_phi<P>(rb2[J], q);
+    const T ph = row_phi<P>(rb2[J], q);
+    L.s2.phi[r2 & 3][lc] = ph;
+    if constexpr (REC) record2(k, rec1, 0, r2, ph);
   }
   __syncthreads();
   // B
-  if (in_stage(k, r - d, 1)) stage_mu<T, NT>(L.s1, r - d, g, lc, k.c);
-  if (in_stage(k, r2 - d, 5)) stage_mu<T, NT>(L.s2, r2 - d, g, lc, k.c);
+  if (in_stage(k, r - d, 1)) {
+    const T mu = stage_mu<T, NT>(L.s1, r - d, g, lc, k.c);
+    if constexpr (REC) record2(k, rec0, 1, r - d, mu);
+  }
+  if (in_stage(k, r2 - d, 5)) {
+    const T mu = stage_mu<T, NT>(L.s2, r2 - d, g, lc, k.c);
+    if constexpr (REC) record2(k, rec1, 1, r2 - d, mu);
+  }
   __syncthreads();
   // C
-  if (in_stage(k, r - 2 * d, 2))
-    stage_macro<P, NT>(L.s1, rb1[(J + 2) & 3], r - 2 * d, g, lc, k.c, nd1[J & 1]);
-  if (in_stage(k, r2 - 2 * d, 6))
-    stage_macro<P, NT>(L.s2, rb2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c, nd2[J & 1]);
+  if (in_stage(k, r - 2 * d, 2)) {
+    stage_macro<P, NT>(L.s1, rb1[(J + 2) & 3], r - 2 * d, g, lc, k.c, nd1[J & 1], rv);
+    if constexpr (REC) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) record2(k, rec0, 2 + i, r - 2 * d, rv[i]);
+    }
+  }
+  if (in_stage(k, r2 - 2 * d, 6)) {
+    stage_macro<P, NT>(L.s2, rb2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c, nd2[J & 1], rv);
+    if constexpr (REC) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i) record2(k, rec1, 2 + i, r2 - 2 * d, rv[i]);
+    }
+  }
   __syncthreads();
   // D1: row r - 3d into the ring; the words of row r + d into the freed slot
   {
@@ -1350,10 +1390,12 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
 template <int P> struct Fused2Waves { static constexpr int value = 2; };
 template <> struct Fused2Waves<P_F64> { static constexpr int value = 1; };
 
-template <int P, bool BIG>
+// REC: also writes the records of the two states the pass starts from
+// (rec0: the state read, rec1: the state after the first step).
+template <int P, bool BIG, bool REC>
 __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
     Pop<P> in, Pop<P> out, Coef<typename PrecT<P>::T> c, Geom g, int width, int nstrips,
-    int seg_len) {
+    int seg_len, typename PrecT<P>::T* rec0, typename PrecT<P>::T* rec1) {
   using T = typename PrecT<P>::T;
   constexpr int NT = 256;
   __shared__ Fused2Lds<P, NT> L;
@@ -1387,13 +1429,17 @@ __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
   if (in_stage(k, r0, 0)) load_row<P, BIG>(k, phys_row(r0, g), rb1[0]);
   int s = 0;   // ring slot D1 writes in this iteration: iteration index mod 3
   for (int it = 0; it < nit; it += 4) {
-    fused2_iter<P, BIG, 0, NT>(k, r0 + k.d * (it + 0), s, rb1, rb2, nd1, nd2, L);
+    fused2_iter<P, BIG, REC, 0, NT>(k, r0 + k.d * (it + 0), s, rb1, rb2, nd1, nd2, L, rec0,
+                                 rec1);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, 1, NT>(k, r0 + k.d * (it + 1), s, rb1, rb2, nd1, nd2, L);
+    fused2_iter<P, BIG, REC, 1, NT>(k, r0 + k.d * (it + 1), s, rb1, rb2, nd1, nd2, L, rec0,
+                                 rec1);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, 2, NT>(k, r0 + k.d * (it + 2), s, rb1, rb2, nd1, nd2, L);
+    fused2_iter<P, BIG, REC, 2, NT>(k, r0 + k.d * (it + 2), s, rb1, rb2, nd1, nd2, L, rec0,
+                                 rec1);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, 3, NT>(k, r0 + k.d * (it + 3), s, rb1, rb2, nd1, nd2, L);
+    fused2_iter<P, BIG, REC, 3, NT>(k, r0 + k.d * (it + 3), s, rb1, rb2, nd1, nd2, L, rec0,
+                                 rec1);
     s = s == 2 ? 0 : s + 1;
   }
 }
@@ -1571,23 +1617,34 @@ int fused2_resident() {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2_fused<P, false>, 256, 0) !=
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_step2_fused<P, false, false>, 256, 0) !=
       hipSuccess)
     return 0;
   return cus * (per_cu > 0 ? per_cu : 1);
 }
 
+template <int P, bool BIG, bool REC>
+static void launch_fused2_variant(const Pop<P>& i, const Pop<P>& o,
+                                  const Coef<typename PrecT<P>::T>& c, const Geom& g,
+                                  const FusedShape& sh, void* rec0, void* rec1, hipStream_t s) {
+  using T = typename PrecT<P>::T;
+  hipLaunchKernelGGL((k_step2_fused<P, BIG, REC>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads),
+                     0, s, i, o, c, g, sh.width, sh.nstrips, sh.seg_rows, (T*)rec0, (T*)rec1);
+}
+
 template <int P>
 hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
-                              const Geom& g, const FusedShape& sh, hipStream_t s) {
+                              const Geom& g, const FusedShape& sh, void* rec0, void* rec1,
+                              hipStream_t s) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
-  const dim3 grid(sh.nstrips * sh.nseg), block(sh.threads);
-  if (fused_big<P>(g))
-    hipLaunchKernelGGL((k_step2_fused<P, true>), grid, block, 0, s, i, o, c, g, sh.width,
-                       sh.nstrips, sh.seg_rows);
-  else
-    hipLaunchKernelGGL((k_step2_fused<P, false>), grid, block, 0, s, i, o, c, g, sh.width,
-                       sh.nstrips, sh.seg_rows);
+  const bool big = fused_big<P>(g);
+  if (rec0 && rec1) {
+    if (big) launch_fused2_variant<P, true, true>(i, o, c, g, sh, rec0, rec1, s);
+    else launch_fused2_variant<P, false, true>(i, o, c, g, sh, rec0, rec1, s);
+  } else {
+    if (big) launch_fused2_variant<P, true, false>(i, o, c, g, sh, nullptr, nullptr, s);
+    else launch_fused2_variant<P, false, false>(i, o, c, g, sh, nullptr, nullptr, s);
+  }
   return hipGetLastError();
 }
 
@@ -1631,7 +1688,8 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
   template FusedShape fused2_shape<P>(const Geom&, int, int);                                    \
   template int fused2_resident<P>();                                                             \
   template hipError_t launch_step2_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,        \
-                                            const Geom&, const FusedShape&, hipStream_t);        \
+                                            const Geom&, const FusedShape&, void*, void*,        \
+                                            hipStream_t);                                        \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
                                      const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
 

@@ -134,6 +134,14 @@ class Lattice:
         _lib.check(self.lib.lbm_launch_info(self.ctx, out), "lbm_launch_info")
         return dict(zip(("strips", "segments", "seg_rows", "threads"), list(out)))
 
+    def step_records(self, records) -> None:
+        """len(records) steps, writing the record of the state step k starts
+        from into records[k] (uint8 device tensors of record_bytes each)."""
+        for r in records:
+            assert r.numel() >= self.record_bytes and r.is_contiguous()
+        arr = (c_void_p * max(len(records), 1))(*[_ptr(r) for r in records])
+        _lib.check(self.lib.lbm_step_records(self.ctx, len(records), arr), "lbm_step_records")
+
     def set_pass(self, steps: int, seg_rows: int = 0) -> None:
         """Time steps per fused launch in step() (2: temporal blocking, the
         default for fp32 and fp16 storage; 1: one launch per step)."""

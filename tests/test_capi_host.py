@@ -90,6 +90,7 @@ def test_null_context_calls(lib):
     assert lib.lbm_launch_info(None, (c_int32 * 4)()) == _lib.LBM_EINVAL
     assert lib.lbm_set_pass(None, 2, 0) == _lib.LBM_EINVAL
     assert lib.lbm_pass_info(None, (c_int32 * 5)()) == _lib.LBM_EINVAL
+    assert lib.lbm_step_records(None, 1, (c_void_p * 1)()) == _lib.LBM_EINVAL
     lib.lbm_destroy(None)
     assert lib.lbm_strerror(_lib.LBM_EDIVERGED).decode().startswith("non-finite")
 
