@@ -78,8 +78,9 @@ typedef enum { LBM_BC_PERIODIC = 0, LBM_BC_WALLS_Y = 1 } lbm_bc;
                                  from F_i and p: the same LBE in the form of
                                  an incompressible model, for ablations    */
 #define LBM_FLAG_UNFUSED  2u  /* run the step as four separate kernels that
-                                 materialise phi, mu and p (same results up
-                                 to rounding; used for cross-checks)        */
+                                 materialise phi, mu and p, and the adjoint
+                                 step as three (same results up to
+                                 rounding; used for cross-checks)           */
 
 typedef struct {
   int32_t nx, ny;         /* lattice size; nx >= 3, ny >= 3,

@@ -12,6 +12,10 @@
 //   collision (BGK + F_i, G_i)                node-local Jacobian transpose
 //   streaming (pull, bounce-back)             gather from the neighbour it fed
 //
+// The default adjoint step is one fused kernel (k_adj_fused, below) that
+// sweeps the rows and applies these transposes in a pipeline; the three
+// separate kernels remain for LBM_FLAG_UNFUSED (cross-checks).
+//
 // The adjoint populations are kept in the canonical pre-collision layout
 // ([18][ny][nx], compute type). The forward step at t enters only through
 // its record: phi, mu, p, S = sum f, jx, jy of the state s_t (planes of the
@@ -641,6 +645,376 @@ __global__ __launch_bounds__(256) void k_hat_to(const T* __restrict__ hat, doubl
   }
 }
 
+// ------------------------------------------------------ fused adjoint step
+// The three kernels above in one sweep over the rows of a strip, the
+// transposed stages in the order their dependencies allow (the forward
+// kernel's pipeline run backwards). A workgroup of 256 lanes owns a strip of
+// at most 248 columns plus 4 halo columns on each side (lane lc <-> column
+// x0 - 4 + lc) and a segment of rows; the record rows and the cotangent
+// fields that cross node boundaries live in LDS rings. In the iteration that
+// brings in record row r (direction d):
+//   0:  record row r (phi, mu, p, S, jx, jy) into the rings
+//   A': collision transpose of row r - d (post-collision cotangents gathered
+//       from the incoming cotangents, prefetched by the previous iteration);
+//       grad p cotangent into LDS, the rest kept in registers
+//   B': pressure cotangent of row r - 2d (grad^T of the grad p cotangents of
+//       rows r - 3d .. r - d), the macroscopic transposes, f cotangents out;
+//       grad mu, lambda D and grad phi cotangents into LDS
+//   C': mu cotangent of row r - 3d (grad^T, lap^T), then mu(phi)
+//   D': phi cotangent of row r - 4d (grad^T, lap^T), g cotangents out; the
+//       gathers of row r's post-collision cotangents and the record row
+//       r + d are issued here for the next iteration.
+// Stage s (A' = 1 ... D' = 4) runs on lanes [s, wi + 8 - s) and rows
+// [y0 - 4 + s, y1 + 4 - s); the record rows reach 4 beyond the segment.
+constexpr int AH = 4;
+constexpr int ANT = 256;
+
+template <typename T>
+struct AdjLds {
+  T phi[8][ANT];             // record rows
+  T mu[4][ANT];
+  T p[4][ANT];
+  T sj[4][3][ANT];           // S, jx, jy
+  T gpx[4][ANT], gpy[4][ANT];                // grad p cotangent
+  T gmx[4][ANT], gmy[4][ANT], lmu[4][ANT];   // grad mu cotangent, lambda x D cotangent
+  T grx[4][ANT], gry[4][ANT];                // drho x grad rho cotangent (grad phi part)
+  T lph[4][ANT];                             // -kappa x mu cotangent (lap phi part)
+};
+
+// Planes of T at a stride of Ns elements, through buffer resources: one
+// descriptor for all planes, the plane and row in the scalar offset; BIG
+// (the planes span 4 GiB or more): one descriptor per plane.
+template <typename T, bool BIG>
+struct PlaneArr {
+  char* base;
+  uint32_t ps;   // bytes between planes
+  __amdgpu_buffer_rsrc_t r;
+  __device__ __forceinline__ void init(const T* p, int64_t Ns, int nplanes) {
+    base = (char*)p;
+    ps = (uint32_t)(Ns * (int64_t)sizeof(T));
+    if constexpr (!BIG)
+      r = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)(nplanes * (int64_t)ps), BUF_WORD3);
+  }
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rs(int plane) const {
+    if constexpr (BIG)
+      return __builtin_amdgcn_make_buffer_rsrc(base + (int64_t)plane * ps, 0, (int)ps, BUF_WORD3);
+    else
+      return r;
+  }
+  __device__ __forceinline__ uint32_t so(int plane, uint32_t elem) const {
+    return (BIG ? 0u : (uint32_t)plane * ps) + elem * (uint32_t)sizeof(T);
+  }
+  // element elem_row + col of plane
+  __device__ __forceinline__ T ld(int plane, uint32_t elem_row, uint32_t col) const {
+    return buf_ld<T>(rs(plane), col * (uint32_t)sizeof(T), so(plane, elem_row));
+  }
+  __device__ __forceinline__ void st(int plane, uint32_t elem_row, uint32_t col, T v) const {
+    buf_st<T>(v, rs(plane), col * (uint32_t)sizeof(T), so(plane, elem_row));
+  }
+};
+
+template <typename T, bool BIG>
+struct AdjCtx {
+  PlaneArr<T, BIG> rec, hin, hout;
+  Coef<T> c;
+  Geom g;
+  int lc, x, wi, y0, y1, d;
+  int col[3];
+  bool act;
+  __device__ __forceinline__ bool in(int v, int s) const {
+    return act && lc >= s && lc < wi + 2 * AH - s && v >= y0 - AH + s && v < y1 + AH - s &&
+           (!g.walls || (v >= 0 && v < g.ny));
+  }
+  __device__ __forceinline__ bool owns(int v) const {
+    return act && lc >= AH && lc < wi + AH && v >= y0 && v < y1;
+  }
+  // physical row of virtual row v (the halo reaches a few rows beyond the
+  // lattice: a short uniform loop instead of a division)
+  __device__ __forceinline__ int prow(int v) const {
+    if (g.walls) return v;
+    while (v < 0) v += g.ny;
+    while (v >= g.ny) v -= g.ny;
+    return v;
+  }
+  // +-1 on the bottom / top wall row, 0 elsewhere (uniform over the row)
+  __device__ __forceinline__ int wall(int v) const {
+    return !g.walls ? 0 : (v == 0 ? -1 : (v == g.ny - 1 ? 1 : 0));
+  }
+};
+
+// Post-collision cotangents of row v at this lane's column, gathered from
+// the incoming pre-collision cotangents (as post_hat: i at x + c_i, or
+// opp(i) at x itself beyond a wall). WALL as AdjCtx::wall(v), so the choice
+// per direction is made at compile time; ro[1 + dy]: element offset of row
+// v + dy.
+template <typename T, bool BIG, int WALL, int I = 0>
+__device__ __forceinline__ void gather_post_w(const AdjCtx<T, BIG>& k, const uint32_t ro[3],
+                                              int koff, T out[9]) {
+  if constexpr (I < 9) {
+    constexpr int cx = CXS(I), cy = CYS(I);
+    constexpr bool bounce = (WALL == -1 && cy == -1) || (WALL == 1 && cy == 1);
+    if constexpr (bounce)
+      out[I] = k.hin.ld(koff + OPP(I), ro[1], k.col[1]);
+    else
+      out[I] = k.hin.ld(koff + I, ro[1 + cy], k.col[1 + cx]);
+    gather_post_w<T, BIG, WALL, I + 1>(k, ro, koff, out);
+  }
+}
+
+template <typename T, bool BIG>
+__device__ __forceinline__ void gather_post(const AdjCtx<T, BIG>& k, int v, int koff, T out[9]) {
+  const int w = k.wall(v);
+  const uint32_t nx = (uint32_t)k.g.nx;
+  const uint32_t ro[3] = {w == -1 ? 0u : (uint32_t)k.prow(v - 1) * nx, (uint32_t)k.prow(v) * nx,
+                          w == 1 ? 0u : (uint32_t)k.prow(v + 1) * nx};
+  if (w == -1)
+    gather_post_w<T, BIG, -1>(k, ro, koff, out);
+  else if (w == 1)
+    gather_post_w<T, BIG, 1>(k, ro, koff, out);
+  else
+    gather_post_w<T, BIG, 0>(k, ro, koff, out);
+}
+
+// grad^T (vx, vy) (if GR) + lap^T ws (if LP) at row v, lane lc, from rings
+// of four rows: the terms of stencil_T in the same order. On a wall row
+// (WALL = -1 bottom, +1 top) the source row beyond the wall drops out and
+// the mirrored ghost adds the row itself for the directions into the wall.
+template <typename T, bool GR, bool LP, int WALL, int I>
+__device__ __forceinline__ void gtl_term(const T (*vx)[ANT], const T (*vy)[ANT],
+                                         const T (*ws)[ANT], int v, int lc, T& gacc, T& lacc) {
+  constexpr int cx = CXS(I), cy = CYS(I);
+  constexpr bool src = !((WALL == -1 && cy == 1) || (WALL == 1 && cy == -1));
+  constexpr bool ghost = (WALL == -1 && cy == -1) || (WALL == 1 && cy == 1);
+  const T w3 = T(3.0 * WGT(I)), w6 = T(6.0 * WGT(I));
+  if constexpr (src) {
+    const int ys = (v - cy) & 3;
+    if constexpr (GR) gacc += w3 * (T(cx) * vx[ys][lc - cx] + T(cy) * vy[ys][lc - cx]);
+    if constexpr (LP) lacc += w6 * ws[ys][lc - cx];
+  }
+  if constexpr (ghost) {
+    if constexpr (GR) gacc += w3 * (T(cx) * vx[v & 3][lc - cx] + T(cy) * vy[v & 3][lc - cx]);
+    if constexpr (LP) lacc += w6 * ws[v & 3][lc - cx];
+  }
+}
+
+template <typename T, bool GR, bool LP, int WALL>
+__device__ __forceinline__ T stencil_Tw(const T (*vx)[ANT], const T (*vy)[ANT],
+                                        const T (*ws)[ANT], int v, int lc) {
+  T gacc = T(0), lacc = T(0);
+  gtl_term<T, GR, LP, WALL, 1>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 2>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 3>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 4>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 5>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 6>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 7>(vx, vy, ws, v, lc, gacc, lacc);
+  gtl_term<T, GR, LP, WALL, 8>(vx, vy, ws, v, lc, gacc, lacc);
+  if constexpr (LP) lacc -= T(10.0 / 3.0) * ws[v & 3][lc];
+  return gacc + lacc;
+}
+
+template <typename T, bool GR, bool LP>
+__device__ __forceinline__ T stencil_Tl(const T (*vx)[ANT], const T (*vy)[ANT],
+                                        const T (*ws)[ANT], int v, int lc, int wall) {
+  if (wall == -1) return stencil_Tw<T, GR, LP, -1>(vx, vy, ws, v, lc);
+  if (wall == 1) return stencil_Tw<T, GR, LP, 1>(vx, vy, ws, v, lc);
+  return stencil_Tw<T, GR, LP, 0>(vx, vy, ws, v, lc);
+}
+
+// Forward node state of row v at lane lc from the record rings (fwd_node).
+template <typename T>
+__device__ __forceinline__ void fwd_node_l(const AdjLds<T>& L, int v, int lc, const Coef<T>& c,
+                                           const Geom& g, Macro<T>& m, T& S, T& jx, T& jy,
+                                           T& gmux, T& gmuy, T& lapmu) {
+  S = L.sj[v & 3][0][lc];
+  jx = L.sj[v & 3][1][lc];
+  jy = L.sj[v & 3][2][lc];
+  T w[3][3], gphx, gphy, lapphi;
+  lds3x3<T, ANT>(L.phi, 7, v, g.ny, g.walls, lc, w);
+  stencil(w, gphx, gphy, lapphi);
+  const T ph = w[1][1];
+  lds3x3<T, ANT>(L.mu, 3, v, g.ny, g.walls, lc, w);
+  stencil(w, gmux, gmuy, lapmu);
+  macro_node(ph, w[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
+}
+
+template <typename T, bool BIG, int J>
+__device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<T>& L, T (&rrec)[6],
+                                         T (&hf)[9], T (&hg)[9], NodeBar<T> (&nbr)[2],
+                                         T (&fdr)[2][9], T (&p2)[2], T (&m1)[2], T (&p3)[2],
+                                         double (&acc)[4]) {
+  const Geom& g = k.g;
+  const Coef<T>& c = k.c;
+  const int lc = k.lc, d = k.d;
+  const int a = r - d, b = r - 2 * d, cm = r - 3 * d, e = r - 4 * d;
+  // 0: record row r into the rings
+  if (k.in(r, 0)) {
+    L.phi[r & 7][lc] = rrec[R_PHI];
+    L.mu[r & 3][lc] = rrec[R_MU];
+    L.p[r & 3][lc] = rrec[R_P];
+    L.sj[r & 3][0][lc] = rrec[R_S];
+    L.sj[r & 3][1][lc] = rrec[R_JX];
+    L.sj[r & 3][2][lc] = rrec[R_JY];
+  }
+  __syncthreads();
+  // A': collision transpose of row a
+  if (k.in(a, 1)) {
+    T S, jx, jy, gmux, gmuy, lapmu;
+    Macro<T> m;
+    fwd_node_l<T>(L, a, lc, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+    T w[3][3], dpx, dpy, lapp;
+    lds3x3<T, ANT>(L.p, 3, a, g.ny, g.walls, lc, w);
+    stencil(w, dpx, dpy, lapp);
+    collide_node_T(hf, hg, m, dpx, dpy, c, nbr[J & 1]);
+    // the direct part of the f cotangents, (1 - 1/tau_f) times the
+    // post-collision ones, waits for B' in registers
+#pragma unroll
+    for (int i = 0; i < 9; ++i) fdr[J & 1][i] = hf[i];
+    L.gpx[a & 3][lc] = nbr[J & 1].dpx;
+    L.gpy[a & 3][lc] = nbr[J & 1].dpy;
+    if (k.owns(a)) acc[AP_ALPHA] += double(nbr[J & 1].alpha);
+  }
+  __syncthreads();
+  // B': pressure cotangent and the macroscopic transposes of row b
+  if (k.in(b, 2)) {
+    const NodeBar<T>& nb = nbr[(J + 1) & 1];
+    const T b_p = nb.p + stencil_Tl<T, true, false>(L.gpx, L.gpy, nullptr, b, lc, k.wall(b));
+    T S, jx, jy, gmux, gmuy, lapmu;
+    Macro<T> m;
+    fwd_node_l<T>(L, b, lc, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+    T b_rho = nb.rho, b_ux = nb.ux, b_uy = nb.uy;
+    T b_Fx = nb.Fx, b_Fy = nb.Fy, b_drx = nb.drx, b_dry = nb.dry;
+    T b_D = nb.D, b_phi = nb.phi;
+    const T b_S = b_p;
+    b_ux += b_p * m.drx * T(1.0 / 6.0);
+    b_uy += b_p * m.dry * T(1.0 / 6.0);
+    b_drx += b_p * m.ux * T(1.0 / 6.0);
+    b_dry += b_p * m.uy * T(1.0 / 6.0);
+    b_rho -= b_p * c.gamma * m.D * T(1.0 / 6.0);
+    b_D -= b_p * c.gamma * m.rho * T(1.0 / 6.0);
+    const T inv = T(3) / m.rho;
+    const T b_jx = b_ux * inv, b_jy = b_uy * inv;
+    b_Fx += b_ux * inv * T(1.0 / 6.0);
+    b_Fy += b_uy * inv * T(1.0 / 6.0);
+    const T b_inv = b_ux * (jx + m.Fx * T(1.0 / 6.0)) + b_uy * (jy + m.Fy * T(1.0 / 6.0));
+    b_rho -= b_inv * inv / m.rho;
+    b_phi -= b_Fx * gmux + b_Fy * gmuy;
+    L.gmx[b & 3][lc] = -m.phi * b_Fx;
+    L.gmy[b & 3][lc] = -m.phi * b_Fy;
+    b_rho += b_Fx * c.gx + b_Fy * c.gy;
+    L.lmu[b & 3][lc] = c.lam * b_D;
+    L.grx[b & 3][lc] = c.drho * b_drx;
+    L.gry[b & 3][lc] = c.drho * b_dry;
+    p2[J & 1] = b_phi + c.drho * b_rho;
+    m1[J & 1] = nb.mu;
+    if (k.owns(b)) {
+      const uint32_t ro = (uint32_t)(b * g.nx);
+#pragma unroll
+      for (int i = 0; i < 9; ++i)
+        k.hout.st(i, ro, (uint32_t)k.x,
+                  fdr[(J + 1) & 1][i] + b_S + T(CXS(i)) * b_jx + T(CYS(i)) * b_jy);
+      acc[AP_LAMBDA] += double(b_D) * double(lapmu);
+    }
+  }
+  __syncthreads();
+  // the direct part of D's g cotangents is gathered again (as in
+  // k_adj_final) rather than kept from A' for three iterations
+  T he[9];
+  if (k.owns(e)) gather_post<T>(k, e, 9, he);
+  // C': mu cotangent of row cm, then mu(phi)
+  if (k.in(cm, 3)) {
+    const T b_mu = m1[(J + 1) & 1] + stencil_Tl<T, true, true>(L.gmx, L.gmy, L.lmu, cm, lc, k.wall(cm));
+    T w[3][3], gx, gy, lapphi;
+    lds3x3<T, ANT>(L.phi, 7, cm, g.ny, g.walls, lc, w);
+    stencil(w, gx, gy, lapphi);
+    const T ph = w[1][1];
+    const T dbulk = c.beta4 * (T(3) * ph * ph - T(3) * ph + T(0.5));
+    p3[J & 1] = p2[(J + 1) & 1] + b_mu * dbulk;
+    L.lph[cm & 3][lc] = -c.kappa * b_mu;
+    if (k.owns(cm)) {
+      acc[AP_BETA] += double(b_mu) * 4.0 * double((ph - T(1)) * ph * (ph - T(0.5)));
+      acc[AP_KAPPA] -= double(b_mu) * double(lapphi);
+    }
+  }
+  __syncthreads();
+  // D': phi cotangent of row e, g cotangents out; then the next iteration's
+  // gathers
+  if (k.owns(e)) {
+    const T b_phi = p3[(J + 1) & 1] + stencil_Tl<T, true, true>(L.grx, L.gry, L.lph, e, lc, k.wall(e));
+    const uint32_t ro = (uint32_t)(e * g.nx);
+#pragma unroll
+    for (int i = 0; i < 9; ++i)
+      k.hout.st(9 + i, ro, (uint32_t)k.x, he[i] * (T(1) - c.inv_tau_g) + b_phi);
+  }
+  if (k.in(r, 1)) {
+    gather_post<T>(k, r, 0, hf);
+    gather_post<T>(k, r, 9, hg);
+  }
+  if (k.in(r + d, 0)) {
+    const uint32_t ro = (uint32_t)(k.prow(r + d) * g.nx);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
+  }
+}
+
+template <typename T>
+struct AdjWaves { static constexpr int value = sizeof(T) == 8 ? 1 : 2; };
+
+// BIG: the 18 cotangent planes span 4 GiB or more (one descriptor per plane).
+template <typename T, bool BIG>
+__global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
+    const T* __restrict__ rec, const T* __restrict__ hin, T* __restrict__ hout,
+    double* acc_part, Coef<T> c, Geom g, int width, int nstrips, int seg_len, int ntiles) {
+  __shared__ AdjLds<T> L;
+  AdjCtx<T, BIG> k;
+  k.rec.init(rec, g.Ns, 6);
+  k.hin.init(hin, g.Ns, 18);
+  k.hout.init(hout, g.Ns, 18);
+  k.c = c;
+  k.g = g;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int seg = tile / nstrips, strip = tile - seg * nstrips;
+    const int x0 = strip * width;
+    k.wi = min(width, g.nx - x0);
+    k.y0 = seg * seg_len;
+    k.y1 = min(g.ny, k.y0 + seg_len);
+    k.d = (seg & 1) ? -1 : 1;
+    const int t = threadIdx.x;
+    k.act = t < k.wi + 2 * AH;
+    k.lc = k.act ? t : AH;
+    int xv = (x0 - AH + k.lc) % g.nx;
+    k.x = xv < 0 ? xv + g.nx : xv;
+    k.col[0] = wrap_x(k.x - 1, g.nx);
+    k.col[1] = k.x;
+    k.col[2] = wrap_x(k.x + 1, g.nx);
+    T rrec[6], hf[9], hg[9], fdr[2][9], p2[2], m1[2], p3[2];
+    NodeBar<T> nbr[2];
+    const int r0 = k.d > 0 ? k.y0 - AH : k.y1 + AH - 1;
+    const int nit = (k.y1 - k.y0) + 2 * AH + 1;
+    if (k.in(r0, 0)) {
+      const uint32_t ro = (uint32_t)(k.prow(r0) * g.nx);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
+    }
+    for (int it = 0; it < nit; it += 4) {
+      adj_iter<T, BIG, 0>(k, r0 + k.d * (it + 0), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
+                            acc);
+      adj_iter<T, BIG, 1>(k, r0 + k.d * (it + 1), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
+                            acc);
+      adj_iter<T, BIG, 2>(k, r0 + k.d * (it + 2), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
+                            acc);
+      adj_iter<T, BIG, 3>(k, r0 + k.d * (it + 3), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
+                            acc);
+    }
+    __syncthreads();
+  }
+  block_add(acc[AP_BETA], AP_BETA, acc_part);
+  block_add(acc[AP_KAPPA], AP_KAPPA, acc_part);
+  block_add(acc[AP_LAMBDA], AP_LAMBDA, acc_part);
+  block_add(acc[AP_ALPHA], AP_ALPHA, acc_part);
+}
+
 // ------------------------------------------------------------------ host
 template <typename T>
 Coef<T> coef_of(const CtxView& v) {
@@ -699,10 +1073,41 @@ lbm_status adj_core(const CtxView& v, const T* rec) {
   const T* hin = (const T*)a.hat[a.cur];
   T* hout = (T*)a.hat[a.cur ^ 1];
   const dim3 grid(a.nred), blk(256);
-  hipLaunchKernelGGL(k_adj_cm<T>, grid, blk, 0, v.stream, rec, hin, hout, af, a.part, k, g);
-  hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, rec + (int64_t)R_PHI * g.Ns, af,
-                     a.part, k, g);
-  hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);
+  if (v.prm->flags & LBM_FLAG_UNFUSED) {
+    hipLaunchKernelGGL(k_adj_cm<T>, grid, blk, 0, v.stream, rec, hin, hout, af, a.part, k, g);
+    hipLaunchKernelGGL(k_adj_mu<T>, grid, blk, 0, v.stream, rec + (int64_t)R_PHI * g.Ns, af,
+                       a.part, k, g);
+    hipLaunchKernelGGL(k_adj_final<T>, grid, blk, 0, v.stream, hin, af, hout, k, g);
+  } else {
+    // strips of at most 248 columns; one round of workgroups (every segment
+    // end recomputes 4 rows); at most nred workgroups, one partial slot each
+    const int fw = ANT - 2 * AH;
+    const int nstrips = (g.nx + fw - 1) / fw;
+    const int width = (g.nx + nstrips - 1) / nstrips;
+    if (a.resident <= 0) {
+      int dev = 0, cus = 0, per_cu = 0;
+      if (hipGetDevice(&dev) == hipSuccess &&
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) == hipSuccess &&
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_adj_fused<T, false>, ANT, 0) ==
+              hipSuccess)
+        a.resident = cus * (per_cu > 0 ? per_cu : 1);
+      if (a.resident <= 0) a.resident = 256;
+    }
+    int nseg = a.resident / nstrips;
+    if (nseg < 1) nseg = 1;
+    int seg = (g.ny + nseg - 1) / nseg;
+    if (seg < 16) seg = 16;
+    if (seg > g.ny) seg = g.ny;
+    nseg = (g.ny + seg - 1) / seg;
+    const int ntiles = nstrips * nseg;
+    const int nblk = ntiles < a.nred ? ntiles : a.nred;
+    if (18 * g.Ns * (int64_t)sizeof(T) > (int64_t)UINT32_MAX)
+      hipLaunchKernelGGL((k_adj_fused<T, true>), dim3(nblk), blk, 0, v.stream, rec, hin, hout,
+                         a.part, k, g, width, nstrips, seg, ntiles);
+    else
+      hipLaunchKernelGGL((k_adj_fused<T, false>), dim3(nblk), blk, 0, v.stream, rec, hin, hout,
+                         a.part, k, g, width, nstrips, seg, ntiles);
+  }
   if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
   a.cur ^= 1;
   return LBM_OK;

@@ -34,6 +34,7 @@ struct AdjointState {
   double* part = nullptr;             // 4 regions x nred x 4
   double* acc = nullptr;              // running totals [4] + final outputs [4]
   int nred = 0;
+  int resident = 0;                   // fused adjoint workgroups resident at once
 };
 
 struct CtxView {

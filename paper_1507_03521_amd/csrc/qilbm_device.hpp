@@ -199,6 +199,34 @@ struct Pop {
   }
 };
 
+// Buffer-resource access: a descriptor covers a byte range (loads beyond it
+// return 0, stores beyond it are dropped); the uniform part of an address
+// goes into the scalar offset, the lane's part into the vector offset.
+constexpr int BUF_WORD3 = 0x00020000;
+typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
+
+template <typename S>
+__device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
+  if constexpr (sizeof(S) == 8) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
+  } else if constexpr (sizeof(S) == 4) {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
+  } else {
+    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
+  }
+}
+template <typename S>
+__device__ __forceinline__ void buf_st(S v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
+                                       uint32_t soff) {
+  if constexpr (sizeof(S) == 8) {
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
+  } else if constexpr (sizeof(S) == 4) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
+  } else {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
+  }
+}
+
 // ------------------------------------------------------------- addressing
 __device__ __forceinline__ int wrap_x(int x, int nx) {
   return x < 0 ? x + nx : (x >= nx ? x - nx : x);
@@ -253,6 +281,22 @@ __device__ __forceinline__ void stencil(const T v[3][3], T& gx, T& gy, T& lap) {
   const T sa = (v[1][2] + v[1][0]) + (v[2][1] + v[0][1]);
   const T sd = (v[2][2] + v[0][0]) + (v[0][2] + v[2][0]);
   lap = T(6) * (a * sa + d * sd - T(5.0 / 9.0) * v[1][1]);
+}
+
+// The same stencil's 3x3 neighbourhood from a ring of rows in LDS: row v of
+// the lattice sits in ring[v & mask], lane lc holds the lane's column (the
+// neighbours at lc -+ 1); at a wall the mirrored ghost row is the row itself.
+template <typename T, int NT>
+__device__ __forceinline__ void lds3x3(const T (*ring)[NT], int mask, int v, int ny, int walls,
+                                       int lc, T out[3][3]) {
+  const int vm = (walls && v == 0) ? v : v - 1;
+  const int vp = (walls && v == ny - 1) ? v : v + 1;
+  const T* a = ring[vm & mask];
+  const T* b = ring[v & mask];
+  const T* d = ring[vp & mask];
+  out[0][0] = a[lc - 1]; out[0][1] = a[lc]; out[0][2] = a[lc + 1];
+  out[1][0] = b[lc - 1]; out[1][1] = b[lc]; out[1][2] = b[lc + 1];
+  out[2][0] = d[lc - 1]; out[2][1] = d[lc]; out[2][2] = d[lc + 1];
 }
 
 // Macroscopic state of one node needed by the collision.

@@ -374,8 +374,6 @@ __device__ __forceinline__ int xcd_tile(int bid, int n) {
 // byte offsets (x - 1, x, x + 1). Loads beyond a descriptor's range return 0.
 // Loads return the raw storage word (R), decoded only where the value is
 // first used, so that a prefetched load is not waited for early.
-constexpr int BUF_WORD3 = 0x00020000;
-typedef unsigned int u32x2 __attribute__((__vector_size__(2 * sizeof(unsigned int))));
 
 template <int P> struct BufT;
 template <> struct BufT<P_F64> { using F = double; using G0 = double; using GR = double; using R = double; };
@@ -385,28 +383,6 @@ template <> struct BufT<P_F32> { using F = float; using G0 = int32_t; using GR =
 // FP16 storage: F is the f_0 plane's binary16; GR the 32-bit word that holds
 // f_i (low half) and g_i (high half), i >= 1.
 template <> struct BufT<P_F16> { using F = __half; using G0 = int32_t; using GR = uint32_t; using R = uint32_t; };
-
-template <typename S>
-__device__ __forceinline__ S buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t voff, uint32_t soff) {
-  if constexpr (sizeof(S) == 8) {
-    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b64(r, voff, soff, 0));
-  } else if constexpr (sizeof(S) == 4) {
-    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b32(r, voff, soff, 0));
-  } else {
-    return __builtin_bit_cast(S, __builtin_amdgcn_raw_buffer_load_b16(r, voff, soff, 0));
-  }
-}
-template <typename S>
-__device__ __forceinline__ void buf_st(S v, __amdgpu_buffer_rsrc_t r, uint32_t voff,
-                                       uint32_t soff) {
-  if constexpr (sizeof(S) == 8) {
-    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(u32x2, v), r, voff, soff, 0);
-  } else if constexpr (sizeof(S) == 4) {
-    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(uint32_t, v), r, voff, soff, 0);
-  } else {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(uint16_t, v), r, voff, soff, 0);
-  }
-}
 
 // BIG: a group of population planes (f_0..8 or g_1..8) spans 4 GiB or more,
 // beyond the 32-bit range of one descriptor; every access then builds a
@@ -743,19 +719,6 @@ struct FusedLds {
   T p[4][NT];
   T node[2][NM][NT];   // ux, uy, Fx, Fy, drx, dry, D
 };
-
-template <typename T, int NT>
-__device__ __forceinline__ void lds3x3(const T (*ring)[NT], int mask, int v, int ny, int walls,
-                                       int lc, T out[3][3]) {
-  const int vm = (walls && v == 0) ? v : v - 1;
-  const int vp = (walls && v == ny - 1) ? v : v + 1;
-  const T* a = ring[vm & mask];
-  const T* b = ring[v & mask];
-  const T* d = ring[vp & mask];
-  out[0][0] = a[lc - 1]; out[0][1] = a[lc]; out[0][2] = a[lc + 1];
-  out[1][0] = b[lc - 1]; out[1][1] = b[lc]; out[1][2] = b[lc + 1];
-  out[2][0] = d[lc - 1]; out[2][1] = d[lc]; out[2][2] = d[lc + 1];
-}
 
 __device__ __forceinline__ int phys_row(int v, const Geom& g) {
   if (g.walls) return v;

@@ -18,9 +18,9 @@ def _rel(a, b):
     return float((a - b).abs().max() / b.abs().max().clamp_min(1e-300))
 
 
-def _lattice(pb, phi0, precision="fp64"):
+def _lattice(pb, phi0, precision="fp64", flags=0):
     from paper_1507_03521_amd import Lattice
-    return Lattice(pb.as_dict(), phi0, precision=precision, device="cuda:0")
+    return Lattice(pb.as_dict(), phi0, precision=precision, flags=flags, device="cuda:0")
 
 
 CASES = [(23, 17, wl.PERIODIC, 0.0), (20, 14, wl.WALLS_Y, -2e-5), (300, 9, wl.WALLS_Y, -1e-5)]
@@ -310,6 +310,47 @@ def test_adjoint_step_from_record_matches_raw_state_path(precision, tol):
     (f0, g0, s0, m0), (f1, g1, s1, m1) = out
     assert _rel(f1, f0) <= tol and _rel(g1, g0) <= tol
     assert s1 == pytest.approx(s0, rel=10 * tol) and m1 == pytest.approx(m0, rel=10 * tol)
+
+
+ADJ_SHAPES = [(300, 41, wl.WALLS_Y, -1e-5), (520, 37, wl.PERIODIC, 0.0), (16, 13, wl.WALLS_Y, -1e-5),
+              (3, 3, wl.PERIODIC, 0.0), (249, 20, wl.WALLS_Y, -2e-5)]
+
+
+@pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-5)])
+@pytest.mark.parametrize("nx,ny,bc,gy", ADJ_SHAPES)
+def test_fused_adjoint_matches_three_kernel_path(precision, tol, nx, ny, bc, gy):
+    """The fused adjoint kernel (default) and the three-kernel adjoint
+    (LBM_FLAG_UNFUSED) on the same record and the same incoming cotangents:
+    the same transposes in a different grouping, so the outgoing cotangents
+    agree to rounding (FP64 1e-13, FP32 1e-5 of the largest magnitude) and
+    the parameter sums to 10x that; shapes with one and several strips,
+    ragged tails, walls and a lattice narrower than the halo."""
+    from paper_1507_03521_amd import LBM_FLAG_UNFUSED
+    print(f"case fused adjoint {precision} {nx}x{ny} bc={bc}", flush=True)
+    pb = wl.droplet64().with_(nx=nx, ny=ny, bc=bc, gy=gy, rho_ref=0.5)
+    f, g = wl.random_state(nx, ny, seed=nx + ny)
+    rng = np.random.default_rng(nx)
+    fbar = rng.standard_normal((9, ny, nx))
+    gbar = rng.standard_normal((9, ny, nx))
+    zero = torch.zeros((ny, nx), dtype=torch.float64, device="cuda:0")
+    lat = _lattice(pb, np.full((ny, nx), 0.5), precision=precision)
+    lat.set_state(f, g)
+    rec = lat.step_record()
+    out = []
+    for flags in (0, LBM_FLAG_UNFUSED):
+        la = _lattice(pb, np.full((ny, nx), 0.5), precision=precision, flags=flags)
+        la.adjoint_begin(zero)
+        la.adjoint_set(fbar, gbar)
+        la.adjoint_step_record(rec)
+        la.adjoint_step_record(rec)      # twice: the second reads the first's output
+        out.append(la.adjoint_get())
+    (f0, g0, s0, m0), (f1, g1, s1, m1) = out
+    ef, eg = _rel(f0, f1), _rel(g0, g1)
+    print(f"  fused vs three kernels: rel f {ef:.2e} g {eg:.2e}; sigma {s0:.6e} {s1:.6e}, "
+          f"M {m0:.6e} {m1:.6e}", flush=True)
+    assert ef <= tol and eg <= tol
+    assert s0 == pytest.approx(s1, rel=10 * tol, abs=1e-300)
+    assert m0 == pytest.approx(m1, rel=10 * tol, abs=1e-300)
 
 
 def test_adjoint_seed_reuses_the_workspace():
