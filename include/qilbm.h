@@ -209,10 +209,11 @@ lbm_status lbm_launch_info(const lbm_ctx* ctx, int32_t out[4]);
  * post-collision words stay in on-chip memory and feed the second step, so
  * the populations cross HBM once per two steps; an odd last step of an
  * lbm_step call runs alone. The intermediate state is kept in the storage
- * format, so results agree with steps = 1 (one launch per step) to
- * rounding: the two kernels evaluate the same expressions, but the compiler
- * may fuse multiply-adds differently in each. The exact integer invariant
- * of the stored g holds in both. seg_rows: rows per workgroup
+ * format (FP16 storage: in the FP32 format, binary32 f and Q2.29 g, so the
+ * state is rounded to binary16 once per pass), so results agree with
+ * steps = 1 (one launch per step) to rounding: the two kernels evaluate the
+ * same expressions, but the compiler may fuse multiply-adds differently in
+ * each. The exact integer invariant of the stored g holds in both. seg_rows: rows per workgroup
  * segment of the two-step kernel (0 = automatic: one round of workgroups).
  * LBM_EINVAL for steps other than 1 and 2, or seg_rows < 0. Applies to lbm_step only (not lbm_step_record, not
  * LBM_FLAG_UNFUSED). */

@@ -973,7 +973,9 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
   k.c = c;
   k.g = g;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+  // the first round of tiles XCD-aware (xcd_tile permutes 0 .. gridDim - 1),
+  // later rounds, if any, at a stride of gridDim
+  for (int tile = xcd_tile(blockIdx.x, gridDim.x); tile < ntiles; tile += gridDim.x) {
     const int seg = tile / nstrips, strip = tile - seg * nstrips;
     const int x0 = strip * width;
     k.wi = min(width, g.nx - x0);

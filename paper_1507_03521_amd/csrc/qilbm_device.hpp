@@ -227,6 +227,14 @@ __device__ __forceinline__ void buf_st(S v, __amdgpu_buffer_rsrc_t r, uint32_t v
   }
 }
 
+// Tiles handed out so that blocks that the hardware places on one XCD
+// (consecutive blocks round-robin over 8 XCDs) get consecutive tiles, i.e.
+// neighbouring tiles share that XCD's L2.
+__device__ __forceinline__ int xcd_tile(int bid, int n) {
+  const int q = n >> 3, rem = n & 7, j = bid & 7, pos = bid >> 3;
+  return j * q + (j < rem ? j : rem) + pos;
+}
+
 // ------------------------------------------------------------- addressing
 __device__ __forceinline__ int wrap_x(int x, int nx) {
   return x < 0 ? x + nx : (x >= nx ? x - nx : x);

@@ -359,14 +359,6 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 constexpr int FH = 3;           // halo columns per side
 constexpr int NM = 7;           // node values kept from C to D
 
-// Tiles handed out so that blocks that the hardware places on one XCD
-// (consecutive blocks round-robin over 8 XCDs) get consecutive tiles, i.e.
-// neighbouring tiles share that XCD's L2.
-__device__ __forceinline__ int xcd_tile(int bid, int n) {
-  const int q = n >> 3, rem = n & 7, j = bid & 7, pos = bid >> 3;
-  return j * q + (j < rem ? j : rem) + pos;
-}
-
 // Population access of the fused kernel through buffer resources: one
 // descriptor each for the f planes, the g_0 plane and the g_1..8 planes.
 // The plane and row parts of an address are uniform over a wavefront and go
@@ -943,9 +935,10 @@ __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void 
 // instead of memory; the second step's stages (A2..D2) pull from that ring
 // and store to memory. The state between the two steps never leaves the
 // chip: per two steps the populations are read once and written once. The
-// ring holds exactly the storage words a single step would have written
-// (binary32 f with Q2.29 g and the exact g_0 closure, or the binary16
-// pairs), so a pass computes what two single steps compute.
+// ring holds the words a single FP32 or FP64 step would have written
+// (binary32 f with Q2.29 g and the exact g_0 closure, or binary64), so a
+// pass computes what two single steps compute; FP16 storage keeps its
+// intermediate state in the FP32 format (MidP).
 //
 // Halo: the second collision at the owned columns needs the first step's
 // output 4 columns (and rows) beyond them (its own stencils reach 3, the
@@ -1001,10 +994,18 @@ template <int NT> struct MidRing<P_F64, NT> {
   double g[3][9][NT];
 };
 
+// Format of the state between the two steps: the storage format, except
+// for FP16 storage, whose intermediate state stays in the FP32 format
+// (binary32 f, Q2.29 g with the exact g_0 closure): the binary16
+// conversions of a ring in the storage format made that kernel
+// arithmetic-bound, and the state is rounded to binary16 once per pass.
+template <int P> struct MidP { static constexpr int value = P; };
+template <> struct MidP<P_F16> { static constexpr int value = P_F32; };
+
 template <int P, int NT>
 struct Fused2Lds {
   StageRings<typename PrecT<P>::T, NT> s1, s2;
-  MidRing<P, NT> mid;
+  MidRing<MidP<P>::value, NT> mid;
 };
 
 template <int P, bool BIG>
@@ -1262,12 +1263,13 @@ __device__ __forceinline__ void stage_collide(const StageRings<T, NT>& S, int cr
 
 template <int P, bool BIG, bool REC, int J, int NT>
 __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, int s,
-                                            Row<P> (&rb1)[4], Row<P> (&rb2)[4],
+                                            Row<P> (&rb1)[4], Row<MidP<P>::value> (&rb2)[4],
                                             typename PrecT<P>::T (&nd1)[2][NM],
                                             typename PrecT<P>::T (&nd2)[2][NM],
                                             Fused2Lds<P, NT>& L, typename PrecT<P>::T* rec0,
                                             typename PrecT<P>::T* rec1) {
   using T = typename PrecT<P>::T;
+  constexpr int P2 = MidP<P>::value;   // format of the ring and of rb2
   const Geom& g = k.g;
   const int lc = k.lc, d = k.d;
   const int r2 = r - 5 * d;
@@ -1285,8 +1287,8 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     // 3, 2 and 1 iterations ago
     const int s1 = s == 0 ? 2 : s - 1, s2 = s == 2 ? 0 : s + 1;
     const int sl[3] = {d > 0 ? s : s1, s2, d > 0 ? s1 : s};
-    pull_mid<P, NT>(L.mid, sl, r2, g, lc, rb2[J]);
-    const T ph = row_phi<P>(rb2[J], q);
+    pull_mid<P2, NT>(L.mid, sl, r2, g, lc, rb2[J]);
+    const T ph = row_phi<P2>(rb2[J], q);
     L.s2.phi[r2 & 3][lc] = ph;
     if constexpr (REC) record2(k, rec1, 0, r2, ph);
   }
@@ -1310,7 +1312,7 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     }
   }
   if (in_stage(k, r2 - 2 * d, 6)) {
-    stage_macro<P, NT>(L.s2, rb2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c, nd2[J & 1], rv);
+    stage_macro<P2, NT>(L.s2, rb2[(J + 2) & 3], r2 - 2 * d, g, lc, k.c, nd2[J & 1], rv);
     if constexpr (REC) {
 #pragma unroll
       for (int i = 0; i < 4; ++i) record2(k, rec1, 2 + i, r2 - 2 * d, rv[i]);
@@ -1327,9 +1329,9 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     if (in_stage(k, r + d, 0)) load_row<P, BIG>(k, phys_row(r + d, g), rb1[(J + 1) & 3]);
     if (in_stage(k, cr, 3)) {
       stage_collide<T, NT>(L.s1, cr, g, lc, k.c, nd1[(J + 1) & 1], f, gg);
-      Row<P> o;
-      row_pack<P>(f, gg, phi_q, o);
-      ring_put<P, NT>(L.mid, s, lc, o);
+      Row<P2> o;
+      row_pack<P2>(f, gg, phi_q, o);
+      ring_put<P2, NT>(L.mid, s, lc, o);
     }
   }
   // D2: row r - 8d to memory
@@ -1338,8 +1340,8 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     if (in_stage(k, cr, 7)) {
       T f[9], gg[9];
       int32_t phi_q;
-      row_phi<P>(rb2[(J + 1) & 3], phi_q);
-      row_unpack<P>(rb2[(J + 1) & 3], f, gg);
+      row_phi<P2>(rb2[(J + 1) & 3], phi_q);
+      row_unpack<P2>(rb2[(J + 1) & 3], f, gg);
       stage_collide<T, NT>(L.s2, cr, g, lc, k.c, nd2[(J + 1) & 1], f, gg);
       store_node2<P, BIG>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
     }
@@ -1385,7 +1387,8 @@ __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
   k.col[0] = (uint32_t)wrap_x(k.x - 1, g.nx);
   k.col[1] = (uint32_t)k.x;
   k.col[2] = (uint32_t)wrap_x(k.x + 1, g.nx);
-  Row<P> rb1[4], rb2[4];
+  Row<P> rb1[4];
+  Row<MidP<P>::value> rb2[4];
   T nd1[2][NM], nd2[2][NM];
   const int r0 = k.d > 0 ? k.y0 - FH2 : k.y1 + FH2 - 1;
   const int nit = (k.y1 - k.y0) + 2 * FH2 + 1;

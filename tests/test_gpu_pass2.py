@@ -2,12 +2,13 @@
 FP32; FP16 storage on request).
 
 The two-step kernel keeps the first step's post-collision populations on
-chip in their storage format (binary32 f with Q2.29 g, or the binary16
-pairs) and runs the second step on them. It evaluates the same expressions
-as the one-step kernel, but the compiler contracts multiply-adds per kernel
-(measured: with contraction off the two write identical bytes), so the two
-agree to rounding, and both conserve the exact integer total of the stored
-g. Checked here against the FP64 oracle and against one step per launch, on
+chip (FP64 and FP32 in their storage format, binary64 or binary32 f with
+Q2.29 g; FP16 storage in that FP32 format, so it rounds to binary16 once
+per pass) and runs the second step on them. It evaluates the same
+expressions as the one-step kernel, but the compiler contracts
+multiply-adds per kernel (measured: with contraction off the two write
+identical bytes), so the two agree to rounding (FP16 storage: to binary16
+rounding), and both conserve the exact integer total of the stored g. Checked here against the FP64 oracle and against one step per launch, on
 lattices with one strip and with several ragged strips, periodic and
 walled, narrower than the kernel's 7-column halo, with segment lengths from
 1 row to the whole lattice, for even and odd step counts, and at the full
