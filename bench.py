@@ -4,8 +4,8 @@ Workload: the 2048 x 8192 Rayleigh-Taylor problem between bounce-back walls
 (Atwood 0.5, Re 3000, Pe 1000, W 4), synthetic initial interface, no
 datasets. A step is one coupled f+g update of the whole lattice (moments,
 chemical potential, gradients, force, velocity, pressure, both collisions,
-streaming). FP32 runs two steps per launch of the fused kernel (the state
-between them stays on chip); FP64 and FP16 storage one step per launch.
+streaming). FP64 and FP32 run two steps per launch of the fused kernel
+(the state between them stays on chip); FP16 storage one step per launch.
 
 Printed: ONE JSON line. ``value`` is the FP32 rate in MLUPS (million lattice
 updates per second); the line also carries the FP64 and FP16-storage rates
@@ -330,7 +330,7 @@ def main():
     ap.add_argument("--seg-rows", type=int, default=0)
     ap.add_argument("--pass-steps", type=int, choices=[1, 2], default=0,
                     help="time steps per fused launch (default: the library's choice per "
-                         "precision: 2 for fp32, 1 otherwise)")
+                         "precision: 2 for fp64 and fp32, 1 for fp16 storage)")
     ap.add_argument("--only", choices=["fp32", "fp64", "fp16"], default=None,
                     help="time one precision only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -385,7 +385,7 @@ def main():
         log(f"timing {prec}: {args.steps} steps after {args.warmup} warm-up")
         ms, phi, m0, m1, info = run_precision(pb, phi0, prec, args.steps, args.warmup,
                                               args.seg_rows,
-                                              args.pass_steps if prec != "fp64" else 0)
+                                              args.pass_steps)
         res[prec] = dict(ms=ms, phi=phi, m0=m0, m1=m1, info=info)
         log(f"  {prec}: {ms:.4f} ms/step, {N / ms / 1e3:.1f} MLUPS, launch {info}")
 
