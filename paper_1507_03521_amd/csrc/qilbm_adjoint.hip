@@ -838,11 +838,16 @@ __device__ __forceinline__ void fwd_node_l(const AdjLds<T>& L, int v, int lc, co
   macro_node(ph, w[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
 }
 
+// Whether the direct part of the g cotangents waits from A' to D' in
+// registers (FP32) or is gathered again in D' (FP64, whose registers are
+// full; the values are the same).
+template <typename T> struct KeepGd { static constexpr bool value = sizeof(T) == 4; };
+
 template <typename T, bool BIG, int J>
 __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<T>& L, T (&rrec)[6],
                                          T (&hf)[9], T (&hg)[9], NodeBar<T> (&nbr)[2],
-                                         T (&fdr)[2][9], T (&p2)[2], T (&m1)[2], T (&p3)[2],
-                                         double (&acc)[4]) {
+                                         T (&fdr)[2][9], T (&gdr)[4][9], T (&p2)[2], T (&m1)[2],
+                                         T (&p3)[2], double (&acc)[4]) {
   const Geom& g = k.g;
   const Coef<T>& c = k.c;
   const int lc = k.lc, d = k.d;
@@ -869,7 +874,10 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     // the direct part of the f cotangents, (1 - 1/tau_f) times the
     // post-collision ones, waits for B' in registers
 #pragma unroll
-    for (int i = 0; i < 9; ++i) fdr[J & 1][i] = hf[i];
+    for (int i = 0; i < 9; ++i) {
+      fdr[J & 1][i] = hf[i];
+      if constexpr (KeepGd<T>::value) gdr[J & 3][i] = hg[i];
+    }
     L.gpx[a & 3][lc] = nbr[J & 1].dpx;
     L.gpy[a & 3][lc] = nbr[J & 1].dpy;
     if (k.owns(a)) acc[AP_ALPHA] += double(nbr[J & 1].alpha);
@@ -917,10 +925,9 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     }
   }
   __syncthreads();
-  // the direct part of D's g cotangents is gathered again (as in
-  // k_adj_final) rather than kept from A' for three iterations
   T he[9];
-  if (k.owns(e)) gather_post<T>(k, e, 9, he);
+  if constexpr (!KeepGd<T>::value)
+    if (k.owns(e)) gather_post<T>(k, e, 9, he);
   // C': mu cotangent of row cm, then mu(phi)
   if (k.in(cm, 3)) {
     const T b_mu = m1[(J + 1) & 1] + stencil_Tl<T, true, true>(L.gmx, L.gmy, L.lmu, cm, lc, k.wall(cm));
@@ -944,7 +951,8 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     const uint32_t ro = (uint32_t)(e * g.nx);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      k.hout.st(9 + i, ro, (uint32_t)k.x, he[i] * (T(1) - c.inv_tau_g) + b_phi);
+      k.hout.st(9 + i, ro, (uint32_t)k.x,
+                (KeepGd<T>::value ? gdr[(J + 1) & 3][i] : he[i] * (T(1) - c.inv_tau_g)) + b_phi);
   }
   if (k.in(r, 1)) {
     gather_post<T>(k, r, 0, hf);
@@ -990,7 +998,7 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
     k.col[0] = wrap_x(k.x - 1, g.nx);
     k.col[1] = k.x;
     k.col[2] = wrap_x(k.x + 1, g.nx);
-    T rrec[6], hf[9], hg[9], fdr[2][9], p2[2], m1[2], p3[2];
+    T rrec[6], hf[9], hg[9], fdr[2][9], gdr[4][9], p2[2], m1[2], p3[2];
     NodeBar<T> nbr[2];
     const int r0 = k.d > 0 ? k.y0 - AH : k.y1 + AH - 1;
     const int nit = (k.y1 - k.y0) + 2 * AH + 1;
@@ -1000,14 +1008,14 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
       for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
     }
     for (int it = 0; it < nit; it += 4) {
-      adj_iter<T, BIG, 0>(k, r0 + k.d * (it + 0), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
-                            acc);
-      adj_iter<T, BIG, 1>(k, r0 + k.d * (it + 1), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
-                            acc);
-      adj_iter<T, BIG, 2>(k, r0 + k.d * (it + 2), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
-                            acc);
-      adj_iter<T, BIG, 3>(k, r0 + k.d * (it + 3), L, rrec, hf, hg, nbr, fdr, p2, m1, p3,
-                            acc);
+      adj_iter<T, BIG, 0>(k, r0 + k.d * (it + 0), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+                            p3, acc);
+      adj_iter<T, BIG, 1>(k, r0 + k.d * (it + 1), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+                            p3, acc);
+      adj_iter<T, BIG, 2>(k, r0 + k.d * (it + 2), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+                            p3, acc);
+      adj_iter<T, BIG, 3>(k, r0 + k.d * (it + 3), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+                            p3, acc);
     }
     __syncthreads();
   }
