@@ -281,6 +281,88 @@ def test_step_records_match_steps_and_oracle(precision, tol, per_pass):
             state = O.step(*state, co)
 
 
+def test_step_records_unfused_path():
+    """lbm_step_records with LBM_FLAG_UNFUSED (one launch sequence per step,
+    records from the unfused kernels): the raw state equals lbm_step's
+    bitwise and the records equal those of the fused two-step passes to
+    rounding (FP64 1e-13)."""
+    from paper_1507_03521_amd import LBM_FLAG_UNFUSED
+    nx, ny, n = 120, 37, 4
+    pb = wl.droplet64().with_(nx=nx, ny=ny, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5)
+    f, g = wl.random_state(nx, ny, seed=23)
+    recs, raws = [], []
+    for flags in (LBM_FLAG_UNFUSED, 0):
+        a = _lattice(pb, np.full((ny, nx), 0.5), flags=flags)
+        b = _lattice(pb, np.full((ny, nx), 0.5), flags=flags)
+        a.set_state(f, g)
+        b.set_state(f, g)
+        r = [torch.empty(a.record_bytes, dtype=torch.uint8, device="cuda:0") for _ in range(n)]
+        a.step_records(r)
+        b.step(n)
+        assert torch.equal(a.save_raw(), b.save_raw())
+        recs.append(r)
+        raws.append(a.save_raw())
+    Ns = recs[0][0].numel() // 48
+    for k in range(n):
+        u = recs[0][k].view(torch.float64)[:6 * Ns].view(6, Ns)[:, :nx * ny]
+        v = recs[1][k].view(torch.float64)[:6 * Ns].view(6, Ns)[:, :nx * ny]
+        for j in range(6):
+            assert _rel(u[j], v[j]) <= 1e-13, (k, j)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_step_records_large_lattice(precision):
+    """Past the 4 GiB plane-group limit (the recording two-step kernel then
+    addresses every plane with its own descriptor): two steps with records
+    leave the raw state of two plain steps bitwise, and the two records
+    match those of the unfused kernels to rounding: near rest p, S and j
+    are small and formed by cancellation, so the bounds are the from-rest
+    ones of the full-size forward checks (FP64 5e-12, FP32 2e-3 of each
+    field's largest magnitude)."""
+    from paper_1507_03521_amd import LBM_FLAG_UNFUSED
+    nx, ny = (4000, 15000) if precision == "fp64" else (8000, 15000)
+    print(f"case step records large {precision} {nx}x{ny}", flush=True)
+    pb = wl.rt2048().with_(nx=nx, ny=ny)
+    dev = torch.device("cuda:0")
+    y = torch.arange(ny, device=dev, dtype=torch.float64)[:, None]
+    x = torch.arange(nx, device=dev, dtype=torch.float64)[None, :]
+    phi0 = 0.5 + 0.5 * torch.tanh(2.0 * (y - ny / 2 - 40.0 * torch.cos(2 * math.pi * 3 * x / nx))
+                                  / pb.W)
+    del x, y
+    dt = torch.float64 if precision == "fp64" else torch.float32
+    tol = 5e-12 if precision == "fp64" else 2e-3
+    out = []
+    for flags in (0, LBM_FLAG_UNFUSED):
+        lat = _lattice(pb, phi0, precision=precision, flags=flags)
+        lat.step(1)
+        recs = [torch.empty(lat.record_bytes, dtype=torch.uint8, device=dev) for _ in range(2)]
+        if flags == 0:
+            ref = _lattice(pb, phi0, precision=precision)
+            ref.step(1)
+            ref.step(2)          # the same launches: one step, then one pair
+            lat.step_records(recs)
+            assert lat.pass_info()["steps"] == 2
+            assert torch.equal(lat.save_raw(), ref.save_raw())
+            ref.close()
+            del ref
+        else:
+            lat.step_records(recs)
+        out.append(recs)
+        lat.close()
+        del lat
+        torch.cuda.empty_cache()
+    Ns = out[0][0].numel() // (6 * (8 if precision == "fp64" else 4))
+    N = nx * ny
+    for k in range(2):
+        u = out[0][k].view(dt)[:6 * Ns].view(6, Ns)[:, :N]
+        v = out[1][k].view(dt)[:6 * Ns].view(6, Ns)[:, :N]
+        for j in range(6):
+            e = float((u[j] - v[j]).abs().max() / v[j].abs().max().clamp_min(1e-300))
+            assert e <= tol, (k, j, e)
+    del out
+    torch.cuda.empty_cache()
+
+
 @pytest.mark.parametrize("precision,tol", [("fp64", 1e-13), ("fp32", 1e-4), ("fp16", 1e-4)])
 def test_adjoint_step_from_record_matches_raw_state_path(precision, tol):
     """One adjoint step from a record (lbm_step_record) equals the step from
