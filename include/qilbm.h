@@ -34,8 +34,8 @@
  *     The library never allocates or frees device memory; all state lives
  *     in the caller's workspace. The library owns only the host context.
  *   Streams: every call enqueues its work on the context's HIP stream and
- *     returns without synchronising, except lbm_mass (host output) and
- *     lbm_adjoint_init (host output), which synchronise that stream.
+ *     returns without synchronising, except lbm_mass, lbm_adjoint_init and
+ *     lbm_adjoint_get (host outputs), which synchronise that stream.
  *   Errors: every function returns an lbm_status; arguments are validated
  *     before any device work, and nothing is enqueued when validation fails.
  *     Kernel-launch failures return LBM_EDEVICE. No exception or abort
