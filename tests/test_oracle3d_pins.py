@@ -1,0 +1,221 @@
+"""Pins of the three-dimensional oracle (D3Q19 form of Sec. III) against
+what the lattice and the mathematics fix, independently of its own code:
+the lattice's isotropy, the Appendix moment identities with three velocity
+components, the Fourier symbols of the stencils (closed forms summed over an
+independently enumerated velocity set), mass conservation, fixed points and
+symmetries, walls as a mirror-doubled periodic lattice, an independent
+brute-force implementation (tests/brute3d.py), and the Laplace law
+Delta P = 2 sigma / R of a spherical droplet.
+"""
+import itertools
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import brute3d as B
+import workloads as wl
+from oracle import qilbm_oracle3d as O
+
+torch.set_num_threads(4)
+
+
+def _co(pb, **kw):
+    return O.coefficients(pb.rho_A, pb.rho_B, pb.sigma, pb.W, pb.M, pb.tau_f, pb.tau_g,
+                          pb.gx, pb.gy, pb.gz, pb.ref_density, pb.bc, **kw)
+
+
+def test_d3q19_lattice_isotropy():
+    c = np.array(O.C, dtype=float)
+    w = np.array(O.WEIGHT)
+    assert len(O.C) == 19 and len(set(O.C)) == 19
+    assert sorted(map(tuple, c)) == sorted(B.VEL)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.allclose((w[:, None] * c).sum(0), 0.0)
+    # second moments c_s^2 delta, fourth moments c_s^4 (dd + dd + dd)
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, c, c), O.CS2 * np.eye(3))
+    m4 = np.einsum("i,ia,ib,ic,id->abcd", w, c, c, c, c)
+    d = np.eye(3)
+    iso = O.CS2 ** 2 * (np.einsum("ab,cd->abcd", d, d) + np.einsum("ac,bd->abcd", d, d)
+                        + np.einsum("ad,bc->abcd", d, d))
+    assert np.allclose(m4, iso)
+    for i, j in enumerate(O.OPPOSITE):
+        assert tuple(-a for a in O.C[i]) == O.C[j]
+
+
+def test_moment_identities_3d():
+    """sum f^eq = p, sum c f^eq = c_s^2 rho u, sum g^eq = phi, sum c g^eq =
+    phi u, sum F_i = c_s^2 (u.grad rho - rho gamma D), sum c F_i = c_s^2 F,
+    sum G_i = 0, sum c G_i = (phi/rho)(F - grad p) (Appendix, with Gamma_i =
+    1 + s_i), at random node values."""
+    rng = np.random.default_rng(5)
+    n = (6,)
+    t = lambda s=1.0: torch.tensor(s * rng.standard_normal(n))
+    co = O.coefficients(1.0, 0.3, 0.01, 4.0, 0.1, 0.8, 0.8)
+    phi = torch.tensor(rng.random(n))
+    rho, p, mu, D = O.density(phi, co), t(1e-2), t(1e-3), t(1e-4)
+    u, F, dr, dp = (t(1e-2), t(1e-2), t(1e-2)), (t(), t(), t()), (t(), t(), t()), (t(), t(), t())
+    c = [torch.tensor(float(v)) for v in range(1)]
+    feq = [O.f_equilibrium(i, p, rho, u) for i in range(O.Q)]
+    geq = [O.g_equilibrium(i, phi, mu, u, co) for i in range(O.Q)]
+    Fi = [O.f_source(i, u, F, dr, rho, D, co) for i in range(O.Q)]
+    Gi = [O.g_source(i, phi, rho, u, dp, F) for i in range(O.Q)]
+
+    def first(vals, a):
+        return sum(O.C[i][a] * vals[i] for i in range(O.Q))
+
+    close = lambda x, y: torch.allclose(x, y, rtol=1e-12, atol=1e-15)
+    assert close(sum(feq), p)
+    assert close(sum(geq), phi)
+    assert close(sum(Fi), O.CS2 * (sum(u[a] * dr[a] for a in range(3)) - rho * co.gamma * D))
+    assert close(sum(Gi), torch.zeros_like(phi))
+    for a in range(3):
+        assert close(first(feq, a), O.CS2 * rho * u[a])
+        assert close(first(geq, a), phi * u[a])
+        assert close(first(Fi, a), O.CS2 * F[a])
+        assert close(first(Gi, a), (phi / rho) * (F[a] - dp[a]))
+
+
+def test_stencil_fourier_symbols_3d():
+    """On a periodic lattice a plane wave exp(i k.x) is an eigenfunction of
+    both stencils; their symbols, summed over brute3d's independent velocity
+    table, are (1/c_s^2) sum_i w_i c_i i sin(k.c_i) and (2/c_s^2) sum_i w_i
+    (cos(k.c_i) - 1); the Laplacian's is -|k|^2 (1 + O(k^2)) in every
+    direction."""
+    nx, ny, nz = 16, 12, 10
+    x, y, z = np.meshgrid(np.arange(nx), np.arange(ny), np.arange(nz), indexing="xy")
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    for m in [(1, 0, 0), (0, 1, 0), (0, 0, 1), (1, 2, 3), (3, 1, 2), (5, 4, 2)]:
+        k = 2 * math.pi * np.array([m[0] / nx, m[1] / ny, m[2] / nz])
+        psi = torch.tensor(np.exp(1j * (k[0] * x + k[1] * y + k[2] * z)))
+        lap_sym = 2.0 / B.CS2 * sum(B.W[i] * (math.cos(float(np.dot(k, c))) - 1.0)
+                                    for i, c in enumerate(B.VEL))
+        grad_sym = [1.0 / B.CS2 * sum(B.W[i] * c[a] * 1j * math.sin(float(np.dot(k, c)))
+                                      for i, c in enumerate(B.VEL)) for a in range(3)]
+        lp = O.lap(psi, O.PERIODIC)
+        assert torch.allclose(lp, lap_sym * psi, atol=1e-12)
+        gr = O.grad(psi, O.PERIODIC)
+        for a in range(3):
+            assert torch.allclose(gr[a], grad_sym[a] * psi, atol=1e-12)
+    # isotropy of the leading term on a long lattice
+    n = 200
+    for dirn in [(1, 0, 0), (1, 1, 0), (1, 1, 1), (2, 1, 0)]:
+        k = 2 * math.pi / n * np.array(dirn, dtype=float)
+        sym = 2.0 / B.CS2 * sum(B.W[i] * (math.cos(float(np.dot(k, c))) - 1.0)
+                                for i, c in enumerate(B.VEL))
+        assert sym == pytest.approx(-np.dot(k, k), rel=3e-3)
+
+
+def _random_state(pb, seed):
+    f, g = wl.random_state3d(pb.nx, pb.ny, pb.nz, seed=seed)
+    return torch.tensor(f), torch.tensor(g)
+
+
+def _small(bc, g=(0.0, 0.0, 0.0)):
+    return wl.droplet3d(6).with_(nx=6, ny=5, nz=7, bc=bc, gx=g[0], gy=g[1], gz=g[2],
+                                 rho_ref=0.5)
+
+
+@pytest.mark.parametrize("bc", [wl.PERIODIC, wl.WALLS_Z])
+def test_mass_conservation_3d(bc):
+    pb = _small(bc, (1e-4, 0.0, -2e-4))
+    co = _co(pb)
+    f, g = _random_state(pb, 3)
+    m0 = O.mass(f, g, co)
+    f, g = O.run(None, co, 5, state=(f, g))
+    m1 = O.mass(f, g, co)
+    assert m1[0] == pytest.approx(m0[0], rel=1e-14)
+    assert m1[1] == pytest.approx(m0[1], rel=1e-14)
+
+
+def test_uniform_state_is_fixed_point_3d():
+    pb = _small(wl.PERIODIC)
+    co = _co(pb)
+    phi0 = np.full((pb.nz, pb.ny, pb.nx), 0.37)
+    f, g = O.initial_state(phi0, co)
+    f1, g1 = O.run(None, co, 3, state=(f, g))
+    # f stays 0; g moves only by the rounding of phi = sum g (a few ulp of 0.37)
+    assert float((f1 - f).abs().max()) <= 1e-16
+    assert float((g1 - g).abs().max()) <= 2e-15
+
+
+def test_translation_is_bitwise_3d():
+    pb = _small(wl.PERIODIC, (1e-4, 2e-4, -1e-4))
+    co = _co(pb)
+    f, g = _random_state(pb, 4)
+    a = O.run(None, co, 3, state=(f, g))
+    sh = (2, 1, 3)
+    b = O.run(None, co, 3, state=(torch.roll(f, sh, dims=(1, 2, 3)),
+                                 torch.roll(g, sh, dims=(1, 2, 3))))
+    assert torch.equal(torch.roll(a[0], sh, dims=(1, 2, 3)), b[0])
+    assert torch.equal(torch.roll(a[1], sh, dims=(1, 2, 3)), b[1])
+
+
+def test_wall_stencils_equal_mirror_doubled_periodic_3d():
+    """The mirrored ghost planes at walls are the periodic stencils on the
+    field doubled by reflection about z = nz - 1/2 (an arbitrary field)."""
+    rng = np.random.default_rng(8)
+    v = torch.tensor(rng.standard_normal((7, 5, 6)))
+    dbl = torch.cat([v, torch.flip(v, dims=(0,))], dim=0)
+    assert torch.allclose(O.lap(v, O.WALLS_Z), O.lap(dbl, O.PERIODIC)[:7], atol=1e-14)
+    for a, b in zip(O.grad(v, O.WALLS_Z), O.grad(dbl, O.PERIODIC)):
+        assert torch.allclose(a, b[:7], atol=1e-14)
+
+
+def test_walls_equal_mirror_doubled_periodic_for_layered_states_3d():
+    """For a state that depends on z only (no in-plane force), half-way
+    bounce-back coincides with specular reflection at the wall, so a walled
+    lattice evolves exactly as the periodic lattice doubled by reflection in
+    z: 30 steps from a layered initial interface."""
+    pb = wl.droplet3d(4).with_(nx=4, ny=3, nz=10, bc=wl.WALLS_Z)
+    z = np.arange(pb.nz, dtype=float)[:, None, None] * np.ones((1, pb.ny, pb.nx))
+    phi0 = 0.5 + 0.45 * np.tanh(2.0 * (z - 3.7) / pb.W) * np.cos(z / 3.0)
+    a = O.run(phi0, _co(pb), 30)
+    pp = pb.with_(nz=2 * pb.nz, bc=wl.PERIODIC)
+    mirror = [O.C.index((c[0], c[1], -c[2])) for c in O.C]
+    b = O.run(np.concatenate([phi0, phi0[::-1]], axis=0), _co(pp), 30)
+    assert float((a[0] - b[0][:, :pb.nz]).abs().max()) <= 1e-15
+    assert float((a[1] - b[1][:, :pb.nz]).abs().max()) <= 1e-14
+    # the upper half is the mirror image
+    assert float((b[1][mirror][:, pb.nz:].flip(1) - b[1][:, :pb.nz]).abs().max()) <= 1e-14
+
+
+@pytest.mark.parametrize("bc,g", [(wl.PERIODIC, (0.0, 0.0, 0.0)),
+                                  (wl.WALLS_Z, (1e-4, -5e-5, -2e-4))])
+def test_brute_force_equals_oracle_3d(bc, g):
+    """tests/brute3d.py (plain floats, push streaming, its own velocity
+    order) and the oracle agree over 3 steps on a 4 x 3 x 5 lattice."""
+    pb = wl.droplet3d(4).with_(nx=4, ny=3, nz=5, bc=bc, gx=g[0], gy=g[1], gz=g[2],
+                               rho_ref=0.55)
+    co = _co(pb)
+    f, g0 = _random_state(pb, 9)
+    k = B.params(pb.rho_A, pb.rho_B, pb.sigma, pb.W, pb.M, pb.tau_f, pb.tau_g, g=g,
+                 rho_ref=0.55, walls=bc == wl.WALLS_Z)
+    perm = [O.C.index(c) for c in B.VEL]          # brute index -> oracle index
+    bf = [f[perm[i]].tolist() for i in range(len(B.VEL))]
+    bg = [g0[perm[i]].tolist() for i in range(len(B.VEL))]
+    fo, go = f, g0
+    for _ in range(3):
+        bf, bg = B.step(bf, bg, k)
+        fo, go = O.step(fo, go, co)
+    bft = torch.tensor(bf, dtype=torch.float64)
+    bgt = torch.tensor(bg, dtype=torch.float64)
+    for i in range(len(B.VEL)):
+        assert float((bft[i] - fo[perm[i]]).abs().max()) <= 1e-13 * float(fo.abs().max())
+        assert float((bgt[i] - go[perm[i]]).abs().max()) <= 1e-13
+
+
+def test_laplace_law_3d():
+    """Spherical droplet R = 8 in a 32^3 periodic box (density ratio 10,
+    sigma = 0.01, W = 4) after 800 steps: Delta P R / (2 sigma) within 8 %
+    (the interface width W/R = 1/2 biases the small droplet; the 2-D check
+    uses R = 16)."""
+    pb = wl.droplet3d(32, 8.0)
+    co = _co(pb)
+    with torch.no_grad():
+        f, g = O.run(wl.phi0_3d(pb), co, 800)
+        dP = O.laplace_pressure(f, g, co)
+    ratio = dP * pb.meta["R"] / (2.0 * pb.sigma)
+    print("3-D Laplace: Delta P R / (2 sigma) =", ratio)
+    assert ratio == pytest.approx(1.0, rel=0.08)

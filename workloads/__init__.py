@@ -32,6 +32,9 @@ Problem sets:
 * ``phase_separation`` -- Sec. IV.D: 100x100 perturbed mixture.
 * ``random_state`` -- arbitrary non-equilibrium populations for one-step
   checks.
+* ``Problem3`` sets (D3Q19 form): ``droplet3d`` (static droplet in a
+  periodic cube, Laplace check), ``rt3d`` (Rayleigh-Taylor between walls in
+  z with the two-dimensional problem's settings), ``random_state3d``.
 """
 from __future__ import annotations
 
@@ -284,3 +287,119 @@ def mobility_from_lambda_beta(lambda_beta: float, beta: float) -> float:
     """M = (lambda beta) / beta; beta must come from the caller's own
     free-energy coefficients."""
     return lambda_beta / beta
+
+
+# ------------------------------------------------------------ three dimensions
+# Problems of the D3Q19 form of the scheme. Arrays are float64 numpy arrays of
+# shape (nz, ny, nx) indexed [z, y, x]; population sets (19, nz, ny, nx), slot
+# 0 the rest population.
+
+WALLS_Z = 1
+
+
+@dataclass(frozen=True)
+class Problem3:
+    """Raw parameters of one three-dimensional lattice problem. ``bc`` is
+    PERIODIC (all axes) or WALLS_Z (periodic in x and y, bounce-back walls
+    below plane z = 0 and above plane nz - 1); gravity (gx, gy, gz)."""
+
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    rho_A: float
+    rho_B: float
+    sigma: float
+    W: float
+    M: float
+    tau_f: float
+    tau_g: float
+    gx: float = 0.0
+    gy: float = 0.0
+    gz: float = 0.0
+    rho_ref: float | None = None
+    bc: int = PERIODIC
+    meta: dict = field(default_factory=dict, compare=False)
+
+    @property
+    def ref_density(self) -> float:
+        return self.rho_A if self.rho_ref is None else self.rho_ref
+
+    def with_(self, **kw) -> "Problem3":
+        return replace(self, **kw)
+
+    def as_dict(self) -> dict:
+        return dict(nx=self.nx, ny=self.ny, nz=self.nz, rho_A=self.rho_A, rho_B=self.rho_B,
+                    sigma=self.sigma, W=self.W, M=self.M, tau_f=self.tau_f,
+                    tau_g=self.tau_g, gx=self.gx, gy=self.gy, gz=self.gz,
+                    rho_ref=self.ref_density, bc=self.bc)
+
+
+def _grid3(nx: int, ny: int, nz: int):
+    z, y, x = np.meshgrid(np.arange(nz, dtype=np.float64), np.arange(ny, dtype=np.float64),
+                          np.arange(nx, dtype=np.float64), indexing="ij")
+    return x, y, z
+
+
+def droplet3d(n: int = 32, R: float = 8.0) -> Problem3:
+    """Static droplet in a periodic cube (the three-dimensional Laplace
+    check, Delta P = 2 sigma / R): density ratio 10, sigma = 0.01, W = 4,
+    M = 0.1, tau_f = tau_g = 0.8, centred."""
+    return Problem3("droplet3d", n, n, n, rho_A=1.0, rho_B=0.1, sigma=0.01, W=4.0, M=0.1,
+                    tau_f=0.8, tau_g=0.8, meta=dict(R=R, xc=n / 2, yc=n / 2, zc=n / 2))
+
+
+def rt3d(nx: int = 256, nz: int = 256) -> Problem3:
+    """Rayleigh-Taylor instability in a box, walls in z: the two-dimensional
+    problem's settings (Atwood 0.5, sqrt(g L) = 0.04, Re = 3000, Pe = 1000,
+    W = 4, L = nx) with a doubly periodic cosine perturbation
+    nz/2 + 0.05 nx (cos 2 pi x / nx + cos 2 pi y / nx)."""
+    L = float(nx)
+    U = 0.04
+    g = U * U / L
+    nu = U * L / 3000.0
+    M = U * L / 1000.0
+    return Problem3("rt3d", nx, nx, nz, rho_A=3.0, rho_B=1.0, sigma=5e-5 * (L / 256.0) ** 2,
+                    W=4.0, M=M, tau_f=3.0 * nu + 0.5, tau_g=1.0, gz=-g, rho_ref=2.0,
+                    bc=WALLS_Z)
+
+
+def phi0_3d(pb: Problem3) -> np.ndarray:
+    x, y, z = _grid3(pb.nx, pb.ny, pb.nz)
+    if pb.name == "droplet3d":
+        r = np.sqrt((x - pb.meta["xc"]) ** 2 + (y - pb.meta["yc"]) ** 2
+                    + (z - pb.meta["zc"]) ** 2)
+        return np.ascontiguousarray(tanh_step(pb.meta["R"] - r, pb.W))
+    if pb.name == "rt3d":
+        h = pb.nz / 2 + 0.05 * pb.nx * (np.cos(2 * math.pi * x / pb.nx)
+                                         + np.cos(2 * math.pi * y / pb.ny))
+        return np.ascontiguousarray(tanh_step(z - h, pb.W))
+    raise KeyError(pb.name)
+
+
+def random_phi3d(nx: int, ny: int, nz: int, seed: int, lo: float = 0.05,
+                 hi: float = 0.95) -> np.ndarray:
+    """Smooth random order parameter in [lo, hi] (a few random Fourier modes)."""
+    rng = np.random.default_rng(seed)
+    x, y, z = _grid3(nx, ny, nz)
+    acc = np.zeros((nz, ny, nx))
+    for _ in range(6):
+        kx, ky, kz = rng.integers(0, 3, size=3)
+        ph = rng.random() * 2.0 * math.pi
+        acc += rng.standard_normal() * np.cos(
+            2 * math.pi * (kx * x / nx + ky * y / ny + kz * z / nz) + ph)
+    acc -= acc.min()
+    acc /= max(acc.max(), 1e-300)
+    return lo + (hi - lo) * acc
+
+
+def random_state3d(nx: int, ny: int, nz: int, seed: int, amp_f: float = 1e-3,
+                   amp_g: float = 2e-3):
+    """Arbitrary pre-collision populations (f, g) of shape (19, nz, ny, nx):
+    the rest slot of g carries a smooth field in [0.05, 0.95], every other
+    slot a small uniform random deviation."""
+    rng = np.random.default_rng(seed + 2000003)
+    g = amp_g * (2.0 * rng.random((19, nz, ny, nx)) - 1.0)
+    g[0] += random_phi3d(nx, ny, nz, seed)
+    f = amp_f * (2.0 * rng.random((19, nz, ny, nx)) - 1.0)
+    return np.ascontiguousarray(f), np.ascontiguousarray(g)
