@@ -1,4 +1,5 @@
-"""ctypes declarations of the C ABI in include/qilbm.h (argument marshalling only)."""
+"""ctypes declarations of the C ABI in include/qilbm.h and include/qilbm3d.h
+(argument marshalling only)."""
 from __future__ import annotations
 
 import ctypes
@@ -24,9 +25,21 @@ class LbmParams(ctypes.Structure):
                 ("bc", c_int32), ("precision", c_int32), ("flags", c_uint32)]
 
 
+class Lbm3Params(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("rho_A", c_double),
+                ("rho_B", c_double), ("sigma", c_double), ("W", c_double), ("M", c_double),
+                ("tau_f", c_double), ("tau_g", c_double), ("gx", c_double), ("gy", c_double),
+                ("gz", c_double), ("rho_ref", c_double), ("bc", c_int32),
+                ("precision", c_int32), ("flags", c_uint32)]
+
+
+LBM3_BC_WALLS_Z = 1
+
 _P = POINTER(LbmParams)
+_P3 = POINTER(Lbm3Params)
 _D = POINTER(c_double)
-# name -> (restype, argtypes); every symbol declared in include/qilbm.h
+# name -> (restype, argtypes); every symbol declared in include/qilbm.h and
+# include/qilbm3d.h
 SIGNATURES = {
     "lbm_workspace_bytes": (c_size_t, [_P]),
     "lbm_coefficients": (c_int32, [_P, _D]),
@@ -58,6 +71,15 @@ SIGNATURES = {
     "lbm_adjoint_get": (c_int32, [c_void_p, c_void_p, c_void_p, _D]),
     "lbm_destroy": (None, [c_void_p]),
     "lbm_strerror": (ctypes.c_char_p, [c_int32]),
+    "lbm3_workspace_bytes": (c_size_t, [_P3]),
+    "lbm3_init": (c_int32, [POINTER(c_void_p), _P3, c_void_p, c_size_t, c_void_p, c_void_p]),
+    "lbm3_step": (c_int32, [c_void_p, c_int64]),
+    "lbm3_moments": (c_int32, [c_void_p] + [c_void_p] * 7),
+    "lbm3_mass": (c_int32, [c_void_p, _D]),
+    "lbm3_get_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "lbm3_set_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "lbm3_time": (c_int64, [c_void_p]),
+    "lbm3_destroy": (None, [c_void_p]),
 }
 
 
@@ -112,3 +134,17 @@ def make_params(p: dict, precision="fp64", flags: int = 0) -> LbmParams:
                      float(p["tau_g"]), float(p.get("gx", 0.0)), float(p.get("gy", 0.0)),
                      float(p["rho_A"] if rho_ref is None else rho_ref), int(p.get("bc", 0)),
                      prec, int(flags))
+
+
+def make_params3(p: dict, precision="fp64", flags: int = 0) -> Lbm3Params:
+    """lbm3_params from a mapping with keys nx, ny, nz, rho_A, rho_B, sigma,
+    W, M, tau_f, tau_g and optionally gx, gy, gz, rho_ref (default rho_A),
+    bc (0 periodic, 1 walls normal to z)."""
+    prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    rho_ref = p.get("rho_ref")
+    return Lbm3Params(int(p["nx"]), int(p["ny"]), int(p["nz"]), float(p["rho_A"]),
+                      float(p["rho_B"]), float(p["sigma"]), float(p["W"]), float(p["M"]),
+                      float(p["tau_f"]), float(p["tau_g"]), float(p.get("gx", 0.0)),
+                      float(p.get("gy", 0.0)), float(p.get("gz", 0.0)),
+                      float(p["rho_A"] if rho_ref is None else rho_ref), int(p.get("bc", 0)),
+                      prec, int(flags))

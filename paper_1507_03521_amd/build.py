@@ -11,7 +11,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libqilbm.so")
-SOURCES = ["qilbm_kernels.hip", "qilbm_capi.hip", "qilbm_adjoint.hip"]
+SOURCES = ["qilbm_kernels.hip", "qilbm_capi.hip", "qilbm_adjoint.hip", "qilbm3d.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

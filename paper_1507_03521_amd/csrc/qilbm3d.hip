@@ -1,0 +1,828 @@
+// Three-dimensional (D3Q19) form of the quasi-incompressible phase-field LBE
+// step (Yang & Guo, Sec. III, every term with three velocity components) for
+// gfx950, and its C ABI (include/qilbm3d.h).
+//
+// The step runs as four node-per-thread kernels, like the unfused
+// two-dimensional path: phi (the pulled g), mu (bulk part minus kappa times
+// the 19-point Laplacian of phi), the pressure (moments of the pulled f,
+// the stencils of phi and mu, force, velocity), and the collision with
+// streaming (grad p from the pressure field). Populations live in a pull
+// layout: slot (i, x) holds the post-collision population i produced at x,
+// so the pre-collision value at x is slot (i, x - c_i), or slot (opp(i), x)
+// when x - c_i lies beyond a wall.
+#include <math.h>
+#include <new>
+
+#include "../../include/qilbm3d.h"
+#include "qilbm_internal.hpp"
+
+namespace qilbm3 {
+
+using qilbm::Coef;
+using qilbm::FixedG;
+using qilbm::GQ;
+using qilbm::GQI;
+using qilbm::GQI_D;
+using qilbm::P_F32;
+using qilbm::P_F64;
+using qilbm::PrecT;
+using qilbm::mu_bulk;
+using qilbm::recip;
+
+// ------------------------------------------------------------------ lattice
+// D3Q19 in the canonical order of the header: rest; the six axis vectors;
+// the twelve vectors with two components +-1 (pairs of opposites).
+__host__ __device__ constexpr int CX(int i) {
+  return (i == 1 || i == 7 || i == 9 || i == 11 || i == 13) ? 1
+         : (i == 2 || i == 8 || i == 10 || i == 12 || i == 14) ? -1 : 0;
+}
+__host__ __device__ constexpr int CY(int i) {
+  return (i == 3 || i == 7 || i == 10 || i == 15 || i == 17) ? 1
+         : (i == 4 || i == 8 || i == 9 || i == 16 || i == 18) ? -1 : 0;
+}
+__host__ __device__ constexpr int CZ(int i) {
+  return (i == 5 || i == 11 || i == 14 || i == 15 || i == 18) ? 1
+         : (i == 6 || i == 12 || i == 13 || i == 16 || i == 17) ? -1 : 0;
+}
+__host__ __device__ constexpr double W(int i) {
+  return i == 0 ? 1.0 / 3.0 : (i <= 6 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+// opposite directions are adjacent: (1,2), (3,4), ..., (17,18)
+__host__ __device__ constexpr int OPP(int i) { return i == 0 ? 0 : ((i & 1) ? i + 1 : i - 1); }
+static_assert(CX(OPP(13)) == -CX(13) && CY(OPP(17)) == -CY(17) && CZ(OPP(18)) == -CZ(18), "opp");
+static_assert(CX(10) == -1 && CY(10) == 1 && CZ(14) == 1 && CX(14) == -1, "table");
+
+struct Geom3 {
+  int nx, ny, nz;
+  int walls;     // 1: bounce-back walls below z = 0 and above z = nz - 1
+  int64_t N;     // nx * ny * nz
+  int64_t Ns;    // plane stride (elements)
+};
+
+template <typename T>
+struct Coef3 {
+  Coef<T> c;     // the two-dimensional coefficient set (gy holds gy, gx gx)
+  T gz;
+};
+
+// Populations: FP64 38 binary64 planes (f_0..18, g_0..18); FP32 19 binary32
+// planes of f, then 19 int32 planes of g in Q2.29.
+template <int P>
+struct Pop3 {
+  char* base;
+  int64_t Ns;
+  using T = typename PrecT<P>::T;
+  __device__ __forceinline__ T f(int i, uint32_t n) const {
+    return reinterpret_cast<const T*>(base)[(int64_t)i * Ns + n];
+  }
+  __device__ __forceinline__ void set_f(int i, uint32_t n, T v) const {
+    reinterpret_cast<T*>(base)[(int64_t)i * Ns + n] = v;
+  }
+  __device__ __forceinline__ int32_t gq(int i, uint32_t n) const {
+    return reinterpret_cast<const int32_t*>(base + 19 * Ns * (int64_t)sizeof(T))[(int64_t)i * Ns + n];
+  }
+  __device__ __forceinline__ T g(int i, uint32_t n) const {
+    if constexpr (P == P_F64)
+      return reinterpret_cast<const double*>(base)[(int64_t)(19 + i) * Ns + n];
+    else
+      return float(gq(i, n)) * GQI;
+  }
+  __device__ __forceinline__ double g_exact(int i, uint32_t n) const {
+    if constexpr (P == P_F64) return g(i, n);
+    else return double(gq(i, n)) * GQI_D;
+  }
+  // stores g_i; returns its Q2.29 word in FP32 (0 in FP64)
+  __device__ __forceinline__ int32_t set_g(int i, uint32_t n, T v) const {
+    if constexpr (P == P_F64) {
+      reinterpret_cast<double*>(base)[(int64_t)(19 + i) * Ns + n] = v;
+      return 0;
+    } else {
+      const int32_t q = __float2int_rn(v * GQ);
+      set_gq(i, n, q);
+      return q;
+    }
+  }
+  // stores g_i given in FP64: rounded once, to binary64 or to Q2.29
+  __device__ __forceinline__ void set_g_d(int i, uint32_t n, double v) const {
+    if constexpr (P == P_F64)
+      reinterpret_cast<double*>(base)[(int64_t)(19 + i) * Ns + n] = v;
+    else
+      set_gq(i, n, __double2int_rn(v * 536870912.0));
+  }
+  __device__ __forceinline__ void set_gq(int i, uint32_t n, int32_t q) const {
+    reinterpret_cast<int32_t*>(base + 19 * Ns * (int64_t)sizeof(T))[(int64_t)i * Ns + n] = q;
+  }
+};
+
+inline int64_t pop3_bytes(int P, int64_t Ns) { return 38 * Ns * (P == P_F64 ? 8 : 4); }
+
+// ------------------------------------------------------------- addressing
+struct Node {
+  int x, y, z;
+  uint32_t n;
+};
+
+// N < 2^29, so the decomposition runs in 32-bit integer division.
+__device__ __forceinline__ Node node_of(int64_t n, const Geom3& g) {
+  Node k;
+  k.n = (uint32_t)n;
+  const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
+  const uint32_t z = k.n / plane, r = k.n - z * plane;
+  const uint32_t y = r / (uint32_t)g.nx;
+  k.z = (int)z;
+  k.y = (int)y;
+  k.x = (int)(r - y * (uint32_t)g.nx);
+  return k;
+}
+
+__device__ __forceinline__ int wrapi(int v, int n) { return v < 0 ? v + n : (v >= n ? v - n : v); }
+
+__device__ __forceinline__ uint32_t idx3(int x, int y, int z, const Geom3& g) {
+  return (uint32_t)(((int64_t)z * g.ny + y) * g.nx + x);
+}
+
+// Pre-collision source of population i at node k: plane index and element.
+template <int I>
+__device__ __forceinline__ void pull_src(const Node& k, const Geom3& g, int& plane, uint32_t& e) {
+  const int zs = k.z - CZ(I);
+  if (zs < 0 || zs >= g.nz) {
+    if (g.walls) {
+      plane = OPP(I);
+      e = k.n;
+      return;
+    }
+  }
+  plane = I;
+  e = idx3(wrapi(k.x - CX(I), g.nx), wrapi(k.y - CY(I), g.ny), wrapi(zs, g.nz), g);
+}
+
+// Element of the stencil neighbour k + c: periodic, or the mirrored ghost
+// plane (the boundary plane itself) beyond a wall.
+__device__ __forceinline__ uint32_t nbr(const Node& k, int cx, int cy, int cz, const Geom3& g) {
+  int z = k.z + cz;
+  if (z < 0 || z >= g.nz) z = g.walls ? k.z : wrapi(z, g.nz);
+  return idx3(wrapi(k.x + cx, g.nx), wrapi(k.y + cy, g.ny), z, g);
+}
+
+// Isotropic central gradient and Laplacian of a field at node k.
+template <typename T, typename F, int I = 1>
+__device__ __forceinline__ void stencil_acc(const F* psi, const Node& k, const Geom3& g, T c0,
+                                            T& gx, T& gy, T& gz, T& lp) {
+  if constexpr (I < 19) {
+    const T v = T(psi[nbr(k, CX(I), CY(I), CZ(I), g)]);
+    const T w = T(W(I));
+    if constexpr (CX(I) != 0) gx += w * T(CX(I)) * v;
+    if constexpr (CY(I) != 0) gy += w * T(CY(I)) * v;
+    if constexpr (CZ(I) != 0) gz += w * T(CZ(I)) * v;
+    lp += w * (v - c0);
+    stencil_acc<T, F, I + 1>(psi, k, g, c0, gx, gy, gz, lp);
+  }
+}
+
+template <typename T, typename F>
+__device__ __forceinline__ void stencil3(const F* psi, const Node& k, const Geom3& g, T& gx,
+                                         T& gy, T& gz, T& lp) {
+  const T c0 = T(psi[k.n]);
+  gx = gy = gz = lp = T(0);
+  stencil_acc<T, F>(psi, k, g, c0, gx, gy, gz, lp);
+  gx *= T(3);
+  gy *= T(3);
+  gz *= T(3);
+  lp *= T(6);
+}
+
+// ------------------------------------------------------------- node algebra
+template <typename T>
+struct Node3 {
+  T phi, rho, mu, p, D;
+  T u[3], F[3], dr[3];
+};
+
+// Force, velocity and pressure (Sec. III moments with three components).
+template <typename T>
+__device__ __forceinline__ void macro3(T phi, T mu, const T gph[3], const T gmu[3], T lapmu,
+                                       T S, const T j[3], const Coef3<T>& k, Node3<T>& m) {
+  const Coef<T>& c = k.c;
+  m.phi = phi;
+  m.mu = mu;
+  m.rho = c.rho_B + c.drho * phi;
+  m.D = c.lam * lapmu;
+  const T b = m.rho - c.rho_ref;
+  const T gv[3] = {c.gx, c.gy, k.gz};
+  const T inv = T(3) * recip(m.rho);
+  T ud = T(0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    m.dr[a] = c.drho * gph[a];
+    m.F[a] = -phi * gmu[a] + b * gv[a];
+    m.u[a] = (j[a] + m.F[a] * T(1.0 / 6.0)) * inv;
+    ud += m.u[a] * m.dr[a];
+  }
+  m.p = S + T(1.0 / 6.0) * (ud - c.gamma * m.rho * m.D);
+}
+
+// BGK collisions of both populations with their sources (Sec. III).
+template <typename T>
+__device__ __forceinline__ void collide3(T f[19], T gg[19], const Node3<T>& m, const T dp[3],
+                                         const Coef<T>& c) {
+  const T usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  const T gpre = -T(3) * m.phi * recip(m.rho);
+  const T h[3] = {dp[0] - m.F[0], dp[1] - m.F[1], dp[2] - m.F[2]};
+  const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
+  const T amu = c.alpha * m.mu;
+  const T r3 = m.rho * T(1.0 / 3.0);
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const T w = T(W(i));
+    const T cv[3] = {T(CX(i)), T(CY(i)), T(CZ(i))};
+    const T cu = cv[0] * m.u[0] + cv[1] * m.u[1] + cv[2] * m.u[2];
+    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T gm = T(1) + s;
+    T fa = T(0), ga = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T cmu = cv[a] - m.u[a];
+      fa += cmu * (gm * m.F[a] + s * m.dr[a] * T(1.0 / 3.0));
+      ga += cmu * h[a];
+    }
+    const T feq = w * (m.p + r3 * s);
+    const T Fi = w * (fa + src1);
+    const T H = (i == 0) ? m.phi - T(1.0 - 1.0 / 3.0) * amu : w * amu;
+    const T geq = H + w * m.phi * s;
+    const T Gi = gpre * w * gm * ga;
+    f[i] = f[i] - (f[i] - feq) * c.inv_tau_f + c.kf * Fi;
+    gg[i] = gg[i] - (gg[i] - geq) * c.inv_tau_g + c.kg * Gi;
+  }
+}
+
+// ------------------------------------------------------------------ kernels
+#define QILBM3_FOR_NODES(n, g)                                                   \
+  for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < (g).N;          \
+       n += (int64_t)gridDim.x * 256)
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_init(const double* __restrict__ phi0, Pop3<P> out,
+                                               Coef3<double> k, Geom3 g) {
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+    double gx, gy, gz, lp;
+    stencil3<double, double>(phi0, nd, g, gx, gy, gz, lp);
+    const double phi = phi0[n];
+    const double mu = mu_bulk(phi, k.c) - k.c.kappa * lp;
+    const double amu = k.c.alpha * mu;
+    // pull layout: g_i pre-collision at x lives in slot (i, x - c_i) (or
+    // (opp(i), x) beyond a wall); scatter each H_i to the slot it is pulled from
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const double h = i == 0 ? phi - (1.0 - 1.0 / 3.0) * amu : W(i) * amu;
+      int zs = nd.z - CZ(i), plane = i;
+      uint32_t e;
+      if ((zs < 0 || zs >= g.nz) && g.walls) {
+        plane = OPP(i);
+        e = nd.n;
+      } else {
+        e = idx3(wrapi(nd.x - CX(i), g.nx), wrapi(nd.y - CY(i), g.ny), wrapi(zs, g.nz), g);
+      }
+      out.set_f(plane, e, typename PrecT<P>::T(0));
+      out.set_g_d(plane, e, h);
+    }
+  }
+}
+
+template <int P, int I = 0>
+__device__ __forceinline__ void pull_all(const Pop3<P>& in, const Node& k, const Geom3& g,
+                                         typename PrecT<P>::T f[19], typename PrecT<P>::T gg[19],
+                                         int32_t& q) {
+  if constexpr (I < 19) {
+    int plane;
+    uint32_t e;
+    pull_src<I>(k, g, plane, e);
+    f[I] = in.f(plane, e);
+    if constexpr (FixedG<P>::value) {
+      const int32_t w = in.gq(plane, e);
+      q += w;
+      gg[I] = float(w) * GQI;
+    } else {
+      gg[I] = in.g(plane, e);
+    }
+    pull_all<P, I + 1>(in, k, g, f, gg, q);
+  }
+}
+
+template <int P, int I = 0>
+__device__ __forceinline__ void pull_g(const Pop3<P>& in, const Node& k, const Geom3& g,
+                                       typename PrecT<P>::T& phi, int32_t& q, double& exact) {
+  if constexpr (I < 19) {
+    int plane;
+    uint32_t e;
+    pull_src<I>(k, g, plane, e);
+    if constexpr (FixedG<P>::value) q += in.gq(plane, e);
+    else phi += in.g(plane, e);
+    exact += in.g_exact(plane, e);
+    pull_g<P, I + 1>(in, k, g, phi, q, exact);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_phi(Pop3<P> in, typename PrecT<P>::T* __restrict__ phi,
+                                              Geom3 g) {
+  using T = typename PrecT<P>::T;
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+    T s = T(0);
+    int32_t q = 0;
+    double ex = 0.0;
+    pull_g<P>(in, nd, g, s, q, ex);
+    phi[n] = FixedG<P>::value ? T(q) * T(GQI) : s;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k3_mu(const T* __restrict__ phi, T* __restrict__ mu,
+                                             Coef3<T> k, Geom3 g) {
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+    T gx, gy, gz, lp;
+    stencil3<T, T>(phi, nd, g, gx, gy, gz, lp);
+    mu[n] = mu_bulk(phi[n], k.c) - k.c.kappa * lp;
+  }
+}
+
+// Node state from the pulled populations and the phi, mu fields.
+template <int P>
+__device__ __forceinline__ void node_state(const Pop3<P>& in, const typename PrecT<P>::T* phi,
+                                           const typename PrecT<P>::T* mu, const Node& nd,
+                                           const Coef3<typename PrecT<P>::T>& k, const Geom3& g,
+                                           typename PrecT<P>::T f[19],
+                                           typename PrecT<P>::T gg[19], int32_t& q,
+                                           Node3<typename PrecT<P>::T>& m) {
+  using T = typename PrecT<P>::T;
+  q = 0;
+  pull_all<P>(in, nd, g, f, gg, q);
+  T S = f[0], j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    S += f[i];
+    if (CX(i)) j[0] += T(CX(i)) * f[i];
+    if (CY(i)) j[1] += T(CY(i)) * f[i];
+    if (CZ(i)) j[2] += T(CZ(i)) * f[i];
+  }
+  T gph[3], gmu[3], lphi, lmu;
+  stencil3<T, T>(phi, nd, g, gph[0], gph[1], gph[2], lphi);
+  stencil3<T, T>(mu, nd, g, gmu[0], gmu[1], gmu[2], lmu);
+  macro3<T>(phi[nd.n], mu[nd.n], gph, gmu, lmu, S, j, k, m);
+}
+
+struct MomentOut3 {
+  double *phi = nullptr, *rho = nullptr, *u[3] = {nullptr, nullptr, nullptr}, *p = nullptr,
+         *mu = nullptr;
+};
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_macro(Pop3<P> in, const typename PrecT<P>::T* __restrict__ phi,
+                                                const typename PrecT<P>::T* __restrict__ mu,
+                                                typename PrecT<P>::T* __restrict__ p,
+                                                MomentOut3 mo, Coef3<typename PrecT<P>::T> k,
+                                                Geom3 g) {
+  using T = typename PrecT<P>::T;
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+    T f[19], gg[19];
+    int32_t q;
+    Node3<T> m;
+    node_state<P>(in, phi, mu, nd, k, g, f, gg, q, m);
+    if (p) p[n] = m.p;
+    if (mo.phi) mo.phi[n] = double(m.phi);
+    if (mo.rho) mo.rho[n] = double(m.rho);
+    for (int a = 0; a < 3; ++a)
+      if (mo.u[a]) mo.u[a][n] = double(m.u[a]);
+    if (mo.p) mo.p[n] = double(m.p);
+    if (mo.mu) mo.mu[n] = double(m.mu);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
+                                                  const typename PrecT<P>::T* __restrict__ phi,
+                                                  const typename PrecT<P>::T* __restrict__ mu,
+                                                  const typename PrecT<P>::T* __restrict__ p,
+                                                  Coef3<typename PrecT<P>::T> k, Geom3 g) {
+  using T = typename PrecT<P>::T;
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+    T f[19], gg[19];
+    int32_t q;
+    Node3<T> m;
+    node_state<P>(in, phi, mu, nd, k, g, f, gg, q, m);
+    T dp[3], lapp;
+    stencil3<T, T>(p, nd, g, dp[0], dp[1], dp[2], lapp);
+    collide3<T>(f, gg, m, dp, k.c);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) out.set_f(i, nd.n, f[i]);
+    if constexpr (FixedG<P>::value) {
+      // g_0 closes the node's Q2.29 sum at the pulled total q
+      int32_t rest = 0;
+#pragma unroll
+      for (int i = 1; i < 19; ++i) rest += out.set_g(i, nd.n, gg[i]);
+      out.set_gq(0, nd.n, q - rest);
+    } else {
+#pragma unroll
+      for (int i = 0; i < 19; ++i) out.set_g(i, nd.n, gg[i]);
+    }
+  }
+}
+
+template <int P, int I = 0>
+__device__ __forceinline__ void to_canonical_dirs(const Pop3<P>& in, const Node& k, const Geom3& g,
+                                                  double* __restrict__ f, double* __restrict__ gg) {
+  if constexpr (I < 19) {
+    int plane;
+    uint32_t e;
+    pull_src<I>(k, g, plane, e);
+    f[(int64_t)I * g.N + k.n] = double(in.f(plane, e));
+    gg[(int64_t)I * g.N + k.n] = in.g_exact(plane, e);   // Q2.29 words exactly
+    to_canonical_dirs<P, I + 1>(in, k, g, f, gg);
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_to_canonical(Pop3<P> in, double* __restrict__ f,
+                                                       double* __restrict__ gg, Geom3 g) {
+  QILBM3_FOR_NODES(n, g) to_canonical_dirs<P>(in, node_of(n, g), g, f, gg);
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_from_canonical(const double* __restrict__ f,
+                                                         const double* __restrict__ gg,
+                                                         Pop3<P> out, Geom3 g) {
+  using T = typename PrecT<P>::T;
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const int zs = nd.z - CZ(i);
+      int plane = i;
+      uint32_t e;
+      if ((zs < 0 || zs >= g.nz) && g.walls) {
+        plane = OPP(i);
+        e = nd.n;
+      } else {
+        e = idx3(wrapi(nd.x - CX(i), g.nx), wrapi(nd.y - CY(i), g.ny), wrapi(zs, g.nz), g);
+      }
+      out.set_f(plane, e, T(f[(int64_t)i * g.N + n]));
+      out.set_g_d(plane, e, gg[(int64_t)i * g.N + n]);
+    }
+  }
+}
+
+// Per-block FP64 partials of (sum phi, sum rho, sum rho u) with phi and rho
+// from the exact stored g; wave64 shuffles, fixed order.
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <int P>
+__global__ __launch_bounds__(256) void k3_mass_partial(Pop3<P> in,
+                                                       const typename PrecT<P>::T* __restrict__ phi,
+                                                       const typename PrecT<P>::T* __restrict__ mu,
+                                                       double* __restrict__ part,
+                                                       Coef3<typename PrecT<P>::T> k, Geom3 g) {
+  using T = typename PrecT<P>::T;
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  QILBM3_FOR_NODES(n, g) {
+    const Node nd = node_of(n, g);
+    T f[19], gg[19];
+    int32_t q;
+    Node3<T> m;
+    node_state<P>(in, phi, mu, nd, k, g, f, gg, q, m);
+    T s = T(0);
+    int32_t q2 = 0;
+    double ex = 0.0;
+    pull_g<P>(in, nd, g, s, q2, ex);
+    const double rho = double(k.c.rho_B) + double(k.c.drho) * ex;
+    a[0] += ex;
+    a[1] += rho;
+    for (int c = 0; c < 3; ++c) a[2 + c] += double(m.rho) * double(m.u[c]);
+  }
+  __shared__ double red[4][5];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) a[c] = wave_sum(a[c]);
+  if (lane == 0)
+    for (int c = 0; c < 5; ++c) red[wave][c] = a[c];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int c = threadIdx.x;
+    part[5 * blockIdx.x + c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  }
+}
+
+// Final sum of nb rows of 5 partials by one workgroup, fixed order.
+__global__ __launch_bounds__(256) void k3_sum5(const double* __restrict__ part, int nb,
+                                               double* __restrict__ out) {
+  double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  for (int b = threadIdx.x; b < nb; b += 256)
+#pragma unroll
+    for (int c = 0; c < 5; ++c) a[c] += part[5 * b + c];
+  __shared__ double red[4][5];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+  for (int c = 0; c < 5; ++c) a[c] = wave_sum(a[c]);
+  if (lane == 0)
+    for (int c = 0; c < 5; ++c) red[wave][c] = a[c];
+  __syncthreads();
+  if (threadIdx.x < 5) {
+    const int c = threadIdx.x;
+    out[c] = (red[0][c] + red[1][c]) + (red[2][c] + red[3][c]);
+  }
+}
+
+}  // namespace qilbm3
+
+// ====================================================================== C ABI
+using namespace qilbm3;
+
+struct lbm3_ctx {
+  lbm3_params prm;
+  double beta, kappa, lam, alpha, gamma, drho;
+  Geom3 geom;
+  hipStream_t stream;
+  char* pop[2];
+  int cur;
+  char* fields;      // phi, mu, p (compute type, Ns each)
+  double* part;      // 5 per reduction block
+  int nred;
+  double* red_out;
+  int64_t t;
+};
+
+namespace {
+
+constexpr size_t ALIGN = 256;
+inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool valid3(const lbm3_params* p) {
+  if (!p) return false;
+  if (p->nx < 3 || p->ny < 3 || p->nz < 3) return false;
+  const int64_t N = (int64_t)p->nx * p->ny * p->nz;
+  if (N > ((int64_t)1 << 29) - 4096) return false;
+  const double v[] = {p->rho_A, p->rho_B, p->sigma, p->W, p->M, p->tau_f, p->tau_g,
+                      p->gx,    p->gy,    p->gz,    p->rho_ref};
+  for (double d : v)
+    if (!isfinite(d)) return false;
+  if (!(p->rho_A > 0.0) || !(p->rho_B > 0.0)) return false;
+  if (!(p->sigma > 0.0) || !(p->W > 0.0) || !(p->M > 0.0)) return false;
+  if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) return false;
+  if (p->bc != LBM_BC_PERIODIC && p->bc != 1) return false;
+  if (p->precision != LBM_FP64 && p->precision != LBM_FP32) return false;
+  if (p->flags & ~(uint32_t)LBM_FLAG_NO_GAMMA) return false;
+  return true;
+}
+
+Geom3 geom_of(const lbm3_params* p) {
+  Geom3 g;
+  g.nx = p->nx;
+  g.ny = p->ny;
+  g.nz = p->nz;
+  g.walls = p->bc == 1;
+  g.N = (int64_t)p->nx * p->ny * p->nz;
+  g.Ns = qilbm::plane_stride(g.N);
+  return g;
+}
+
+struct Layout3 {
+  size_t pop0, pop1, fields, part, red, total;
+  int nred;
+};
+
+Layout3 layout3(const lbm3_params* p) {
+  const Geom3 g = geom_of(p);
+  Layout3 L;
+  const size_t pb = up((size_t)pop3_bytes(p->precision, g.Ns));
+  L.nred = (int)((g.N + 255) / 256);
+  if (L.nred > 2048) L.nred = 2048;
+  L.pop0 = 0;
+  L.pop1 = pb;
+  L.fields = 2 * pb;
+  L.part = L.fields + up(3 * (size_t)g.Ns * 8);
+  L.red = L.part + up((size_t)L.nred * 5 * 8);
+  L.total = L.red + up(8 * 8);
+  return L;
+}
+
+template <typename T>
+Coef3<T> coef3(const lbm3_ctx* c) {
+  Coef3<T> k;
+  k.c.beta4 = T(4.0 * c->beta);
+  k.c.kappa = T(c->kappa);
+  k.c.lam = T(c->lam);
+  k.c.alpha = T(c->alpha);
+  k.c.gamma = T(c->gamma);
+  k.c.drho = T(c->drho);
+  k.c.rho_B = T(c->prm.rho_B);
+  k.c.rho_ref = T(c->prm.rho_ref);
+  k.c.gx = T(c->prm.gx);
+  k.c.gy = T(c->prm.gy);
+  k.gz = T(c->prm.gz);
+  k.c.inv_tau_f = T(1.0 / c->prm.tau_f);
+  k.c.inv_tau_g = T(1.0 / c->prm.tau_g);
+  k.c.kf = T(1.0 - 0.5 / c->prm.tau_f);
+  k.c.kg = T(1.0 - 0.5 / c->prm.tau_g);
+  return k;
+}
+
+unsigned grid_of(int64_t N) {
+  const int64_t b = (N + 255) / 256;
+  return (unsigned)(b < 65536 ? b : 65536);
+}
+
+lbm_status st(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
+
+template <int P>
+hipError_t fields_p(lbm3_ctx* c) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  Pop3<P> in{c->pop[c->cur], g.Ns};
+  T* phi = (T*)c->fields;
+  T* mu = (T*)(c->fields + g.Ns * 8);
+  hipLaunchKernelGGL(k3_phi<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in, phi, g);
+  hipLaunchKernelGGL(k3_mu<T>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, (const T*)phi, mu,
+                     coef3<T>(c), g);
+  return hipGetLastError();
+}
+
+template <int P>
+lbm_status step_p(lbm3_ctx* c, int64_t n) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  const Coef3<T> k = coef3<T>(c);
+  T* phi = (T*)c->fields;
+  T* mu = (T*)(c->fields + g.Ns * 8);
+  T* p = (T*)(c->fields + 2 * g.Ns * 8);
+  for (int64_t s = 0; s < n; ++s) {
+    Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
+    if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
+    hipLaunchKernelGGL(k3_macro<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in,
+                       (const T*)phi, (const T*)mu, p, MomentOut3{}, k, g);
+    hipLaunchKernelGGL(k3_collide<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in, out,
+                       (const T*)phi, (const T*)mu, (const T*)p, k, g);
+    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+template <int P>
+lbm_status moments_p(lbm3_ctx* c, const MomentOut3& mo) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
+  Pop3<P> in{c->pop[c->cur], g.Ns};
+  hipLaunchKernelGGL(k3_macro<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in,
+                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8), (T*)nullptr, mo,
+                     coef3<T>(c), g);
+  return st(hipGetLastError());
+}
+
+template <int P>
+lbm_status mass_p(lbm3_ctx* c) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
+  Pop3<P> in{c->pop[c->cur], g.Ns};
+  hipLaunchKernelGGL(k3_mass_partial<P>, dim3(c->nred), dim3(256), 0, c->stream, in,
+                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8), c->part,
+                     coef3<T>(c), g);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  hipLaunchKernelGGL(k3_sum5, dim3(1), dim3(256), 0, c->stream, (const double*)c->part, c->nred,
+                     c->red_out);
+  if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+  return LBM_OK;
+}
+
+#define QILBM3_DISPATCH(prec, FN, ...) \
+  ((prec) == LBM_FP64 ? FN<P_F64>(__VA_ARGS__) : FN<P_F32>(__VA_ARGS__))
+
+}  // namespace
+
+extern "C" {
+
+size_t lbm3_workspace_bytes(const lbm3_params* params) {
+  if (!valid3(params)) return 0;
+  return layout3(params).total;
+}
+
+lbm_status lbm3_init(lbm3_ctx** out, const lbm3_params* params, void* ws, size_t bytes,
+                     const double* phi0, void* stream) {
+  if (!out) return LBM_EINVAL;
+  *out = nullptr;
+  if (!valid3(params) || !ws || !phi0) return LBM_EINVAL;
+  if ((uintptr_t)ws % ALIGN != 0) return LBM_EINVAL;
+  const Layout3 L = layout3(params);
+  if (bytes < L.total) return LBM_ENOMEM;
+  lbm3_ctx* c = new (std::nothrow) lbm3_ctx();
+  if (!c) return LBM_ENOMEM;
+  c->prm = *params;
+  // Sec. II-III with phi_A = 1, phi_B = 0 (as for the two-dimensional step)
+  c->beta = 12.0 * params->sigma / params->W;
+  c->kappa = 1.5 * params->sigma * params->W;
+  c->lam = params->M;
+  c->alpha = params->M / ((params->tau_g - 0.5) / 3.0);
+  c->gamma = (params->flags & LBM_FLAG_NO_GAMMA) ? 0.0 : params->rho_A / params->rho_B - 1.0;
+  c->drho = params->rho_A - params->rho_B;
+  c->geom = geom_of(params);
+  c->stream = (hipStream_t)stream;
+  char* base = (char*)ws;
+  c->pop[0] = base + L.pop0;
+  c->pop[1] = base + L.pop1;
+  c->cur = 0;
+  c->fields = base + L.fields;
+  c->part = (double*)(base + L.part);
+  c->nred = L.nred;
+  c->red_out = (double*)(base + L.red);
+  c->t = 0;
+  hipError_t e = qilbm::launch_zero(base, L.fields, c->stream);
+  if (e == hipSuccess) {
+    const Coef3<double> k = coef3<double>(c);
+    if (params->precision == LBM_FP64)
+      hipLaunchKernelGGL(k3_init<P_F64>, dim3(grid_of(c->geom.N)), dim3(256), 0, c->stream,
+                         phi0, Pop3<P_F64>{c->pop[0], c->geom.Ns}, k, c->geom);
+    else
+      hipLaunchKernelGGL(k3_init<P_F32>, dim3(grid_of(c->geom.N)), dim3(256), 0, c->stream,
+                         phi0, Pop3<P_F32>{c->pop[0], c->geom.Ns}, k, c->geom);
+    e = hipGetLastError();
+  }
+  if (e != hipSuccess) {
+    delete c;
+    return LBM_EDEVICE;
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm3_step(lbm3_ctx* c, int64_t nsteps) {
+  if (!c || nsteps < 0) return LBM_EINVAL;
+  return QILBM3_DISPATCH(c->prm.precision, step_p, c, nsteps);
+}
+
+lbm_status lbm3_moments(lbm3_ctx* c, double* phi, double* rho, double* ux, double* uy,
+                        double* uz, double* p, double* mu) {
+  if (!c) return LBM_EINVAL;
+  MomentOut3 mo;
+  mo.phi = phi;
+  mo.rho = rho;
+  mo.u[0] = ux;
+  mo.u[1] = uy;
+  mo.u[2] = uz;
+  mo.p = p;
+  mo.mu = mu;
+  return QILBM3_DISPATCH(c->prm.precision, moments_p, c, mo);
+}
+
+lbm_status lbm3_mass(lbm3_ctx* c, double out[5]) {
+  if (!c || !out) return LBM_EINVAL;
+  lbm_status s = QILBM3_DISPATCH(c->prm.precision, mass_p, c);
+  if (s != LBM_OK) return s;
+  double tot[5];
+  if (hipMemcpyAsync(tot, c->red_out, 5 * sizeof(double), hipMemcpyDeviceToHost, c->stream) !=
+      hipSuccess)
+    return LBM_EDEVICE;
+  if (hipStreamSynchronize(c->stream) != hipSuccess) return LBM_EDEVICE;
+  for (int k = 0; k < 5; ++k) out[k] = tot[k];
+  for (int k = 0; k < 5; ++k)
+    if (!isfinite(out[k])) return LBM_EDIVERGED;
+  return LBM_OK;
+}
+
+lbm_status lbm3_get_state(lbm3_ctx* c, double* f, double* g) {
+  if (!c || !f || !g) return LBM_EINVAL;
+  const Geom3& gm = c->geom;
+  if (c->prm.precision == LBM_FP64)
+    hipLaunchKernelGGL(k3_to_canonical<P_F64>, dim3(grid_of(gm.N)), dim3(256), 0, c->stream,
+                       Pop3<P_F64>{c->pop[c->cur], gm.Ns}, f, g, gm);
+  else
+    hipLaunchKernelGGL(k3_to_canonical<P_F32>, dim3(grid_of(gm.N)), dim3(256), 0, c->stream,
+                       Pop3<P_F32>{c->pop[c->cur], gm.Ns}, f, g, gm);
+  return st(hipGetLastError());
+}
+
+lbm_status lbm3_set_state(lbm3_ctx* c, const double* f, const double* g) {
+  if (!c || !f || !g) return LBM_EINVAL;
+  const Geom3& gm = c->geom;
+  if (c->prm.precision == LBM_FP64)
+    hipLaunchKernelGGL(k3_from_canonical<P_F64>, dim3(grid_of(gm.N)), dim3(256), 0, c->stream,
+                       f, g, Pop3<P_F64>{c->pop[c->cur], gm.Ns}, gm);
+  else
+    hipLaunchKernelGGL(k3_from_canonical<P_F32>, dim3(grid_of(gm.N)), dim3(256), 0, c->stream,
+                       f, g, Pop3<P_F32>{c->pop[c->cur], gm.Ns}, gm);
+  return st(hipGetLastError());
+}
+
+int64_t lbm3_time(const lbm3_ctx* c) { return c ? c->t : -1; }
+
+void lbm3_destroy(lbm3_ctx* c) { delete c; }
+
+}  // extern "C"

@@ -1,7 +1,8 @@
 """Host-side checks of the C-ABI library that need no GPU: it loads, exports
-every symbol include/qilbm.h declares, and rejects invalid arguments before
-any device work."""
+every symbol include/*.h declares, and rejects invalid arguments before any
+device work."""
 import ctypes
+import glob
 import os
 import re
 from ctypes import c_int32, byref, c_double, c_void_p
@@ -11,13 +12,16 @@ import pytest
 import workloads as wl
 from paper_1507_03521_amd import _lib
 
-HEADER = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "include", "qilbm.h")
+HEADERS = sorted(glob.glob(os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                                        "include", "*.h")))
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(lbm_[a-z_0-9]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(lbm3?_[a-z_0-9]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -27,7 +31,8 @@ def lib():
 
 def test_every_declared_symbol_is_exported(lib):
     names = _declared()
-    assert len(names) >= 20
+    assert len(HEADERS) >= 2 and len(names) >= 29
+    assert any(n.startswith("lbm3_") for n in names)
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(_lib.SIGNATURES), set(names) ^ set(_lib.SIGNATURES)
@@ -117,3 +122,51 @@ def test_coefficients_match_paper_relations(lib):
     p.flags = _lib.LBM_FLAG_NO_GAMMA
     assert lib.lbm_coefficients(byref(p), out) == 0
     assert out[4] == 0.0
+
+
+def _params3(**kw):
+    d = wl.droplet3d().as_dict()
+    d.update(kw)
+    return _lib.make_params3(d)
+
+
+@pytest.mark.parametrize("bad", [dict(nx=2), dict(nz=0), dict(tau_f=0.5), dict(tau_g=0.4),
+                                 dict(sigma=0.0), dict(M=0.0), dict(rho_B=0.0),
+                                 dict(gz=float("nan")), dict(bc=2)])
+def test_3d_invalid_parameters_rejected(lib, bad):
+    p = _params3(**bad)
+    assert lib.lbm3_workspace_bytes(byref(p)) == 0
+    ctx = c_void_p()
+    assert lib.lbm3_init(byref(ctx), byref(p), c_void_p(256), 1 << 30, c_void_p(256),
+                         None) == _lib.LBM_EINVAL
+    assert not ctx.value
+
+
+def test_3d_precision_flags_and_init_checks(lib):
+    p = _params3()
+    p.precision = _lib.LBM_FP16_STORE            # not offered in 3-D
+    assert lib.lbm3_workspace_bytes(byref(p)) == 0
+    p = _params3()
+    p.flags = _lib.LBM_FLAG_UNFUSED              # only LBM_FLAG_NO_GAMMA
+    assert lib.lbm3_workspace_bytes(byref(p)) == 0
+    p = _params3()
+    nbytes = lib.lbm3_workspace_bytes(byref(p))
+    # two population sets of 38 planes (FP64) plus fields
+    assert nbytes >= 2 * 38 * 8 * 32 ** 3
+    ctx = c_void_p()
+    assert lib.lbm3_init(byref(ctx), byref(p), None, nbytes, c_void_p(256), None) == _lib.LBM_EINVAL
+    assert lib.lbm3_init(byref(ctx), byref(p), c_void_p(256), nbytes, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm3_init(byref(ctx), byref(p), c_void_p(264), nbytes, c_void_p(256), None) == _lib.LBM_EINVAL
+    assert lib.lbm3_init(byref(ctx), byref(p), c_void_p(256), nbytes - 1, c_void_p(256), None) == _lib.LBM_ENOMEM
+    p.precision = _lib.LBM_FP32
+    assert 0 < lib.lbm3_workspace_bytes(byref(p)) < nbytes
+
+
+def test_3d_null_context_calls(lib):
+    assert lib.lbm3_step(None, 1) == _lib.LBM_EINVAL
+    assert lib.lbm3_mass(None, (c_double * 5)()) == _lib.LBM_EINVAL
+    assert lib.lbm3_moments(None, *([None] * 7)) == _lib.LBM_EINVAL
+    assert lib.lbm3_get_state(None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm3_set_state(None, None, None) == _lib.LBM_EINVAL
+    assert lib.lbm3_time(None) == -1
+    lib.lbm3_destroy(None)
