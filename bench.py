@@ -10,7 +10,8 @@ streaming). FP64 and FP32 run two steps per launch of the fused kernel
 Printed: ONE JSON line. ``value`` is the FP32 rate in MLUPS (million lattice
 updates per second); the line also carries the FP64 and FP16-storage rates
 with their deviation from the FP64 GPU run, the adjoint/forward step-time
-ratio, the roofline position of the fused kernel and the CPU-oracle rate.
+ratio, the roofline position of the fused kernel, the CPU-oracle rate and
+the three-dimensional (D3Q19, 256^3 box) step's rates.
 """
 from __future__ import annotations
 
@@ -73,6 +74,35 @@ def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
     info = lat.pass_info()
     del lat
     return ms, phi, m0, m1, info
+
+
+# D3Q19: 19 f and 19 g read and written once per node and step
+BYTES_PER_LU_3D = {"fp64": 608, "fp32": 304}
+
+
+def run_3d(steps: int, warmup: int):
+    """The three-dimensional step on the 256^3 Rayleigh-Taylor box (walls
+    normal to z): rate per precision, the step's algorithmic HBM rate (19 f
+    and 19 g per node read and written once) and the totals' drift."""
+    import workloads as wl
+    from paper_1507_03521_amd import Lattice3D
+    pb = wl.rt3d()
+    phi0 = wl.phi0_3d(pb)
+    N = pb.nx * pb.ny * pb.nz
+    out = {"workload": "rt3d: Rayleigh-Taylor 256x256x256, walls in z, Atwood 0.5, "
+                       "Re 3000, Pe 1000, W 4", "kernels": "k3_phi, k3_mu, k3_macro, k3_collide"}
+    for prec in ("fp32", "fp64"):
+        lat = Lattice3D(pb.as_dict(), phi0, precision=prec, device="cuda:0")
+        m0 = lat.mass()
+        ms = timed_steps(lat, steps, warmup)
+        m1 = lat.mass()
+        del lat
+        gbs = BYTES_PER_LU_3D[prec] * N / (ms * 1e-3) / 1e9
+        out[prec] = dict(mlups=round(N / ms / 1e3, 2), ms_per_step=round(ms, 5),
+                         alg_gbps=round(gbs, 1), hbm_roofline_frac=round(gbs / PEAK_HBM_GBS, 4),
+                         phi_total_drift=abs(m1[0] - m0[0]) / abs(m0[0]))
+        log(f"  3-D {prec}: {ms:.4f} ms/step, {N / ms / 1e3:.1f} MLUPS")
+    return out
 
 
 def adjoint_ratio(pb, phi0, precision, fwd_ms, nadj=10):
@@ -335,6 +365,9 @@ def main():
                     help="time one precision only (for profiler runs)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-adjoint", action="store_true")
+    ap.add_argument("--no-3d", action="store_true",
+                    help="skip the three-dimensional (D3Q19) 256^3 leg")
+    ap.add_argument("--steps-3d", type=int, default=200)
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -442,6 +475,9 @@ def main():
     if not args.no_adjoint and main_prec in ("fp32", "fp64"):
         log("timing adjoint")
         line["adjoint"] = adjoint_ratio(pb, phi0, main_prec, ms)
+    if not args.no_3d:
+        log("timing the three-dimensional step")
+        line["d3q19"] = run_3d(args.steps_3d, max(1, args.steps_3d // 10))
     if not args.no_cpu_baseline:
         log("timing CPU oracle sample")
         line["cpu_baseline"] = cpu_baseline(pb, phi0, args.cpu_rows, args.cpu_steps)

@@ -120,6 +120,7 @@ inline int64_t pop3_bytes(int P, int64_t Ns) { return 38 * Ns * (P == P_F64 ? 8 
 struct Node {
   int x, y, z;
   uint32_t n;
+  bool inner;   // all 18 neighbours inside the lattice: constant offsets
 };
 
 // N < 2^29, so the decomposition runs in 32-bit integer division.
@@ -132,6 +133,8 @@ __device__ __forceinline__ Node node_of(int64_t n, const Geom3& g) {
   k.z = (int)z;
   k.y = (int)y;
   k.x = (int)(r - y * (uint32_t)g.nx);
+  k.inner = k.x >= 1 && k.x < g.nx - 1 && k.y >= 1 && k.y < g.ny - 1 && k.z >= 1 &&
+            k.z < g.nz - 1;
   return k;
 }
 
@@ -141,24 +144,32 @@ __device__ __forceinline__ uint32_t idx3(int x, int y, int z, const Geom3& g) {
   return (uint32_t)(((int64_t)z * g.ny + y) * g.nx + x);
 }
 
+// Linear offset of vector (cx, cy, cz).
+__device__ __forceinline__ int off3(int cx, int cy, int cz, const Geom3& g) {
+  return cx + g.nx * (cy + g.ny * cz);
+}
+
 // Pre-collision source of population i at node k: plane index and element.
 template <int I>
 __device__ __forceinline__ void pull_src(const Node& k, const Geom3& g, int& plane, uint32_t& e) {
-  const int zs = k.z - CZ(I);
-  if (zs < 0 || zs >= g.nz) {
-    if (g.walls) {
-      plane = OPP(I);
-      e = k.n;
-      return;
-    }
-  }
   plane = I;
+  if (k.inner) {
+    e = k.n - off3(CX(I), CY(I), CZ(I), g);
+    return;
+  }
+  const int zs = k.z - CZ(I);
+  if ((zs < 0 || zs >= g.nz) && g.walls) {
+    plane = OPP(I);
+    e = k.n;
+    return;
+  }
   e = idx3(wrapi(k.x - CX(I), g.nx), wrapi(k.y - CY(I), g.ny), wrapi(zs, g.nz), g);
 }
 
 // Element of the stencil neighbour k + c: periodic, or the mirrored ghost
 // plane (the boundary plane itself) beyond a wall.
 __device__ __forceinline__ uint32_t nbr(const Node& k, int cx, int cy, int cz, const Geom3& g) {
+  if (k.inner) return k.n + off3(cx, cy, cz, g);
   int z = k.z + cz;
   if (z < 0 || z >= g.nz) z = g.walls ? k.z : wrapi(z, g.nz);
   return idx3(wrapi(k.x + cx, g.nx), wrapi(k.y + cy, g.ny), z, g);
@@ -348,17 +359,26 @@ __global__ __launch_bounds__(256) void k3_mu(const T* __restrict__ phi, T* __res
   }
 }
 
-// Node state from the pulled populations and the phi, mu fields.
+template <int P, int I = 0>
+__device__ __forceinline__ void pull_f(const Pop3<P>& in, const Node& k, const Geom3& g,
+                                       typename PrecT<P>::T f[19]) {
+  if constexpr (I < 19) {
+    int plane;
+    uint32_t e;
+    pull_src<I>(k, g, plane, e);
+    f[I] = in.f(plane, e);
+    pull_f<P, I + 1>(in, k, g, f);
+  }
+}
+
+// Node state from the pulled f and the phi, mu fields.
 template <int P>
-__device__ __forceinline__ void node_state(const Pop3<P>& in, const typename PrecT<P>::T* phi,
+__device__ __forceinline__ void node_macro(const typename PrecT<P>::T f[19],
+                                           const typename PrecT<P>::T* phi,
                                            const typename PrecT<P>::T* mu, const Node& nd,
                                            const Coef3<typename PrecT<P>::T>& k, const Geom3& g,
-                                           typename PrecT<P>::T f[19],
-                                           typename PrecT<P>::T gg[19], int32_t& q,
                                            Node3<typename PrecT<P>::T>& m) {
   using T = typename PrecT<P>::T;
-  q = 0;
-  pull_all<P>(in, nd, g, f, gg, q);
   T S = f[0], j[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int i = 1; i < 19; ++i) {
@@ -387,10 +407,10 @@ __global__ __launch_bounds__(256) void k3_macro(Pop3<P> in, const typename PrecT
   using T = typename PrecT<P>::T;
   QILBM3_FOR_NODES(n, g) {
     const Node nd = node_of(n, g);
-    T f[19], gg[19];
-    int32_t q;
+    T f[19];
     Node3<T> m;
-    node_state<P>(in, phi, mu, nd, k, g, f, gg, q, m);
+    pull_f<P>(in, nd, g, f);
+    node_macro<P>(f, phi, mu, nd, k, g, m);
     if (p) p[n] = m.p;
     if (mo.phi) mo.phi[n] = double(m.phi);
     if (mo.rho) mo.rho[n] = double(m.rho);
@@ -411,9 +431,10 @@ __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
   QILBM3_FOR_NODES(n, g) {
     const Node nd = node_of(n, g);
     T f[19], gg[19];
-    int32_t q;
+    int32_t q = 0;
     Node3<T> m;
-    node_state<P>(in, phi, mu, nd, k, g, f, gg, q, m);
+    pull_all<P>(in, nd, g, f, gg, q);
+    node_macro<P>(f, phi, mu, nd, k, g, m);
     T dp[3], lapp;
     stencil3<T, T>(p, nd, g, dp[0], dp[1], dp[2], lapp);
     collide3<T>(f, gg, m, dp, k.c);
@@ -493,10 +514,10 @@ __global__ __launch_bounds__(256) void k3_mass_partial(Pop3<P> in,
   double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
   QILBM3_FOR_NODES(n, g) {
     const Node nd = node_of(n, g);
-    T f[19], gg[19];
-    int32_t q;
+    T f[19];
     Node3<T> m;
-    node_state<P>(in, phi, mu, nd, k, g, f, gg, q, m);
+    pull_f<P>(in, nd, g, f);
+    node_macro<P>(f, phi, mu, nd, k, g, m);
     T s = T(0);
     int32_t q2 = 0;
     double ex = 0.0;
