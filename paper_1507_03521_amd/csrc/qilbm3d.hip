@@ -12,6 +12,7 @@
 // when x - c_i lies beyond a wall.
 #include <math.h>
 #include <new>
+#include <type_traits>
 
 #include "../../include/qilbm3d.h"
 #include "qilbm_internal.hpp"
@@ -28,6 +29,10 @@ using qilbm::P_F64;
 using qilbm::PrecT;
 using qilbm::mu_bulk;
 using qilbm::recip;
+using qilbm::BUF_WORD3;
+using qilbm::buf_ld;
+using qilbm::buf_st;
+using qilbm::xcd_tile;
 
 // ------------------------------------------------------------------ lattice
 // D3Q19 in the canonical order of the header: rest; the six axis vectors;
@@ -120,9 +125,9 @@ inline int64_t pop3_bytes(int P, int64_t Ns) { return 38 * Ns * (P == P_F64 ? 8 
 struct Node {
   int x, y, z;
   uint32_t n;
-  bool inner;   // all 18 neighbours inside the lattice: constant offsets
 };
 
+// Per-node addressing of the cold kernels (initial state, state transfer):
 // N < 2^29, so the decomposition runs in 32-bit integer division.
 __device__ __forceinline__ Node node_of(int64_t n, const Geom3& g) {
   Node k;
@@ -133,8 +138,6 @@ __device__ __forceinline__ Node node_of(int64_t n, const Geom3& g) {
   k.z = (int)z;
   k.y = (int)y;
   k.x = (int)(r - y * (uint32_t)g.nx);
-  k.inner = k.x >= 1 && k.x < g.nx - 1 && k.y >= 1 && k.y < g.ny - 1 && k.z >= 1 &&
-            k.z < g.nz - 1;
   return k;
 }
 
@@ -144,32 +147,22 @@ __device__ __forceinline__ uint32_t idx3(int x, int y, int z, const Geom3& g) {
   return (uint32_t)(((int64_t)z * g.ny + y) * g.nx + x);
 }
 
-// Linear offset of vector (cx, cy, cz).
-__device__ __forceinline__ int off3(int cx, int cy, int cz, const Geom3& g) {
-  return cx + g.nx * (cy + g.ny * cz);
-}
-
 // Pre-collision source of population i at node k: plane index and element.
 template <int I>
 __device__ __forceinline__ void pull_src(const Node& k, const Geom3& g, int& plane, uint32_t& e) {
-  plane = I;
-  if (k.inner) {
-    e = k.n - off3(CX(I), CY(I), CZ(I), g);
-    return;
-  }
   const int zs = k.z - CZ(I);
   if ((zs < 0 || zs >= g.nz) && g.walls) {
     plane = OPP(I);
     e = k.n;
     return;
   }
+  plane = I;
   e = idx3(wrapi(k.x - CX(I), g.nx), wrapi(k.y - CY(I), g.ny), wrapi(zs, g.nz), g);
 }
 
 // Element of the stencil neighbour k + c: periodic, or the mirrored ghost
 // plane (the boundary plane itself) beyond a wall.
 __device__ __forceinline__ uint32_t nbr(const Node& k, int cx, int cy, int cz, const Geom3& g) {
-  if (k.inner) return k.n + off3(cx, cy, cz, g);
   int z = k.z + cz;
   if (z < 0 || z >= g.nz) z = g.walls ? k.z : wrapi(z, g.nz);
   return idx3(wrapi(k.x + cx, g.nx), wrapi(k.y + cy, g.ny), z, g);
@@ -300,97 +293,213 @@ __global__ __launch_bounds__(256) void k3_init(const double* __restrict__ phi0, 
   }
 }
 
-template <int P, int I = 0>
-__device__ __forceinline__ void pull_all(const Pop3<P>& in, const Node& k, const Geom3& g,
-                                         typename PrecT<P>::T f[19], typename PrecT<P>::T gg[19],
-                                         int32_t& q) {
-  if constexpr (I < 19) {
-    int plane;
-    uint32_t e;
-    pull_src<I>(k, g, plane, e);
-    f[I] = in.f(plane, e);
-    if constexpr (FixedG<P>::value) {
-      const int32_t w = in.gq(plane, e);
-      q += w;
-      gg[I] = float(w) * GQI;
-    } else {
-      gg[I] = in.g(plane, e);
-    }
-    pull_all<P, I + 1>(in, k, g, f, gg, q);
+// ------------------------------------------------------ row-wave kernels
+// Work unit of the step kernels: one wave (64 lanes) takes 64 consecutive x
+// of one (y, z) row. Everything that depends on y and z -- periodic wrap,
+// the walls, the element index of the 3 x 3 neighbouring rows -- is then
+// uniform across the wave and sits in scalar registers; a lane only holds
+// its x and the wrapped x - 1, x + 1. Memory goes through buffer
+// descriptors: the lane's byte offset in x (voffset) plus a scalar
+// plane-and-row offset (soffset), so a neighbour access costs no vector
+// address arithmetic and no integer division anywhere.
+struct RowCtx {
+  uint32_t rb[3][3];   // element index of (0, y + cy, z + cz), cy, cz in -1..1;
+                       // beyond a wall z is clamped (mirrored ghost plane)
+  bool below, above;   // walls: plane z - 1 / z + 1 lies beyond a wall
+};
+
+struct Lane {
+  uint32_t xo[3];      // byte offsets of x - 1, x, x + 1 (wrapped)
+  uint32_t x;
+};
+
+__device__ __forceinline__ RowCtx row_ctx(uint32_t y, uint32_t z, const Geom3& g) {
+  RowCtx R;
+  const uint32_t nx = g.nx, ny = g.ny, nz = g.nz;
+  const bool wl = g.walls;
+  const uint32_t ys[3] = {y == 0 ? ny - 1 : y - 1, y, y + 1 == ny ? 0 : y + 1};
+  const uint32_t zs[3] = {z == 0 ? (wl ? 0 : nz - 1) : z - 1, z,
+                          z + 1 == nz ? (wl ? z : 0) : z + 1};
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) R.rb[a][b] = (zs[b] * ny + ys[a]) * nx;
+  R.below = wl && z == 0;
+  R.above = wl && z + 1 == nz;
+  return R;
+}
+
+template <int WS>
+__device__ __forceinline__ Lane lane_of(uint32_t x, const Geom3& g) {
+  Lane L;
+  const uint32_t nx = g.nx;
+  L.x = x;
+  L.xo[0] = (x == 0 ? nx - 1 : x - 1) * WS;
+  L.xo[1] = x * WS;
+  L.xo[2] = (x + 1 == nx ? 0 : x + 1) * WS;
+  return L;
+}
+
+// Runs fn(row, lane) for every node, one (row, 64-column chunk) per wave;
+// blocks are placed XCD-contiguously over the tasks.
+template <int WS, typename Fn>
+__device__ __forceinline__ void for_rows(const Geom3& g, uint32_t nxc, Fn&& fn) {
+  const uint32_t lane = threadIdx.x & 63;
+  const uint32_t nb = gridDim.x;
+  const uint32_t b = (uint32_t)xcd_tile((int)blockIdx.x, (int)nb);
+  const uint32_t ntask = nxc * (uint32_t)g.ny * (uint32_t)g.nz;
+  for (uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(b * 4 + (threadIdx.x >> 6)));
+       t < ntask; t += nb * 4) {
+    const uint32_t row = t / nxc, xc = t - row * nxc;
+    const uint32_t z = row / (uint32_t)g.ny, y = row - z * (uint32_t)g.ny;
+    const uint32_t x = xc * 64 + lane;
+    if (x < (uint32_t)g.nx) fn(row_ctx(y, z, g), lane_of<WS>(x, g));
   }
 }
 
-template <int P, int I = 0>
-__device__ __forceinline__ void pull_g(const Pop3<P>& in, const Node& k, const Geom3& g,
-                                       typename PrecT<P>::T& phi, int32_t& q, double& exact) {
-  if constexpr (I < 19) {
-    int plane;
-    uint32_t e;
-    pull_src<I>(k, g, plane, e);
-    if constexpr (FixedG<P>::value) q += in.gq(plane, e);
-    else phi += in.g(plane, e);
-    exact += in.g_exact(plane, e);
-    pull_g<P, I + 1>(in, k, g, phi, q, exact);
+// Equally spaced planes of words S; one descriptor for all of them when
+// they span less than 4 GiB (BIG = false), else one per plane.
+template <typename S, bool BIG>
+struct Planes {
+  char* base;
+  uint32_t pb;                     // plane stride in bytes
+  __amdgpu_buffer_rsrc_t all;
+  __device__ __forceinline__ Planes(const void* b, int64_t Ns, int nplanes)
+      : base((char*)b), pb((uint32_t)(Ns * (int64_t)sizeof(S))) {
+    if constexpr (!BIG)
+      all = __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)((int64_t)nplanes * pb), BUF_WORD3);
   }
-}
+  __device__ __forceinline__ __amdgpu_buffer_rsrc_t rsrc(int plane) const {
+    if constexpr (BIG)
+      return __builtin_amdgcn_make_buffer_rsrc(base + (int64_t)plane * pb, 0, (int)pb, BUF_WORD3);
+    else
+      return all;
+  }
+  __device__ __forceinline__ uint32_t soff(int plane, uint32_t row) const {
+    return (BIG ? 0u : (uint32_t)plane * pb) + row * (uint32_t)sizeof(S);
+  }
+  __device__ __forceinline__ S ld(int plane, uint32_t row, uint32_t vo) const {
+    return buf_ld<S>(rsrc(plane), vo, soff(plane, row));
+  }
+  __device__ __forceinline__ void st(int plane, uint32_t row, uint32_t vo, S v) const {
+    buf_st<S>(v, rsrc(plane), vo, soff(plane, row));
+  }
+};
 
-template <int P>
-__global__ __launch_bounds__(256) void k3_phi(Pop3<P> in, typename PrecT<P>::T* __restrict__ phi,
-                                              Geom3 g) {
+// The two population sets of a buffer: f (T) and g (T, or Q2.29 words).
+template <int P, bool BIG>
+struct PopView {
   using T = typename PrecT<P>::T;
-  QILBM3_FOR_NODES(n, g) {
-    const Node nd = node_of(n, g);
-    T s = T(0);
-    int32_t q = 0;
-    double ex = 0.0;
-    pull_g<P>(in, nd, g, s, q, ex);
-    phi[n] = FixedG<P>::value ? T(q) * T(GQI) : s;
+  using GW = typename std::conditional<P == P_F64, double, int32_t>::type;
+  Planes<T, BIG> f;
+  Planes<GW, BIG> g;
+  __device__ __forceinline__ explicit PopView(const Pop3<P>& p)
+      : f(p.base, p.Ns, 19), g(p.base + 19 * p.Ns * (int64_t)sizeof(T), p.Ns, 19) {}
+};
+
+// Slot holding the pre-collision population i of the lane's node.
+struct Src {
+  int plane;
+  uint32_t row, vo;
+};
+
+__device__ __forceinline__ Src pull_at(int i, const RowCtx& R, const Lane& L) {
+  const int cz = CZ(i);
+  const bool beyond = (cz == 1 && R.below) || (cz == -1 && R.above);
+  Src s;
+  s.plane = beyond ? OPP(i) : i;
+  s.row = beyond ? R.rb[1][1] : R.rb[1 - CY(i)][1 - cz];
+  s.vo = beyond ? L.xo[1] : L.xo[1 - CX(i)];
+  return s;
+}
+
+// Isotropic gradient and Laplacian of a field (in direction order).
+template <typename T>
+__device__ __forceinline__ void stencil_r(const Planes<T, false>& F, const RowCtx& R,
+                                          const Lane& L, T& c0, T& gx, T& gy, T& gz, T& lp) {
+  c0 = F.ld(0, R.rb[1][1], L.xo[1]);
+  gx = gy = gz = lp = T(0);
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    const T v = F.ld(0, R.rb[CY(i) + 1][CZ(i) + 1], L.xo[CX(i) + 1]);
+    const T w = T(W(i));
+    if (CX(i) != 0) gx += w * T(CX(i)) * v;
+    if (CY(i) != 0) gy += w * T(CY(i)) * v;
+    if (CZ(i) != 0) gz += w * T(CZ(i)) * v;
+    lp += w * (v - c0);
   }
+  gx *= T(3);
+  gy *= T(3);
+  gz *= T(3);
+  lp *= T(6);
+}
+
+template <int P, bool BIG>
+__global__ __launch_bounds__(256) void k3_phi(Pop3<P> in, typename PrecT<P>::T* __restrict__ phi,
+                                              Geom3 g, uint32_t nxc) {
+  using T = typename PrecT<P>::T;
+  const PopView<P, BIG> v(in);
+  const Planes<T, false> out(phi, g.Ns, 1);
+  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
+    if constexpr (FixedG<P>::value) {
+      int32_t q = 0;
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const Src s = pull_at(i, R, L);
+        q += v.g.ld(s.plane, s.row, s.vo);
+      }
+      out.st(0, R.rb[1][1], L.xo[1], T(q) * T(GQI));
+    } else {
+      T a = T(0);
+#pragma unroll
+      for (int i = 0; i < 19; ++i) {
+        const Src s = pull_at(i, R, L);
+        a += v.g.ld(s.plane, s.row, s.vo);
+      }
+      out.st(0, R.rb[1][1], L.xo[1], a);
+    }
+  });
 }
 
 template <typename T>
 __global__ __launch_bounds__(256) void k3_mu(const T* __restrict__ phi, T* __restrict__ mu,
-                                             Coef3<T> k, Geom3 g) {
-  QILBM3_FOR_NODES(n, g) {
-    const Node nd = node_of(n, g);
-    T gx, gy, gz, lp;
-    stencil3<T, T>(phi, nd, g, gx, gy, gz, lp);
-    mu[n] = mu_bulk(phi[n], k.c) - k.c.kappa * lp;
-  }
+                                             Coef3<T> k, Geom3 g, uint32_t nxc) {
+  const Planes<T, false> ph(phi, g.Ns, 1), out(mu, g.Ns, 1);
+  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
+    T c0, gx, gy, gz, lp;
+    stencil_r<T>(ph, R, L, c0, gx, gy, gz, lp);
+    out.st(0, R.rb[1][1], L.xo[1], mu_bulk(c0, k.c) - k.c.kappa * lp);
+  });
 }
 
-template <int P, int I = 0>
-__device__ __forceinline__ void pull_f(const Pop3<P>& in, const Node& k, const Geom3& g,
-                                       typename PrecT<P>::T f[19]) {
-  if constexpr (I < 19) {
-    int plane;
-    uint32_t e;
-    pull_src<I>(k, g, plane, e);
-    f[I] = in.f(plane, e);
-    pull_f<P, I + 1>(in, k, g, f);
-  }
-}
-
-// Node state from the pulled f and the phi, mu fields.
-template <int P>
-__device__ __forceinline__ void node_macro(const typename PrecT<P>::T f[19],
-                                           const typename PrecT<P>::T* phi,
-                                           const typename PrecT<P>::T* mu, const Node& nd,
-                                           const Coef3<typename PrecT<P>::T>& k, const Geom3& g,
-                                           Node3<typename PrecT<P>::T>& m) {
+// Pulled f of the lane's node and the node state from it and the phi, mu
+// fields.
+template <int P, bool BIG>
+__device__ __forceinline__ void node_state_r(const PopView<P, BIG>& v,
+                                             const Planes<typename PrecT<P>::T, false>& ph,
+                                             const Planes<typename PrecT<P>::T, false>& mf,
+                                             const RowCtx& R, const Lane& L,
+                                             const Coef3<typename PrecT<P>::T>& k,
+                                             typename PrecT<P>::T f[19],
+                                             Node3<typename PrecT<P>::T>& m) {
   using T = typename PrecT<P>::T;
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const Src s = pull_at(i, R, L);
+    f[i] = v.f.ld(s.plane, s.row, s.vo);
+  }
   T S = f[0], j[3] = {T(0), T(0), T(0)};
 #pragma unroll
   for (int i = 1; i < 19; ++i) {
     S += f[i];
-    if (CX(i)) j[0] += T(CX(i)) * f[i];
-    if (CY(i)) j[1] += T(CY(i)) * f[i];
-    if (CZ(i)) j[2] += T(CZ(i)) * f[i];
+    if (CX(i) != 0) j[0] += T(CX(i)) * f[i];
+    if (CY(i) != 0) j[1] += T(CY(i)) * f[i];
+    if (CZ(i) != 0) j[2] += T(CZ(i)) * f[i];
   }
-  T gph[3], gmu[3], lphi, lmu;
-  stencil3<T, T>(phi, nd, g, gph[0], gph[1], gph[2], lphi);
-  stencil3<T, T>(mu, nd, g, gmu[0], gmu[1], gmu[2], lmu);
-  macro3<T>(phi[nd.n], mu[nd.n], gph, gmu, lmu, S, j, k, m);
+  T phi, mu, gph[3], gmu[3], lphi, lmu;
+  stencil_r<T>(ph, R, L, phi, gph[0], gph[1], gph[2], lphi);
+  stencil_r<T>(mf, R, L, mu, gmu[0], gmu[1], gmu[2], lmu);
+  macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
 }
 
 struct MomentOut3 {
@@ -398,59 +507,77 @@ struct MomentOut3 {
          *mu = nullptr;
 };
 
-template <int P>
+template <int P, bool BIG>
 __global__ __launch_bounds__(256) void k3_macro(Pop3<P> in, const typename PrecT<P>::T* __restrict__ phi,
                                                 const typename PrecT<P>::T* __restrict__ mu,
                                                 typename PrecT<P>::T* __restrict__ p,
                                                 MomentOut3 mo, Coef3<typename PrecT<P>::T> k,
-                                                Geom3 g) {
+                                                Geom3 g, uint32_t nxc) {
   using T = typename PrecT<P>::T;
-  QILBM3_FOR_NODES(n, g) {
-    const Node nd = node_of(n, g);
+  const PopView<P, BIG> v(in);
+  const Planes<T, false> ph(phi, g.Ns, 1), mf(mu, g.Ns, 1), pf(p, g.Ns, 1);
+  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
     T f[19];
     Node3<T> m;
-    pull_f<P>(in, nd, g, f);
-    node_macro<P>(f, phi, mu, nd, k, g, m);
-    if (p) p[n] = m.p;
+    node_state_r<P, BIG>(v, ph, mf, R, L, k, f, m);
+    if (p) pf.st(0, R.rb[1][1], L.xo[1], m.p);
+    const uint32_t n = R.rb[1][1] + L.x;
     if (mo.phi) mo.phi[n] = double(m.phi);
     if (mo.rho) mo.rho[n] = double(m.rho);
     for (int a = 0; a < 3; ++a)
       if (mo.u[a]) mo.u[a][n] = double(m.u[a]);
     if (mo.p) mo.p[n] = double(m.p);
     if (mo.mu) mo.mu[n] = double(m.mu);
-  }
+  });
 }
 
-template <int P>
+template <int P, bool BIG>
 __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
                                                   const typename PrecT<P>::T* __restrict__ phi,
                                                   const typename PrecT<P>::T* __restrict__ mu,
                                                   const typename PrecT<P>::T* __restrict__ p,
-                                                  Coef3<typename PrecT<P>::T> k, Geom3 g) {
+                                                  Coef3<typename PrecT<P>::T> k, Geom3 g,
+                                                  uint32_t nxc) {
   using T = typename PrecT<P>::T;
-  QILBM3_FOR_NODES(n, g) {
-    const Node nd = node_of(n, g);
+  const PopView<P, BIG> v(in), w(out);
+  const Planes<T, false> ph(phi, g.Ns, 1), mf(mu, g.Ns, 1), pf(p, g.Ns, 1);
+  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
     T f[19], gg[19];
     int32_t q = 0;
-    Node3<T> m;
-    pull_all<P>(in, nd, g, f, gg, q);
-    node_macro<P>(f, phi, mu, nd, k, g, m);
-    T dp[3], lapp;
-    stencil3<T, T>(p, nd, g, dp[0], dp[1], dp[2], lapp);
-    collide3<T>(f, gg, m, dp, k.c);
 #pragma unroll
-    for (int i = 0; i < 19; ++i) out.set_f(i, nd.n, f[i]);
+    for (int i = 0; i < 19; ++i) {
+      const Src s = pull_at(i, R, L);
+      if constexpr (FixedG<P>::value) {
+        const int32_t word = v.g.ld(s.plane, s.row, s.vo);
+        q += word;
+        gg[i] = float(word) * GQI;
+      } else {
+        gg[i] = v.g.ld(s.plane, s.row, s.vo);
+      }
+    }
+    Node3<T> m;
+    node_state_r<P, BIG>(v, ph, mf, R, L, k, f, m);
+    T p0, dp[3], lapp;
+    stencil_r<T>(pf, R, L, p0, dp[0], dp[1], dp[2], lapp);
+    collide3<T>(f, gg, m, dp, k.c);
+    const uint32_t row = R.rb[1][1], vo = L.xo[1];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) w.f.st(i, row, vo, f[i]);
     if constexpr (FixedG<P>::value) {
       // g_0 closes the node's Q2.29 sum at the pulled total q
       int32_t rest = 0;
 #pragma unroll
-      for (int i = 1; i < 19; ++i) rest += out.set_g(i, nd.n, gg[i]);
-      out.set_gq(0, nd.n, q - rest);
+      for (int i = 1; i < 19; ++i) {
+        const int32_t word = __float2int_rn(gg[i] * GQ);
+        rest += word;
+        w.g.st(i, row, vo, word);
+      }
+      w.g.st(0, row, vo, q - rest);
     } else {
 #pragma unroll
-      for (int i = 0; i < 19; ++i) out.set_g(i, nd.n, gg[i]);
+      for (int i = 0; i < 19; ++i) w.g.st(i, row, vo, gg[i]);
     }
-  }
+  });
 }
 
 template <int P, int I = 0>
@@ -504,29 +631,32 @@ __device__ __forceinline__ double wave_sum(double v) {
   return v;
 }
 
-template <int P>
+template <int P, bool BIG>
 __global__ __launch_bounds__(256) void k3_mass_partial(Pop3<P> in,
                                                        const typename PrecT<P>::T* __restrict__ phi,
                                                        const typename PrecT<P>::T* __restrict__ mu,
                                                        double* __restrict__ part,
-                                                       Coef3<typename PrecT<P>::T> k, Geom3 g) {
+                                                       Coef3<typename PrecT<P>::T> k, Geom3 g,
+                                                       uint32_t nxc) {
   using T = typename PrecT<P>::T;
+  const PopView<P, BIG> v(in);
+  const Planes<T, false> ph(phi, g.Ns, 1), mf(mu, g.Ns, 1);
   double a[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
-  QILBM3_FOR_NODES(n, g) {
-    const Node nd = node_of(n, g);
+  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
     T f[19];
     Node3<T> m;
-    pull_f<P>(in, nd, g, f);
-    node_macro<P>(f, phi, mu, nd, k, g, m);
-    T s = T(0);
-    int32_t q2 = 0;
-    double ex = 0.0;
-    pull_g<P>(in, nd, g, s, q2, ex);
-    const double rho = double(k.c.rho_B) + double(k.c.drho) * ex;
+    node_state_r<P, BIG>(v, ph, mf, R, L, k, f, m);
+    double ex = 0.0;   // phi from the stored g, exactly
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const Src s = pull_at(i, R, L);
+      if constexpr (FixedG<P>::value) ex += double(v.g.ld(s.plane, s.row, s.vo)) * GQI_D;
+      else ex += v.g.ld(s.plane, s.row, s.vo);
+    }
     a[0] += ex;
-    a[1] += rho;
+    a[1] += double(k.c.rho_B) + double(k.c.drho) * ex;
     for (int c = 0; c < 3; ++c) a[2 + c] += double(m.rho) * double(m.u[c]);
-  }
+  });
   __shared__ double red[4][5];
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 #pragma unroll
@@ -659,6 +789,21 @@ unsigned grid_of(int64_t N) {
   return (unsigned)(b < 65536 ? b : 65536);
 }
 
+// Row-wave launches: ceil(nx / 64) chunks per row, four per workgroup.
+uint32_t chunks_x(const Geom3& g) { return (uint32_t)((g.nx + 63) / 64); }
+
+unsigned row_grid(const Geom3& g) {
+  const int64_t tasks = (int64_t)chunks_x(g) * g.ny * g.nz;
+  const int64_t b = (tasks + 3) / 4;
+  return (unsigned)(b < (1 << 24) ? b : (1 << 24));
+}
+
+// A population set spans more than 4 GiB - 1 bytes: one descriptor per plane.
+template <int P>
+bool big3(const Geom3& g) {
+  return 19 * g.Ns * (int64_t)sizeof(typename PrecT<P>::T) > (int64_t)UINT32_MAX;
+}
+
 lbm_status st(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
 template <int P>
@@ -668,27 +813,53 @@ hipError_t fields_p(lbm3_ctx* c) {
   Pop3<P> in{c->pop[c->cur], g.Ns};
   T* phi = (T*)c->fields;
   T* mu = (T*)(c->fields + g.Ns * 8);
-  hipLaunchKernelGGL(k3_phi<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in, phi, g);
-  hipLaunchKernelGGL(k3_mu<T>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, (const T*)phi, mu,
-                     coef3<T>(c), g);
+  const uint32_t nxc = chunks_x(g);
+  if (big3<P>(g))
+    hipLaunchKernelGGL((k3_phi<P, true>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, phi, g,
+                       nxc);
+  else
+    hipLaunchKernelGGL((k3_phi<P, false>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, phi, g,
+                       nxc);
+  hipLaunchKernelGGL(k3_mu<T>, dim3(row_grid(g)), dim3(256), 0, c->stream, (const T*)phi, mu,
+                     coef3<T>(c), g, nxc);
   return hipGetLastError();
+}
+
+template <int P, bool BIG>
+void launch_macro(lbm3_ctx* c, typename PrecT<P>::T* p, const MomentOut3& mo) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  Pop3<P> in{c->pop[c->cur], g.Ns};
+  hipLaunchKernelGGL((k3_macro<P, BIG>), dim3(row_grid(g)), dim3(256), 0, c->stream, in,
+                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8), p, mo, coef3<T>(c), g,
+                     chunks_x(g));
+}
+
+template <int P, bool BIG>
+void launch_collide(lbm3_ctx* c) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
+  hipLaunchKernelGGL((k3_collide<P, BIG>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, out,
+                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8),
+                     (const T*)(c->fields + 2 * g.Ns * 8), coef3<T>(c), g, chunks_x(g));
 }
 
 template <int P>
 lbm_status step_p(lbm3_ctx* c, int64_t n) {
   using T = typename PrecT<P>::T;
   const Geom3& g = c->geom;
-  const Coef3<T> k = coef3<T>(c);
-  T* phi = (T*)c->fields;
-  T* mu = (T*)(c->fields + g.Ns * 8);
   T* p = (T*)(c->fields + 2 * g.Ns * 8);
+  const bool big = big3<P>(g);
   for (int64_t s = 0; s < n; ++s) {
-    Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
     if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
-    hipLaunchKernelGGL(k3_macro<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in,
-                       (const T*)phi, (const T*)mu, p, MomentOut3{}, k, g);
-    hipLaunchKernelGGL(k3_collide<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in, out,
-                       (const T*)phi, (const T*)mu, (const T*)p, k, g);
+    if (big) {
+      launch_macro<P, true>(c, p, MomentOut3{});
+      launch_collide<P, true>(c);
+    } else {
+      launch_macro<P, false>(c, p, MomentOut3{});
+      launch_collide<P, false>(c);
+    }
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     c->cur ^= 1;
     c->t += 1;
@@ -698,13 +869,11 @@ lbm_status step_p(lbm3_ctx* c, int64_t n) {
 
 template <int P>
 lbm_status moments_p(lbm3_ctx* c, const MomentOut3& mo) {
-  using T = typename PrecT<P>::T;
-  const Geom3& g = c->geom;
   if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
-  Pop3<P> in{c->pop[c->cur], g.Ns};
-  hipLaunchKernelGGL(k3_macro<P>, dim3(grid_of(g.N)), dim3(256), 0, c->stream, in,
-                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8), (T*)nullptr, mo,
-                     coef3<T>(c), g);
+  if (big3<P>(c->geom))
+    launch_macro<P, true>(c, nullptr, mo);
+  else
+    launch_macro<P, false>(c, nullptr, mo);
   return st(hipGetLastError());
 }
 
@@ -714,9 +883,14 @@ lbm_status mass_p(lbm3_ctx* c) {
   const Geom3& g = c->geom;
   if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
   Pop3<P> in{c->pop[c->cur], g.Ns};
-  hipLaunchKernelGGL(k3_mass_partial<P>, dim3(c->nred), dim3(256), 0, c->stream, in,
-                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8), c->part,
-                     coef3<T>(c), g);
+  const T* phi = (const T*)c->fields;
+  const T* mu = (const T*)(c->fields + g.Ns * 8);
+  if (big3<P>(g))
+    hipLaunchKernelGGL((k3_mass_partial<P, true>), dim3(c->nred), dim3(256), 0, c->stream, in,
+                       phi, mu, c->part, coef3<T>(c), g, chunks_x(g));
+  else
+    hipLaunchKernelGGL((k3_mass_partial<P, false>), dim3(c->nred), dim3(256), 0, c->stream, in,
+                       phi, mu, c->part, coef3<T>(c), g, chunks_x(g));
   if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
   hipLaunchKernelGGL(k3_sum5, dim3(1), dim3(256), 0, c->stream, (const double*)c->part, c->nred,
                      c->red_out);

@@ -178,11 +178,23 @@ def test_no_gamma_flag_matches_oracle():
     assert _rel(f1, fr) < 1e-12 and _rel(g1, gr) < 1e-12
 
 
-@pytest.mark.parametrize("precision", ["fp64", "fp32"])
-def test_full_size_rt3d_crop(precision):
-    """256^3 Rayleigh-Taylor box: two steps, then one more step compared on
-    the interior of a 24 x 24 x 256 crop stepped by the oracle."""
-    pb = wl.rt3d()
+def _set_bytes(N, word):
+    Ns = (N + 255) // 256 * 256 + 2304
+    return 19 * Ns * word
+
+
+# 256^3 (one descriptor per population set) and lattices whose population
+# sets exceed 4 GiB (one descriptor per plane)
+CROP_CASES = [("fp64", 256, 256), ("fp32", 256, 256), ("fp64", 320, 288), ("fp32", 400, 360)]
+
+
+@pytest.mark.parametrize("precision,nx,nz", CROP_CASES)
+def test_full_size_rt3d_crop(precision, nx, nz):
+    """Rayleigh-Taylor box: two steps, then one more step compared on the
+    interior of a 24 x 24 x nz crop stepped by the oracle."""
+    pb = wl.rt3d(nx=nx, nz=nz)
+    big = _set_bytes(nx * nx * nz, 8 if precision == "fp64" else 4) > 2 ** 32 - 1
+    assert big == (nx != 256)
     phi0 = wl.phi0_3d(pb)
     lat = _lattice(pb, phi0, precision)
     lat.step(2)
