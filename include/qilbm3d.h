@@ -22,8 +22,12 @@
  *   Precision: LBM_FP64 (binary64 populations) or LBM_FP32 (f binary32, g
  *     Q2.29 fixed point, so the lattice total of phi is an exact integer
  *     invariant); LBM_FP16_STORE is not offered in 3-D.
- *   Kernels: one thread per node (phi; mu; pressure; collision with
- *     streaming), the populations in a pull layout; no LDS tiling yet.
+ *   Kernels: the populations in a pull layout. FP32 runs one fused kernel
+ *     per step (a workgroup sweeps a 64 x 16 column tile along z, phi, mu and
+ *     p in LDS plane rings); FP64, and FP32 with LBM_FLAG_UNFUSED, run four
+ *     kernels per step (phi; mu; pressure; collision with streaming), one
+ *     wave per 64-node run of a row. The two FP32 paths agree to rounding
+ *     order and hold the same exact phi total.
  *   Memory, streams, errors: as in qilbm.h (caller-owned device workspace,
  *     asynchronous calls on the context's stream except lbm3_mass).
  */
@@ -48,7 +52,8 @@ typedef struct {
   double rho_ref;         /* reference density of the body force              */
   int32_t bc;             /* LBM_BC_PERIODIC, or 1 = walls normal to z         */
   int32_t precision;      /* LBM_FP64 or LBM_FP32                              */
-  uint32_t flags;         /* LBM_FLAG_NO_GAMMA (others are rejected)           */
+  uint32_t flags;         /* LBM_FLAG_NO_GAMMA, LBM_FLAG_UNFUSED (others are
+                             rejected)                                        */
 } lbm3_params;
 
 typedef struct lbm3_ctx lbm3_ctx;

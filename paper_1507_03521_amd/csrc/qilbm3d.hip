@@ -384,6 +384,13 @@ struct Planes {
   __device__ __forceinline__ void st(int plane, uint32_t row, uint32_t vo, S v) const {
     buf_st<S>(v, rsrc(plane), vo, soff(plane, row));
   }
+  // byte offsets: sb (scalar, within the plane) and vb (per lane)
+  __device__ __forceinline__ S ldb(int plane, uint32_t sb, uint32_t vb) const {
+    return buf_ld<S>(rsrc(plane), vb, (BIG ? 0u : (uint32_t)plane * pb) + sb);
+  }
+  __device__ __forceinline__ void stb(int plane, uint32_t sb, uint32_t vb, S v) const {
+    buf_st<S>(v, rsrc(plane), vb, (BIG ? 0u : (uint32_t)plane * pb) + sb);
+  }
 };
 
 // The two population sets of a buffer: f (T) and g (T, or Q2.29 words).
@@ -580,6 +587,349 @@ __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
   });
 }
 
+// ------------------------------------------------------ fused z-sweep step
+// One kernel per time step. A workgroup owns a TX x TY tile of (x, y) and a
+// segment [z0, z1) of planes and sweeps it in z. In the iteration that
+// reaches plane a it
+//   A: forms phi(a) from the pulled g over the tile plus 3 halo nodes,
+//   B: forms mu(a-1) from the phi planes a-2..a over the tile plus 2,
+//   C: forms the pressure p(a-2) from its pulled f and the phi, mu stencils
+//      over the tile plus 1,
+//   D: collides plane a-3 of the tile (grad p from the p planes a-4..a-2)
+//      and writes both post-collision populations.
+// phi, mu and p live in LDS rings of 5, 4 and 3 planes; the populations
+// are read from HBM where a stage needs them (the re-reads of D follow
+// those of A and C closely enough to be served by the caches) and written
+// once. Halo nodes and the 3 planes of warm-up at each segment end are
+// recomputed by the neighbouring workgroups. Results equal those of the
+// four-kernel path up to the rounding order of contracted multiply-adds.
+// Used for FP32 only: the halo and warm-up re-reads and the second pull of
+// each population are not caught by L2 (measured 453 B read per node
+// against 365 for the four kernels together), so the kernel gains
+// little over the four-kernel path in FP32, and in FP64 (one 512-lane
+// workgroup per CU, barrier-bound) it was a quarter slower.
+namespace fz {
+constexpr int TX = 64, TY = 16;
+template <int H>
+struct Reg {
+  static constexpr int W = TX + 2 * H, HT = TY + 2 * H, A = W * HT;
+};
+constexpr int RPHI = 5, RMU = 4, RP = 3;
+}  // namespace fz
+
+template <int P>
+struct FzThreads {
+  static constexpr int value = 256;
+};
+
+// node rounds of stages C and D unrolled together (loads of several nodes
+// in flight at once), within the register budget of two waves per SIMD
+template <int P>
+struct FzUnrollC {
+  static constexpr int value = 5;
+};
+template <int P>
+struct FzUnrollD {
+  static constexpr int value = 2;
+};
+
+template <int P>
+struct FzLds {
+  using T = typename PrecT<P>::T;
+  T phi[fz::RPHI][fz::Reg<3>::A];
+  T mu[fz::RMU][fz::Reg<2>::A];
+  T p[fz::RP][fz::Reg<1>::A];
+};
+
+struct Fz3Shape {
+  int ntx, nty, nseg, seg;
+};
+
+__device__ __forceinline__ int wrapm(int v, int n) {
+  while (v < 0) v += n;
+  while (v >= n) v -= n;
+  return v;
+}
+
+// Byte offsets of a node's x - 1, x, x + 1 and of its rows y - 1, y, y + 1
+// (wrapped) within a plane.
+struct XY {
+  uint32_t xo[3], yo[3];
+};
+
+template <int WS>
+__device__ __forceinline__ XY xy_of(int gx, int gy, const Geom3& g) {
+  XY q;
+  const int nx = g.nx, ny = g.ny;
+  q.xo[0] = (uint32_t)(gx == 0 ? nx - 1 : gx - 1) * WS;
+  q.xo[1] = (uint32_t)gx * WS;
+  q.xo[2] = (uint32_t)(gx + 1 == nx ? 0 : gx + 1) * WS;
+  q.yo[0] = (uint32_t)(gy == 0 ? ny - 1 : gy - 1) * (uint32_t)nx * WS;
+  q.yo[1] = (uint32_t)gy * (uint32_t)nx * WS;
+  q.yo[2] = (uint32_t)(gy + 1 == ny ? 0 : gy + 1) * (uint32_t)nx * WS;
+  return q;
+}
+
+// Planes z - 1, z, z + 1 of global plane z as byte offsets (wrapped; at a
+// wall the missing plane is flagged and never addressed).
+struct ZP {
+  uint32_t zo[3];
+  bool below, above;
+};
+
+template <int WS>
+__device__ __forceinline__ ZP zp_of(int z, const Geom3& g) {
+  ZP Z;
+  const uint32_t pl = (uint32_t)g.nx * (uint32_t)g.ny * WS;
+  const int nz = g.nz;
+  Z.zo[0] = (uint32_t)(z == 0 ? nz - 1 : z - 1) * pl;
+  Z.zo[1] = (uint32_t)z * pl;
+  Z.zo[2] = (uint32_t)(z + 1 == nz ? 0 : z + 1) * pl;
+  Z.below = g.walls && z == 0;
+  Z.above = g.walls && z + 1 == nz;
+  return Z;
+}
+
+struct SrcB {
+  int plane;
+  uint32_t sb, vb;
+};
+
+// Slot of the pre-collision population i of a node (pull; bounce-back
+// from the node's own opposite slot beyond a wall).
+__device__ __forceinline__ SrcB pull_b(int i, const ZP& Z, const XY& q) {
+  const int cz = CZ(i);
+  const bool beyond = (cz == 1 && Z.below) || (cz == -1 && Z.above);
+  SrcB s;
+  s.plane = beyond ? OPP(i) : i;
+  s.sb = beyond ? Z.zo[1] : Z.zo[1 - cz];
+  s.vb = beyond ? q.yo[1] + q.xo[1] : q.yo[1 - CY(i)] + q.xo[1 - CX(i)];
+  return s;
+}
+
+// Isotropic gradient and Laplacian from three LDS planes of a region of
+// row width RW, at index o (same accumulation order as stencil_r).
+template <typename T, int RW>
+__device__ __forceinline__ void lds_stencil(const T* pm, const T* p0, const T* pp, int o, T& c0,
+                                            T& gx, T& gy, T& gz, T& lp) {
+  c0 = p0[o];
+  gx = gy = gz = lp = T(0);
+#pragma unroll
+  for (int i = 1; i < 19; ++i) {
+    const T* pl = CZ(i) < 0 ? pm : (CZ(i) > 0 ? pp : p0);
+    const T v = pl[o + CY(i) * RW + CX(i)];
+    const T w = T(W(i));
+    if (CX(i) != 0) gx += w * T(CX(i)) * v;
+    if (CY(i) != 0) gy += w * T(CY(i)) * v;
+    if (CZ(i) != 0) gz += w * T(CZ(i)) * v;
+    lp += w * (v - c0);
+  }
+  gx *= T(3);
+  gy *= T(3);
+  gz *= T(3);
+  lp *= T(6);
+}
+
+template <int P, bool BIG>
+__global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3<P> out,
+                                                                Coef3<typename PrecT<P>::T> k,
+                                                                Geom3 g, Fz3Shape sh) {
+  using T = typename PrecT<P>::T;
+  using namespace fz;
+  constexpr int NT = FzThreads<P>::value;
+  constexpr int WS = sizeof(T);
+  using RA = Reg<3>;
+  using RB = Reg<2>;
+  using RC = Reg<1>;
+  __shared__ FzLds<P> L;
+
+  const int ntiles = sh.ntx * sh.nty;
+  const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int tile = b % ntiles, sg = b / ntiles;
+  const int x0 = (tile % sh.ntx) * TX, y0 = (tile / sh.ntx) * TY;
+  const int z0 = sg * sh.seg;
+  if (z0 >= g.nz) return;                  // whole workgroup, before any barrier
+  const int z1 = min(z0 + sh.seg, g.nz);
+  const int nz = g.nz;
+  const bool wl = g.walls;
+  const int vbase = z0 - 3;
+  const PopView<P, BIG> v(in), w(out);
+  const int tid = threadIdx.x;
+
+  // ring slot of virtual plane zz as read by a stencil (clamped at walls)
+  auto slot = [&](int zz, int R) {
+    if (wl) zz = zz < 0 ? 0 : (zz >= nz ? nz - 1 : zz);
+    return (zz - vbase) % R;
+  };
+  auto real = [&](int zz) { return wl ? (zz >= 0 && zz < nz) : true; };
+
+  const int niter = (z1 - z0) + 6;
+  for (int it = 0; it < niter; ++it) {
+    const int a = vbase + it;
+    // A: phi(a) over the tile plus 3
+    if (real(a)) {
+      const ZP Z = zp_of<WS>(wrapm(a, nz), g);
+      T* dst = L.phi[slot(a, RPHI)];
+#pragma unroll
+      for (int rr = 0; rr < (RA::A + NT - 1) / NT; ++rr) {
+        const int r = tid + rr * NT;
+        if (r >= RA::A) break;
+        const int ly = r / RA::W, lx = r - ly * RA::W;
+        const XY q = xy_of<WS>(wrapm(x0 - 3 + lx, g.nx), wrapm(y0 - 3 + ly, g.ny), g);
+        if constexpr (FixedG<P>::value) {
+          int32_t s = 0;
+#pragma unroll
+          for (int i = 0; i < 19; ++i) {
+            const SrcB o = pull_b(i, Z, q);
+            s += v.g.ldb(o.plane, o.sb, o.vb);
+          }
+          dst[r] = T(s) * T(GQI);
+        } else {
+          T s = T(0);
+#pragma unroll
+          for (int i = 0; i < 19; ++i) {
+            const SrcB o = pull_b(i, Z, q);
+            s += v.g.ldb(o.plane, o.sb, o.vb);
+          }
+          dst[r] = s;
+        }
+      }
+    }
+    __syncthreads();
+    // B: mu(a-1) over the tile plus 2
+    const int zb = a - 1;
+    if (zb >= z0 - 2 && zb < z1 + 2 && real(zb)) {
+      const T* pm = L.phi[slot(zb - 1, RPHI)];
+      const T* p0 = L.phi[slot(zb, RPHI)];
+      const T* pp = L.phi[slot(zb + 1, RPHI)];
+      T* dst = L.mu[slot(zb, RMU)];
+#pragma unroll
+      for (int rr = 0; rr < (RB::A + NT - 1) / NT; ++rr) {
+        const int r = tid + rr * NT;
+        if (r >= RB::A) break;
+        const int ly = r / RB::W, lx = r - ly * RB::W;
+        T c0, gx, gy, gz, lp;
+        lds_stencil<T, RA::W>(pm, p0, pp, (ly + 1) * RA::W + lx + 1, c0, gx, gy, gz, lp);
+        dst[r] = mu_bulk(c0, k.c) - k.c.kappa * lp;
+      }
+    }
+    __syncthreads();
+    // C: p(a-2) over the tile plus 1
+    const int zc = a - 2;
+    if (zc >= z0 - 1 && zc < z1 + 1 && real(zc)) {
+      const ZP Z = zp_of<WS>(wrapm(zc, nz), g);
+      const T* fm = L.phi[slot(zc - 1, RPHI)];
+      const T* f0 = L.phi[slot(zc, RPHI)];
+      const T* fp = L.phi[slot(zc + 1, RPHI)];
+      const T* mm = L.mu[slot(zc - 1, RMU)];
+      const T* m0 = L.mu[slot(zc, RMU)];
+      const T* mp = L.mu[slot(zc + 1, RMU)];
+      T* dst = L.p[slot(zc, RP)];
+#pragma unroll FzUnrollC<P>::value
+      for (int rr = 0; rr < (RC::A + NT - 1) / NT; ++rr) {
+        const int r = tid + rr * NT;
+        if (r >= RC::A) break;
+        const int ly = r / RC::W, lx = r - ly * RC::W;
+        const XY q = xy_of<WS>(wrapm(x0 - 1 + lx, g.nx), wrapm(y0 - 1 + ly, g.ny), g);
+        T f[19];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+          const SrcB o = pull_b(i, Z, q);
+          f[i] = v.f.ldb(o.plane, o.sb, o.vb);
+        }
+        T S = f[0], j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+          S += f[i];
+          if (CX(i) != 0) j[0] += T(CX(i)) * f[i];
+          if (CY(i) != 0) j[1] += T(CY(i)) * f[i];
+          if (CZ(i) != 0) j[2] += T(CZ(i)) * f[i];
+        }
+        T phi, mu, gph[3], gmu[3], lphi, lmu;
+        lds_stencil<T, RA::W>(fm, f0, fp, (ly + 2) * RA::W + lx + 2, phi, gph[0], gph[1], gph[2],
+                              lphi);
+        lds_stencil<T, RB::W>(mm, m0, mp, (ly + 1) * RB::W + lx + 1, mu, gmu[0], gmu[1], gmu[2],
+                              lmu);
+        Node3<T> m;
+        macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
+        dst[r] = m.p;
+      }
+    }
+    __syncthreads();
+    // D: collide plane a-3 of the tile
+    const int zd = a - 3;
+    if (zd >= z0 && zd < z1) {
+      const ZP Z = zp_of<WS>(zd, g);
+      const T* fm = L.phi[slot(zd - 1, RPHI)];
+      const T* f0 = L.phi[slot(zd, RPHI)];
+      const T* fp = L.phi[slot(zd + 1, RPHI)];
+      const T* mm = L.mu[slot(zd - 1, RMU)];
+      const T* m0 = L.mu[slot(zd, RMU)];
+      const T* mp = L.mu[slot(zd + 1, RMU)];
+      const T* qm = L.p[slot(zd - 1, RP)];
+      const T* q0 = L.p[slot(zd, RP)];
+      const T* qp = L.p[slot(zd + 1, RP)];
+#pragma unroll FzUnrollD<P>::value
+      for (int rr = 0; rr < (TX * TY + NT - 1) / NT; ++rr) {
+        const int r = tid + rr * NT;
+        const int ly = r / TX, lx = r - ly * TX;
+        const int X = x0 + lx, Y = y0 + ly;
+        if (X >= g.nx || Y >= g.ny) continue;
+        const XY q = xy_of<WS>(X, Y, g);
+        T f[19], gg[19];
+        int32_t qs = 0;
+#pragma unroll
+        for (int i = 0; i < 19; ++i) {
+          const SrcB o = pull_b(i, Z, q);
+          f[i] = v.f.ldb(o.plane, o.sb, o.vb);
+          if constexpr (FixedG<P>::value) {
+            const int32_t word = v.g.ldb(o.plane, o.sb, o.vb);
+            qs += word;
+            gg[i] = float(word) * GQI;
+          } else {
+            gg[i] = v.g.ldb(o.plane, o.sb, o.vb);
+          }
+        }
+        T S = f[0], j[3] = {T(0), T(0), T(0)};
+#pragma unroll
+        for (int i = 1; i < 19; ++i) {
+          S += f[i];
+          if (CX(i) != 0) j[0] += T(CX(i)) * f[i];
+          if (CY(i) != 0) j[1] += T(CY(i)) * f[i];
+          if (CZ(i) != 0) j[2] += T(CZ(i)) * f[i];
+        }
+        T phi, mu, gph[3], gmu[3], lphi, lmu, p0, dp[3], lpp;
+        lds_stencil<T, RA::W>(fm, f0, fp, (ly + 3) * RA::W + lx + 3, phi, gph[0], gph[1], gph[2],
+                              lphi);
+        lds_stencil<T, RB::W>(mm, m0, mp, (ly + 2) * RB::W + lx + 2, mu, gmu[0], gmu[1], gmu[2],
+                              lmu);
+        lds_stencil<T, RC::W>(qm, q0, qp, (ly + 1) * RC::W + lx + 1, p0, dp[0], dp[1], dp[2], lpp);
+        Node3<T> m;
+        macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
+        collide3<T>(f, gg, m, dp, k.c);
+        const uint32_t sb = Z.zo[1], vb = q.yo[1] + q.xo[1];
+#pragma unroll
+        for (int i = 0; i < 19; ++i) w.f.stb(i, sb, vb, f[i]);
+        if constexpr (FixedG<P>::value) {
+          // g_0 closes the node's Q2.29 sum at the pulled total
+          int32_t rest = 0;
+#pragma unroll
+          for (int i = 1; i < 19; ++i) {
+            const int32_t word = __float2int_rn(gg[i] * GQ);
+            rest += word;
+            w.g.stb(i, sb, vb, word);
+          }
+          w.g.stb(0, sb, vb, qs - rest);
+        } else {
+#pragma unroll
+          for (int i = 0; i < 19; ++i) w.g.stb(i, sb, vb, gg[i]);
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
 template <int P, int I = 0>
 __device__ __forceinline__ void to_canonical_dirs(const Pop3<P>& in, const Node& k, const Geom3& g,
                                                   double* __restrict__ f, double* __restrict__ gg) {
@@ -707,6 +1057,7 @@ struct lbm3_ctx {
   int nred;
   double* red_out;
   int64_t t;
+  int resident;      // workgroups of the fused kernel resident at once (0: not yet known)
 };
 
 namespace {
@@ -728,7 +1079,7 @@ bool valid3(const lbm3_params* p) {
   if (!(p->tau_f > 0.5) || !(p->tau_g > 0.5)) return false;
   if (p->bc != LBM_BC_PERIODIC && p->bc != 1) return false;
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32) return false;
-  if (p->flags & ~(uint32_t)LBM_FLAG_NO_GAMMA) return false;
+  if (p->flags & ~(uint32_t)(LBM_FLAG_NO_GAMMA | LBM_FLAG_UNFUSED)) return false;
   return true;
 }
 
@@ -846,9 +1197,61 @@ void launch_collide(lbm3_ctx* c) {
 }
 
 template <int P>
+int fused_resident3() {
+  int dev = 0, cus = 0, per_cu = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+    return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_fused<P, false>,
+                                                   FzThreads<P>::value, 0) != hipSuccess)
+    return 0;
+  return cus * (per_cu > 0 ? per_cu : 1);
+}
+
+// Tiles of TX x TY columns times z-segments, one round of workgroups.
+Fz3Shape fused_shape3(const Geom3& g, int resident) {
+  Fz3Shape sh;
+  sh.ntx = (g.nx + fz::TX - 1) / fz::TX;
+  sh.nty = (g.ny + fz::TY - 1) / fz::TY;
+  const int ntiles = sh.ntx * sh.nty;
+  int nseg = resident > ntiles ? resident / ntiles : 1;
+  if (nseg > g.nz) nseg = g.nz;
+  sh.seg = (g.nz + nseg - 1) / nseg;
+  sh.nseg = (g.nz + sh.seg - 1) / sh.seg;
+  return sh;
+}
+
+template <int P>
+lbm_status step_fused_p(lbm3_ctx* c, int64_t n) {
+  using T = typename PrecT<P>::T;
+  const Geom3& g = c->geom;
+  if (c->resident == 0) c->resident = fused_resident3<P>();
+  if (c->resident <= 0) return LBM_EDEVICE;
+  const Fz3Shape sh = fused_shape3(g, c->resident);
+  const unsigned nblk = (unsigned)(sh.ntx * sh.nty * sh.nseg);
+  const Coef3<T> k = coef3<T>(c);
+  const bool big = big3<P>(g);
+  for (int64_t s = 0; s < n; ++s) {
+    Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
+    if (big)
+      hipLaunchKernelGGL((k3_fused<P, true>), dim3(nblk), dim3(FzThreads<P>::value), 0, c->stream,
+                         in, out, k, g, sh);
+    else
+      hipLaunchKernelGGL((k3_fused<P, false>), dim3(nblk), dim3(FzThreads<P>::value), 0,
+                         c->stream, in, out, k, g, sh);
+    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+    c->cur ^= 1;
+    c->t += 1;
+  }
+  return LBM_OK;
+}
+
+template <int P>
 lbm_status step_p(lbm3_ctx* c, int64_t n) {
   using T = typename PrecT<P>::T;
   const Geom3& g = c->geom;
+  if constexpr (P == P_F32)
+    if (!(c->prm.flags & LBM_FLAG_UNFUSED)) return step_fused_p<P>(c, n);
   T* p = (T*)(c->fields + 2 * g.Ns * 8);
   const bool big = big3<P>(g);
   for (int64_t s = 0; s < n; ++s) {
@@ -939,6 +1342,7 @@ lbm_status lbm3_init(lbm3_ctx** out, const lbm3_params* params, void* ws, size_t
   c->nred = L.nred;
   c->red_out = (double*)(base + L.red);
   c->t = 0;
+  c->resident = 0;
   hipError_t e = qilbm::launch_zero(base, L.fields, c->stream);
   if (e == hipSuccess) {
     const Coef3<double> k = coef3<double>(c);

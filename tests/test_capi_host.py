@@ -147,8 +147,10 @@ def test_3d_precision_flags_and_init_checks(lib):
     p.precision = _lib.LBM_FP16_STORE            # not offered in 3-D
     assert lib.lbm3_workspace_bytes(byref(p)) == 0
     p = _params3()
-    p.flags = _lib.LBM_FLAG_UNFUSED              # only LBM_FLAG_NO_GAMMA
+    p.flags = 4                                  # only LBM_FLAG_NO_GAMMA and LBM_FLAG_UNFUSED
     assert lib.lbm3_workspace_bytes(byref(p)) == 0
+    p.flags = _lib.LBM_FLAG_NO_GAMMA | _lib.LBM_FLAG_UNFUSED
+    assert lib.lbm3_workspace_bytes(byref(p)) > 0
     p = _params3()
     nbytes = lib.lbm3_workspace_bytes(byref(p))
     # two population sets of 38 planes (FP64) plus fields

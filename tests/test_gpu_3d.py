@@ -218,3 +218,51 @@ def test_full_size_rt3d_crop(precision, nx, nz):
     assert _rel(gg, gr) < tg
     mass = lat.mass()
     assert np.isfinite(mass).all()
+
+
+# shapes for the fused z-sweep kernel: tiles smaller than the 64 x 16 tile
+# (multiple wraps), ragged tiles, several tiles, and segments of one or a
+# few planes (small tile counts give many segments)
+FUSED_SHAPES = [(3, 3, 3, wl.PERIODIC), (5, 4, 3, wl.WALLS_Z), (17, 9, 6, wl.PERIODIC),
+                (33, 20, 11, wl.WALLS_Z), (70, 17, 9, wl.PERIODIC), (130, 33, 40, wl.WALLS_Z),
+                (64, 16, 300, wl.PERIODIC)]
+FUSED_TOL = {"fp32": (3e-5, 1e-6)}
+
+
+@pytest.mark.parametrize("precision", ["fp32"])
+@pytest.mark.parametrize("nx,ny,nz,bc", FUSED_SHAPES)
+def test_fused_matches_four_kernel_path(nx, ny, nz, bc, precision):
+    """The fused z-sweep step (the FP32 default) and the four node kernels
+    (LBM_FLAG_UNFUSED) from the same random state, three steps: equal up to
+    the rounding order of contracted multiply-adds; the lattice total of phi
+    is equal bit for bit."""
+    from paper_1507_03521_amd import LBM_FLAG_UNFUSED
+    pb = _problem(nx, ny, nz, bc, (1e-6, -2e-6, -1e-5 if bc else 3e-6))
+    f0, g0 = wl.random_state3d(nx, ny, nz, seed=nz * 7 + nx)
+    a = _lattice(pb, g0.sum(0), precision)
+    b = _lattice(pb, g0.sum(0), precision, flags=LBM_FLAG_UNFUSED)
+    a.set_state(f0, g0)
+    b.set_state(f0, g0)
+    ma = a.mass()
+    a.step(3)
+    b.step(3)
+    fa, ga = a.get_state()
+    fb, gb = b.get_state()
+    tf, tg = FUSED_TOL[precision]
+    assert _rel(fa, fb) < tf
+    assert _rel(ga, gb) < tg
+    if precision == "fp32":
+        assert a.mass()[0] == b.mass()[0] == ma[0]
+
+
+def test_fused_one_step_matches_oracle_walls():
+    """Fused FP32 kernel against the oracle, one step, several segments."""
+    pb = _problem(70, 17, 23, wl.WALLS_Z, (2e-6, 1e-6, -2e-5))
+    f0, g0 = wl.random_state3d(70, 17, 23, seed=11)
+    lat = _lattice(pb, g0.sum(0), "fp32")
+    lat.set_state(f0, g0)
+    fa, ga = lat.get_state()
+    lat.step(1)
+    f1, g1 = lat.get_state()
+    fr, gr = O.step(fa.cpu(), ga.cpu(), _co(pb))
+    assert _rel(f1, fr) < 3e-5 and _rel(g1, gr) < 1e-6
