@@ -34,6 +34,11 @@ Readings of points the paper leaves open (each is pinned by a test):
   population whose source node lies beyond a wall is the opposite population
   of the same node after collision; stencils see mirrored ghost rows
   psi(x, -1) = psi(x, 0), psi(x, ny) = psi(x, ny - 1).
+
+Variant beyond the paper (its collisions are BGK; it cites generalisations
+with multiple relaxation times without specifying one): with
+``trt_magic`` > 0 the flow LBE f collides with two relaxation times
+(:func:`collide_f_trt`); g keeps the paper's BGK collision.
 """
 from __future__ import annotations
 
@@ -78,10 +83,11 @@ class Coefficients:
     gy: float
     rho_ref: float
     bc: int
+    trt_magic: float = 0.0          # 0: BGK for f; > 0: TRT with this magic parameter
 
 
 def coefficients(rho_A, rho_B, sigma, W, M, tau_f, tau_g, gx=0.0, gy=0.0,
-                 rho_ref=None, bc=PERIODIC, no_gamma=False) -> Coefficients:
+                 rho_ref=None, bc=PERIODIC, no_gamma=False, trt_magic=0.0) -> Coefficients:
     """beta and kappa from W = sqrt(8 kappa / beta) / |phi_A - phi_B| and
     sigma = |phi_A - phi_B|^3 sqrt(2 kappa beta) / 6 (Sec. II); lambda = M and
     alpha from lambda = c_s^2 (tau_g - 1/2) alpha (Sec. III); gamma from the
@@ -101,16 +107,19 @@ def coefficients(rho_A, rho_B, sigma, W, M, tau_f, tau_g, gx=0.0, gy=0.0,
     gamma = 0.0 if no_gamma else (rho_r - 1.0) / (PHI_A - PHI_B * rho_r)
     drho = (rho_A - rho_B) / (PHI_A - PHI_B)
     return Coefficients(beta, kappa, lam, alpha, gamma, drho, rho_A, rho_B,
-                        tau_f, tau_g, gx, gy, rho_A if rho_ref is None else rho_ref, bc)
+                        tau_f, tau_g, gx, gy, rho_A if rho_ref is None else rho_ref, bc,
+                        float(trt_magic))
 
 
-def coefficients_of(problem, sigma=None, M=None, no_gamma=False) -> Coefficients:
+def coefficients_of(problem, sigma=None, M=None, no_gamma=False,
+                    trt_magic=0.0) -> Coefficients:
     """Coefficients of a ``workloads.Problem`` (sigma and M overridable)."""
     return coefficients(problem.rho_A, problem.rho_B,
                         problem.sigma if sigma is None else sigma, problem.W,
                         problem.M if M is None else M, problem.tau_f,
                         problem.tau_g, problem.gx, problem.gy,
-                        problem.ref_density, problem.bc, no_gamma=no_gamma)
+                        problem.ref_density, problem.bc, no_gamma=no_gamma,
+                        trt_magic=trt_magic)
 
 
 # ------------------------------------------------------------ stencils
@@ -275,10 +284,12 @@ def macroscopic(f, g, co):
 
 def collide(f, g, m, co):
     """BGK collisions with forcing (Sec. III, both LBEs):
-    f_i* = f_i - (f_i - f_i^eq)/tau_f + (1 - 1/(2 tau_f)) F_i and likewise g."""
+    f_i* = f_i - (f_i - f_i^eq)/tau_f + (1 - 1/(2 tau_f)) F_i and likewise g.
+    With ``co.trt_magic`` > 0, f collides by :func:`collide_f_trt` instead."""
     fs, gs = [], []
     kf = 1.0 - 0.5 / co.tau_f
     kg = 1.0 - 0.5 / co.tau_g
+    feqs, Fs = [], []
     for i in range(9):
         feq = f_equilibrium(i, m["p"], m["rho"], m["ux"], m["uy"])
         Fi = f_source(i, m["ux"], m["uy"], m["Fx"], m["Fy"], m["drx"], m["dry"],
@@ -286,9 +297,41 @@ def collide(f, g, m, co):
         geq = g_equilibrium(i, m["phi"], m["mu"], m["ux"], m["uy"], co)
         Gi = g_source(i, m["phi"], m["rho"], m["ux"], m["uy"], m["dpx"], m["dpy"],
                       m["Fx"], m["Fy"])
+        feqs.append(feq)
+        Fs.append(Fi)
         fs.append(f[i] - (f[i] - feq) / co.tau_f + kf * Fi)
         gs.append(g[i] - (g[i] - geq) / co.tau_g + kg * Gi)
+    if co.trt_magic > 0.0:
+        fs = collide_f_trt(f, feqs, Fs, co)
     return torch.stack(fs), torch.stack(gs)
+
+
+def tau_minus(co):
+    """Relaxation time of the odd part: the magic parameter is
+    Lambda = (tau_f - 1/2)(tau_- - 1/2)."""
+    return 0.5 + co.trt_magic / (co.tau_f - 0.5)
+
+
+def collide_f_trt(f, feq, F, co):
+    """Two-relaxation-time collision of f with forcing (Ginzburg, Verhaeghe
+    and d'Humieres, 2008): populations, equilibria and sources are split into
+    parts even and odd under c_i -> -c_i, x_i^(+-) = (x_i +- x_opp(i)) / 2;
+    the even part relaxes with tau_f (it carries the viscous stress), the odd
+    part with tau_- (:func:`tau_minus`), and each source part takes its own
+    factor 1 - 1/(2 tau):
+    f_i* = f_i - (f_i^+ - f_i^eq+)/tau_f - (f_i^- - f_i^eq-)/tau_-
+           + (1 - 1/(2 tau_f)) F_i^+ + (1 - 1/(2 tau_-)) F_i^-.
+    tau_- = tau_f (Lambda = (tau_f - 1/2)^2) is the BGK collision."""
+    tm = tau_minus(co)
+    out = []
+    for i in range(9):
+        o = OPPOSITE[i]
+        fp, fm = 0.5 * (f[i] + f[o]), 0.5 * (f[i] - f[o])
+        ep, em = 0.5 * (feq[i] + feq[o]), 0.5 * (feq[i] - feq[o])
+        sp, sm = 0.5 * (F[i] + F[o]), 0.5 * (F[i] - F[o])
+        out.append(f[i] - (fp - ep) / co.tau_f - (fm - em) / tm
+                   + (1.0 - 0.5 / co.tau_f) * sp + (1.0 - 0.5 / tm) * sm)
+    return out
 
 
 def stream(pop, bc):
