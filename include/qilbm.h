@@ -95,6 +95,19 @@ typedef struct {
   int32_t bc;             /* lbm_bc                                          */
   int32_t precision;      /* lbm_precision                                   */
   uint32_t flags;         /* LBM_FLAG_*                                      */
+  double trt_magic;       /* 0: the paper's BGK collision of f. > 0: a
+                             two-relaxation-time collision of f (a variant
+                             beyond the paper, which cites generalisations
+                             with several relaxation times but specifies
+                             none): f, f^eq and F_i split into parts even and
+                             odd under c_i -> -c_i; the even part relaxes with
+                             tau_f, the odd part with tau_- = 1/2 + trt_magic /
+                             (tau_f - 1/2), each source part with its own
+                             1 - 1/(2 tau). g keeps BGK. 3/16 puts half-way
+                             bounce-back walls exactly half-way for any tau_f.
+                             With TRT the step runs one time step per pass,
+                             and step records and the adjoint are refused
+                             (LBM_EINVAL). Finite, >= 0.                    */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -22,7 +22,8 @@ class LbmParams(ctypes.Structure):
     _fields_ = [("nx", c_int32), ("ny", c_int32), ("rho_A", c_double), ("rho_B", c_double),
                 ("sigma", c_double), ("W", c_double), ("M", c_double), ("tau_f", c_double),
                 ("tau_g", c_double), ("gx", c_double), ("gy", c_double), ("rho_ref", c_double),
-                ("bc", c_int32), ("precision", c_int32), ("flags", c_uint32)]
+                ("bc", c_int32), ("precision", c_int32), ("flags", c_uint32),
+                ("trt_magic", c_double)]
 
 
 class Lbm3Params(ctypes.Structure):
@@ -126,14 +127,15 @@ def check(status: int, what: str = "") -> None:
 
 def make_params(p: dict, precision="fp64", flags: int = 0) -> LbmParams:
     """lbm_params from a mapping with keys nx, ny, rho_A, rho_B, sigma, W, M,
-    tau_f, tau_g and optionally gx, gy, rho_ref (default rho_A), bc."""
+    tau_f, tau_g and optionally gx, gy, rho_ref (default rho_A), bc and
+    trt_magic (0: BGK collision of f; > 0: two-relaxation-time collision)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     rho_ref = p.get("rho_ref")
     return LbmParams(int(p["nx"]), int(p["ny"]), float(p["rho_A"]), float(p["rho_B"]),
                      float(p["sigma"]), float(p["W"]), float(p["M"]), float(p["tau_f"]),
                      float(p["tau_g"]), float(p.get("gx", 0.0)), float(p.get("gy", 0.0)),
                      float(p["rho_A"] if rho_ref is None else rho_ref), int(p.get("bc", 0)),
-                     prec, int(flags))
+                     prec, int(flags), float(p.get("trt_magic", 0.0)))
 
 
 def make_params3(p: dict, precision="fp64", flags: int = 0) -> Lbm3Params:

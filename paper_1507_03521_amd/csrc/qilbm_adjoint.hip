@@ -1174,8 +1174,10 @@ using namespace qilbm;
 
 extern "C" {
 
+// The adjoint transposes the BGK collisions only: contexts with the
+// two-relaxation-time variant are refused.
 size_t lbm_adjoint_workspace_bytes(const lbm_params* params) {
-  if (!params || lbm_workspace_bytes(params) == 0) return 0;
+  if (!params || lbm_workspace_bytes(params) == 0 || params->trt_magic > 0.0) return 0;
   return adj_layout(params).total;
 }
 
@@ -1183,6 +1185,7 @@ lbm_status lbm_adjoint_begin(lbm_ctx* ctx, void* ws, size_t bytes, const double*
   if (!ctx || !ws || !dL_dphi) return LBM_EINVAL;
   if ((uintptr_t)ws % ALIGN != 0) return LBM_EINVAL;
   CtxView v = ctx_view(ctx);
+  if (v.prm->trt_magic > 0.0) return LBM_EINVAL;
   const AdjLayout L = adj_layout(v.prm);
   if (bytes < L.total) return LBM_ENOMEM;
   AdjointState& a = *v.adj;
@@ -1221,6 +1224,7 @@ lbm_status lbm_adjoint_seed(lbm_ctx* ctx, const double* dL_dphi) {
 lbm_status lbm_adjoint_step(lbm_ctx* ctx, const void* fwd_state) {
   if (!ctx || !fwd_state) return LBM_EINVAL;
   CtxView v = ctx_view(ctx);
+  if (v.prm->trt_magic > 0.0) return LBM_EINVAL;
   if (!v.adj->active) return LBM_ESTATE;
   switch (v.prm->precision) {
     case LBM_FP64: return adj_step_p<P_F64>(v, fwd_state);
@@ -1233,6 +1237,7 @@ lbm_status lbm_adjoint_step_record(lbm_ctx* ctx, const void* record_dev) {
   if (!ctx || !record_dev) return LBM_EINVAL;
   if ((uintptr_t)record_dev % ALIGN != 0) return LBM_EINVAL;
   CtxView v = ctx_view(ctx);
+  if (v.prm->trt_magic > 0.0) return LBM_EINVAL;
   if (!v.adj->active) return LBM_ESTATE;
   if (v.prm->precision == LBM_FP64) return adj_core<double>(v, (const double*)record_dev);
   return adj_core<float>(v, (const float*)record_dev);

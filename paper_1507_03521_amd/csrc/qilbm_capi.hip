@@ -41,7 +41,7 @@ inline size_t up(size_t v) { return (v + ALIGN - 1) / ALIGN * ALIGN; }
 
 bool finite_all(const lbm_params* p) {
   const double v[] = {p->rho_A, p->rho_B, p->sigma, p->W, p->M, p->tau_f, p->tau_g,
-                      p->gx,    p->gy,    p->rho_ref};
+                      p->gx,    p->gy,    p->rho_ref, p->trt_magic};
   for (double d : v)
     if (!isfinite(d)) return false;
   return true;
@@ -60,6 +60,7 @@ bool valid(const lbm_params* p) {
   if (p->bc != LBM_BC_PERIODIC && p->bc != LBM_BC_WALLS_Y) return false;
   if (p->precision < LBM_FP64 || p->precision > LBM_FP16_STORE) return false;
   if (p->flags & ~(uint32_t)(LBM_FLAG_NO_GAMMA | LBM_FLAG_UNFUSED)) return false;
+  if (!(p->trt_magic >= 0.0)) return false;
   return true;
 }
 
@@ -124,8 +125,15 @@ Coef<T> coef_t(const lbm_ctx* c) {
   k.inv_tau_g = T(1.0 / c->prm.tau_g);
   k.kf = T(1.0 - 0.5 / c->prm.tau_f);
   k.kg = T(1.0 - 0.5 / c->prm.tau_g);
+  // odd part of the TRT collision: tau_- = 1/2 + magic / (tau_f - 1/2)
+  const double tau_m =
+      c->prm.trt_magic > 0.0 ? 0.5 + c->prm.trt_magic / (c->prm.tau_f - 0.5) : c->prm.tau_f;
+  k.inv_tau_m = T(1.0 / tau_m);
+  k.km = T(1.0 - 0.5 / tau_m);
   return k;
 }
+
+bool trt_of(const lbm_ctx* c) { return c->prm.trt_magic > 0.0; }
 
 lbm_status st(hipError_t e) { return e == hipSuccess ? LBM_OK : LBM_EDEVICE; }
 
@@ -142,9 +150,11 @@ lbm_status step_p(lbm_ctx* c, int64_t n, void* const* recs) {
   using T = typename PrecT<P>::T;
   const Coef<T> k = coef_t<T>(c);
   const bool unfused = c->prm.flags & LBM_FLAG_UNFUSED;
+  const bool trt = trt_of(c);
+  if (trt && recs) return LBM_EINVAL;
   const int64_t pl = c->geom.Ns;
   int64_t done = 0;
-  if (!unfused && c->pass_steps == 2 && n >= 2) {
+  if (!unfused && !trt && c->pass_steps == 2 && n >= 2) {
     const FusedShape sh2 = fused2_shape<P>(c->geom, c->pass_seg_rows, c->resident2);
     for (; n - done >= 2; done += 2) {
       void* r0 = recs ? recs[done] : nullptr;
@@ -165,10 +175,10 @@ lbm_status step_p(lbm_ctx* c, int64_t n, void* const* recs) {
                                  (T*)rec + 2 * pl, (T*)rec + 3 * pl, k, c->geom, c->stream);
     else if (unfused)
       e = launch_step_unfused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], phi_f(c), mu_f(c), p_f(c),
-                                 nullptr, k, c->geom, c->stream);
+                                 nullptr, k, c->geom, c->stream, trt);
     else
       e = launch_step_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh, rec,
-                               c->stream);
+                               c->stream, trt);
     if (e != hipSuccess) return LBM_EDEVICE;
     c->cur ^= 1;
     c->t += 1;
@@ -250,7 +260,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
   // two steps per pass where it is the faster kernel (FP32, FP64); FP16
   // storage keeps one (its two-step kernel measured slower: the binary16
   // conversions of the intermediate state make it arithmetic-bound)
-  c->pass_steps = params->precision == LBM_FP16_STORE ? 1 : 2;
+  c->pass_steps = (params->precision == LBM_FP16_STORE || params->trt_magic > 0.0) ? 1 : 2;
   c->pass_seg_rows = 0;
   c->resident2 = QILBM_DISPATCH(params->precision, fused2_resident);
   c->pbytes = pop_bytes(params->precision, c->geom.Ns);
@@ -280,14 +290,14 @@ size_t lbm_record_bytes(const lbm_ctx* c) {
 }
 
 lbm_status lbm_step_record(lbm_ctx* c, void* record_dev) {
-  if (!c || !record_dev) return LBM_EINVAL;
+  if (!c || !record_dev || trt_of(c)) return LBM_EINVAL;
   if ((uintptr_t)record_dev % ALIGN != 0) return LBM_EINVAL;
   void* const recs[1] = {record_dev};
   return QILBM_DISPATCH(c->prm.precision, step_p, c, 1, recs);
 }
 
 lbm_status lbm_step_records(lbm_ctx* c, int64_t nsteps, void* const* records) {
-  if (!c || nsteps < 0 || (nsteps > 0 && !records)) return LBM_EINVAL;
+  if (!c || nsteps < 0 || (nsteps > 0 && !records) || trt_of(c)) return LBM_EINVAL;
   for (int64_t k = 0; k < nsteps; ++k)
     if (!records[k] || (uintptr_t)records[k] % ALIGN != 0) return LBM_EINVAL;
   return QILBM_DISPATCH(c->prm.precision, step_p, c, nsteps, records);
@@ -374,6 +384,7 @@ lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
 
 lbm_status lbm_set_pass(lbm_ctx* c, int32_t steps, int32_t seg_rows) {
   if (!c || seg_rows < 0 || (steps != 1 && steps != 2)) return LBM_EINVAL;
+  if (steps == 2 && trt_of(c)) return LBM_EINVAL;
   c->pass_steps = steps;
   c->pass_seg_rows = seg_rows;
   return LBM_OK;

@@ -44,6 +44,9 @@ struct Coef {
   T gx, gy;     // gravity
   T inv_tau_f, inv_tau_g;
   T kf, kg;     // 1 - 1 / (2 tau)
+  // two-relaxation-time collision of f (used by the TRT kernel variants):
+  // 1 / tau_- and 1 - 1 / (2 tau_-) of the part odd under c_i -> -c_i
+  T inv_tau_m, km;
 };
 
 struct Geom {
@@ -364,6 +367,52 @@ __device__ __forceinline__ void collide_node(T f[9], T g[9], const Macro<T>& m, 
     const T Gi = gpre * w * gm * (cxu * hx + cyu * hy);
     f[i] = f[i] - (f[i] - feq) * c.inv_tau_f + c.kf * Fi;
     g[i] = g[i] - (g[i] - geq) * c.inv_tau_g + c.kg * Gi;
+  }
+}
+
+// Two-relaxation-time variant of the f collision (g keeps BGK): f, f^eq and
+// F_i split into parts even and odd under c_i -> -c_i; the even part relaxes
+// with tau_f, the odd part with tau_- (magic parameter
+// (tau_f - 1/2)(tau_- - 1/2)), and each source part takes its own
+// 1 - 1/(2 tau) (Ginzburg, Verhaeghe and d'Humieres, 2008). The rest
+// population has no odd part.
+template <typename T>
+__device__ __forceinline__ void collide_node_trt(T f[9], T g[9], const Macro<T>& m, T dpx,
+                                                 T dpy, const Coef<T>& c) {
+  const T usq = m.ux * m.ux + m.uy * m.uy;
+  const T gpre = -T(3) * m.phi * recip(m.rho);
+  const T hx = dpx - m.Fx, hy = dpy - m.Fy;
+  const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
+  const T amu = c.alpha * m.mu;
+  const T r3 = m.rho * T(1.0 / 3.0);
+  const T dx3 = m.drx * T(1.0 / 3.0), dy3 = m.dry * T(1.0 / 3.0);
+  T feq[9], Fs[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const T w = T(WGT(i));
+    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
+    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
+    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T gm = T(1) + s;
+    feq[i] = w * (m.p + r3 * s);
+    Fs[i] = w * (cxu * (gm * m.Fx + s * dx3) + cyu * (gm * m.Fy + s * dy3) + src1);
+    const T H = (i == 0) ? m.phi - T(1.0 - 4.0 / 9.0) * amu : w * amu;
+    const T geq = H + w * m.phi * s;
+    const T Gi = gpre * w * gm * (cxu * hx + cyu * hy);
+    g[i] = g[i] - (g[i] - geq) * c.inv_tau_g + c.kg * Gi;
+  }
+  f[0] = f[0] - (f[0] - feq[0]) * c.inv_tau_f + c.kf * Fs[0];
+#pragma unroll
+  for (int i = 1; i < 9; ++i) {
+    const int o = OPP(i);
+    if (o < i) continue;
+    const T fp = T(0.5) * (f[i] + f[o]), fm = T(0.5) * (f[i] - f[o]);
+    const T ep = T(0.5) * (feq[i] + feq[o]), em = T(0.5) * (feq[i] - feq[o]);
+    const T sp = T(0.5) * (Fs[i] + Fs[o]), sm = T(0.5) * (Fs[i] - Fs[o]);
+    const T dp = c.kf * sp - (fp - ep) * c.inv_tau_f;
+    const T dm = c.km * sm - (fm - em) * c.inv_tau_m;
+    f[i] = f[i] + dp + dm;
+    f[o] = f[o] + dp - dm;
   }
 }
 

@@ -70,13 +70,16 @@ hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* 
 template <int P>
 hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu, void* p,
                                void* sj, const Coef<typename PrecT<P>::T>& c, const Geom& g,
-                               hipStream_t s);
+                               hipStream_t s, bool trt = false);
 // One fused step; when rec is not null it also writes the forward quantities
 // of the state it reads (the record: planes phi, mu, p, S, jx, jy of the
 // compute type at stride Ns).
+// trt selects the two-relaxation-time collision of f (no recording variant:
+// rec must then be null).
 template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
-                             const Geom& g, const FusedShape& sh, void* rec, hipStream_t s);
+                             const Geom& g, const FusedShape& sh, void* rec, hipStream_t s,
+                             bool trt = false);
 // Two steps per launch: the state between the two steps stays on chip.
 // With rec0 and rec1 not null it also writes the records of the state it
 // reads (rec0) and of the state after the first step (rec1). Its shape, for

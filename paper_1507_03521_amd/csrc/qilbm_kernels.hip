@@ -252,7 +252,7 @@ __device__ __forceinline__ double pull_phi_exact(const Pop<P>& in, int x, int y,
 
 // Collision with all fields materialised; post-collision values stay at
 // their node (pull layout).
-template <int P>
+template <int P, bool TRT = false>
 __global__ __launch_bounds__(256) void k_collide(Pop<P> in, Pop<P> out,
                                                  const typename PrecT<P>::T* __restrict__ phi,
                                                  const typename PrecT<P>::T* __restrict__ mu,
@@ -271,7 +271,8 @@ __global__ __launch_bounds__(256) void k_collide(Pop<P> in, Pop<P> out,
   stencil(v, dpx, dpy, lapp);
   int32_t phi_q = 0;
   if constexpr (FixedG<P>::value) phi_q = pull_phi_q<P>(in, x, y, g);
-  collide_node(f, gg, m, dpx, dpy, c);
+  if constexpr (TRT) collide_node_trt(f, gg, m, dpx, dpy, c);
+  else collide_node(f, gg, m, dpx, dpy, c);
   store_node<P>(out, (uint32_t)n, f, gg, phi_q);
 }
 
@@ -732,7 +733,7 @@ __device__ __forceinline__ bool need_p(const FusedCtx<P, BIG>& k, int q) {
   return k.act && k.lc >= 2 && k.lc < k.wi + 4 && q >= k.y0 - 1 && q < k.y1 + 1 && row_ok(q, k.g);
 }
 
-template <int P, bool BIG, bool REC, int J, int NT>
+template <int P, bool BIG, bool REC, int J, int NT, bool TRT = false>
 __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
                                            typename BufT<P>::R (&gb)[4][9],
                                            typename BufT<P>::R (&fb)[2][9],
@@ -855,7 +856,8 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
     m.p = v[1][1];
     stencil(v, dpx, dpy, lapp);
     const int32_t phi_q = FixedG<P>::value ? L.phiq[cr & 7][lc] : 0;
-    collide_node(f, gg, m, dpx, dpy, k.c);
+    if constexpr (TRT) collide_node_trt(f, gg, m, dpx, dpy, k.c);
+    else collide_node(f, gg, m, dpx, dpy, k.c);
     store_row<P, BIG>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
   }
 }
@@ -874,7 +876,7 @@ template <> struct FusedWaves<P_F64> { static constexpr int value = 2; };
 // workgroup per CU at that register count, gave 28.7).
 template <int P> struct FusedThreads { static constexpr int value = 256; };
 
-template <int P, bool BIG, bool REC>
+template <int P, bool BIG, bool REC, bool TRT = false>
 __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void k_step_fused(Pop<P> in, Pop<P> out,
                                                    Coef<typename PrecT<P>::T> c, Geom g, int width,
                                                    int nstrips, int seg_len,
@@ -920,10 +922,10 @@ __global__ __launch_bounds__(FusedThreads<P>::value, FusedWaves<P>::value) void 
     if constexpr (P == P_F16) f0b[0] = pull_f0(k, phys_row(r0, g));
   }
   for (int it = 0; it < nit; it += 4) {
-    fused_iter<P, BIG, REC, 0, NT>(k, r0 + k.d * (it + 0), gb, fb, f0b, L);
-    fused_iter<P, BIG, REC, 1, NT>(k, r0 + k.d * (it + 1), gb, fb, f0b, L);
-    fused_iter<P, BIG, REC, 2, NT>(k, r0 + k.d * (it + 2), gb, fb, f0b, L);
-    fused_iter<P, BIG, REC, 3, NT>(k, r0 + k.d * (it + 3), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 0, NT, TRT>(k, r0 + k.d * (it + 0), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 1, NT, TRT>(k, r0 + k.d * (it + 1), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 2, NT, TRT>(k, r0 + k.d * (it + 2), gb, fb, f0b, L);
+    fused_iter<P, BIG, REC, 3, NT, TRT>(k, r0 + k.d * (it + 3), gb, fb, f0b, L);
   }
 }
 
@@ -1474,15 +1476,19 @@ hipError_t launch_macro(const void* pop, const void* phi, const void* mu, void* 
 template <int P>
 hipError_t launch_step_unfused(const void* pin, void* pout, void* phi, void* mu, void* p,
                                void* sj, const Coef<typename PrecT<P>::T>& c, const Geom& g,
-                               hipStream_t s) {
+                               hipStream_t s, bool trt) {
   using T = typename PrecT<P>::T;
   hipError_t e = launch_fields<P>(pin, phi, mu, c, g, s);
   if (e != hipSuccess) return e;
   e = launch_macro<P>(pin, phi, mu, p, sj, MomentOut{}, c, g, s);
   if (e != hipSuccess) return e;
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
-  hipLaunchKernelGGL(k_collide<P>, dim3(nblk(g.N, 256)), dim3(256), 0, s, i, o, (const T*)phi,
-                     (const T*)mu, (const T*)p, c, g);
+  if (trt)
+    hipLaunchKernelGGL((k_collide<P, true>), dim3(nblk(g.N, 256)), dim3(256), 0, s, i, o,
+                       (const T*)phi, (const T*)mu, (const T*)p, c, g);
+  else
+    hipLaunchKernelGGL(k_collide<P>, dim3(nblk(g.N, 256)), dim3(256), 0, s, i, o, (const T*)phi,
+                       (const T*)mu, (const T*)p, c, g);
   return hipGetLastError();
 }
 
@@ -1531,21 +1537,27 @@ int fused_resident() {
   return cus * (per_cu > 0 ? per_cu : 1);
 }
 
-template <int P, bool BIG, bool REC>
+template <int P, bool BIG, bool REC, bool TRT = false>
 static void launch_fused_variant(const Pop<P>& i, const Pop<P>& o,
                                  const Coef<typename PrecT<P>::T>& c, const Geom& g,
                                  const FusedShape& sh, void* rec, hipStream_t s) {
   using T = typename PrecT<P>::T;
-  hipLaunchKernelGGL((k_step_fused<P, BIG, REC>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads), 0,
-                     s, i, o, c, g, sh.width, sh.nstrips, sh.seg_rows, (T*)rec);
+  hipLaunchKernelGGL((k_step_fused<P, BIG, REC, TRT>), dim3(sh.nstrips * sh.nseg),
+                     dim3(sh.threads), 0, s, i, o, c, g, sh.width, sh.nstrips, sh.seg_rows,
+                     (T*)rec);
 }
 
 template <int P>
 hipError_t launch_step_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
-                             const Geom& g, const FusedShape& sh, void* rec, hipStream_t s) {
+                             const Geom& g, const FusedShape& sh, void* rec, hipStream_t s,
+                             bool trt) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
   const bool big = fused_big<P>(g);
-  if (rec) {
+  if (trt) {
+    if (rec) return hipErrorInvalidValue;       // no recording TRT variant
+    if (big) launch_fused_variant<P, true, false, true>(i, o, c, g, sh, rec, s);
+    else launch_fused_variant<P, false, false, true>(i, o, c, g, sh, rec, s);
+  } else if (rec) {
     if (big) launch_fused_variant<P, true, true>(i, o, c, g, sh, rec, s);
     else launch_fused_variant<P, false, true>(i, o, c, g, sh, rec, s);
   } else {
@@ -1645,9 +1657,11 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
                                       const MomentOut&, const Coef<PrecT<P>::T>&, const Geom&,   \
                                       hipStream_t);                                              \
   template hipError_t launch_step_unfused<P>(const void*, void*, void*, void*, void*, void*,     \
-                                             const Coef<PrecT<P>::T>&, const Geom&, hipStream_t); \
+                                             const Coef<PrecT<P>::T>&, const Geom&, hipStream_t,  \
+                                             bool);                                               \
   template hipError_t launch_step_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,         \
-                                           const Geom&, const FusedShape&, void*, hipStream_t);  \
+                                           const Geom&, const FusedShape&, void*, hipStream_t,   \
+                                           bool);                                                \
   template int fused_resident<P>();                                                              \
   template FusedShape fused_shape<P>(const Geom&, int, int);                                     \
   template bool fused_big<P>(const Geom&);                                                       \

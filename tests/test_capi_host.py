@@ -172,3 +172,14 @@ def test_3d_null_context_calls(lib):
     assert lib.lbm3_set_state(None, None, None) == _lib.LBM_EINVAL
     assert lib.lbm3_time(None) == -1
     lib.lbm3_destroy(None)
+
+
+def test_trt_parameter_checks(lib):
+    """trt_magic: finite and >= 0 (0 is the BGK collision); the adjoint
+    refuses the two-relaxation-time variant."""
+    for bad in (-0.1, float("nan"), float("inf")):
+        assert lib.lbm_workspace_bytes(byref(_params(trt_magic=bad))) == 0
+    p = _params(trt_magic=0.25)
+    assert lib.lbm_workspace_bytes(byref(p)) == lib.lbm_workspace_bytes(byref(_params()))
+    assert lib.lbm_adjoint_workspace_bytes(byref(p)) == 0
+    assert lib.lbm_adjoint_workspace_bytes(byref(_params())) > 0
