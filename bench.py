@@ -10,8 +10,9 @@ streaming). FP64 and FP32 run two steps per launch of the fused kernel
 Printed: ONE JSON line. ``value`` is the FP32 rate in MLUPS (million lattice
 updates per second); the line also carries the FP64 and FP16-storage rates
 with their deviation from the FP64 GPU run, the adjoint/forward step-time
-ratio, the roofline position of the fused kernel, the CPU-oracle rate and
-the three-dimensional (D3Q19, 256^3 box) step's rates.
+ratio, the roofline position of the fused kernel, the CPU-oracle rate, the
+rate with the two-relaxation-time collision variant and the
+three-dimensional (D3Q19, 256^3 box) step's rates.
 """
 from __future__ import annotations
 
@@ -74,6 +75,25 @@ def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
     info = lat.pass_info()
     del lat
     return ms, phi, m0, m1, info
+
+
+def run_trt(pb, phi0, steps: int, warmup: int, magic: float = 0.25):
+    """FP32 step with the two-relaxation-time collision of f (one step per
+    launch of the fused kernel) next to the BGK one-step kernel on the same
+    lattice."""
+    from paper_1507_03521_amd import Lattice
+    N = pb.nx * pb.ny
+    out = {"magic": magic, "precision": "fp32", "steps_per_launch": 1}
+    for name, m in (("bgk_one_step", 0.0), ("trt", magic)):
+        lat = Lattice(dict(pb.as_dict(), trt_magic=m), phi0, precision="fp32", device="cuda:0")
+        lat.set_pass(1)
+        ms = timed_steps(lat, steps, warmup)
+        del lat
+        out[name] = dict(mlups=round(N / ms / 1e3, 2), ms_per_step=round(ms, 5),
+                         hbm_roofline_frac=round(BYTES_PER_LU["fp32"] * N / (ms * 1e-3) / 1e9
+                                                 / PEAK_HBM_GBS, 4))
+        log(f"  {name}: {ms:.4f} ms/step")
+    return out
 
 
 # D3Q19: 19 f and 19 g read and written once per node and step
@@ -371,6 +391,8 @@ def main():
     ap.add_argument("--no-3d", action="store_true",
                     help="skip the three-dimensional (D3Q19) 256^3 leg")
     ap.add_argument("--steps-3d", type=int, default=200)
+    ap.add_argument("--no-trt", action="store_true",
+                    help="skip the two-relaxation-time (FP32, one step per launch) leg")
     ap.add_argument("--cpu-rows", type=int, default=2048)
     ap.add_argument("--cpu-steps", type=int, default=8)
     ap.add_argument("--copy-calibration", action="store_true",
@@ -478,6 +500,9 @@ def main():
     if not args.no_adjoint and main_prec in ("fp32", "fp64"):
         log("timing adjoint")
         line["adjoint"] = adjoint_ratio(pb, phi0, main_prec, ms)
+    if not args.no_trt:
+        log("timing the two-relaxation-time collision variant")
+        line["trt"] = run_trt(pb, phi0, 200, 20)
     if not args.no_3d:
         log("timing the three-dimensional step")
         line["d3q19"] = run_3d(args.steps_3d, max(1, args.steps_3d // 10))
