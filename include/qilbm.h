@@ -105,9 +105,8 @@ typedef struct {
                              (tau_f - 1/2), each source part with its own
                              1 - 1/(2 tau). g keeps BGK. 3/16 puts half-way
                              bounce-back walls exactly half-way for any tau_f.
-                             With TRT the step runs one time step per pass,
-                             and step records and the adjoint are refused
-                             (LBM_EINVAL). Finite, >= 0.                    */
+                             With TRT, step records and the adjoint are
+                             refused (LBM_EINVAL). Finite, >= 0.            */
 } lbm_params;
 
 typedef struct lbm_ctx lbm_ctx;

@@ -154,13 +154,13 @@ lbm_status step_p(lbm_ctx* c, int64_t n, void* const* recs) {
   if (trt && recs) return LBM_EINVAL;
   const int64_t pl = c->geom.Ns;
   int64_t done = 0;
-  if (!unfused && !trt && c->pass_steps == 2 && n >= 2) {
+  if (!unfused && c->pass_steps == 2 && n >= 2) {
     const FusedShape sh2 = fused2_shape<P>(c->geom, c->pass_seg_rows, c->resident2);
     for (; n - done >= 2; done += 2) {
       void* r0 = recs ? recs[done] : nullptr;
       void* r1 = recs ? recs[done + 1] : nullptr;
       if (launch_step2_fused<P>(c->pop[c->cur], c->pop[c->cur ^ 1], k, c->geom, sh2, r0, r1,
-                                c->stream) != hipSuccess)
+                                c->stream, trt) != hipSuccess)
         return LBM_EDEVICE;
       c->cur ^= 1;
       c->t += 2;
@@ -260,7 +260,7 @@ lbm_status lbm_init(lbm_ctx** out, const lbm_params* params, void* workspace_dev
   // two steps per pass where it is the faster kernel (FP32, FP64); FP16
   // storage keeps one (its two-step kernel measured slower: the binary16
   // conversions of the intermediate state make it arithmetic-bound)
-  c->pass_steps = (params->precision == LBM_FP16_STORE || params->trt_magic > 0.0) ? 1 : 2;
+  c->pass_steps = params->precision == LBM_FP16_STORE ? 1 : 2;
   c->pass_seg_rows = 0;
   c->resident2 = QILBM_DISPATCH(params->precision, fused2_resident);
   c->pbytes = pop_bytes(params->precision, c->geom.Ns);
@@ -384,7 +384,6 @@ lbm_status lbm_launch_info(const lbm_ctx* c, int32_t out[4]) {
 
 lbm_status lbm_set_pass(lbm_ctx* c, int32_t steps, int32_t seg_rows) {
   if (!c || seg_rows < 0 || (steps != 1 && steps != 2)) return LBM_EINVAL;
-  if (steps == 2 && trt_of(c)) return LBM_EINVAL;
   c->pass_steps = steps;
   c->pass_seg_rows = seg_rows;
   return LBM_OK;

@@ -91,7 +91,7 @@ int fused2_resident();
 template <int P>
 hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
                               const Geom& g, const FusedShape& sh, void* rec0, void* rec1,
-                              hipStream_t s);
+                              hipStream_t s, bool trt = false);
 template <int P>
 hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
                        const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);

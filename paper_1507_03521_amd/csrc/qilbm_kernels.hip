@@ -1241,7 +1241,7 @@ __device__ __forceinline__ void stage_macro(StageRings<typename PrecT<P>::T, NT>
 
 // Stage D of one pipeline: collision of row cr (f, gg hold its pulled
 // populations on entry, the post-collision ones on exit).
-template <typename T, int NT>
+template <typename T, int NT, bool TRT = false>
 __device__ __forceinline__ void stage_collide(const StageRings<T, NT>& S, int cr, const Geom& g,
                                               int lc, const Coef<T>& c, const T nd[NM], T f[9],
                                               T gg[9]) {
@@ -1260,10 +1260,11 @@ __device__ __forceinline__ void stage_collide(const StageRings<T, NT>& S, int cr
   lds3x3<T, NT>(S.p, 3, cr, g.ny, g.walls, lc, v);
   m.p = v[1][1];
   stencil(v, dpx, dpy, lapp);
-  collide_node(f, gg, m, dpx, dpy, c);
+  if constexpr (TRT) collide_node_trt(f, gg, m, dpx, dpy, c);
+  else collide_node(f, gg, m, dpx, dpy, c);
 }
 
-template <int P, bool BIG, bool REC, int J, int NT>
+template <int P, bool BIG, bool REC, int J, int NT, bool TRT = false>
 __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, int s,
                                             Row<P> (&rb1)[4], Row<MidP<P>::value> (&rb2)[4],
                                             typename PrecT<P>::T (&nd1)[2][NM],
@@ -1330,7 +1331,7 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
     row_unpack<P>(rb1[(J + 1) & 3], f, gg);
     if (in_stage(k, r + d, 0)) load_row<P, BIG>(k, phys_row(r + d, g), rb1[(J + 1) & 3]);
     if (in_stage(k, cr, 3)) {
-      stage_collide<T, NT>(L.s1, cr, g, lc, k.c, nd1[(J + 1) & 1], f, gg);
+      stage_collide<T, NT, TRT>(L.s1, cr, g, lc, k.c, nd1[(J + 1) & 1], f, gg);
       Row<P2> o;
       row_pack<P2>(f, gg, phi_q, o);
       ring_put<P2, NT>(L.mid, s, lc, o);
@@ -1344,7 +1345,7 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
       int32_t phi_q;
       row_phi<P2>(rb2[(J + 1) & 3], phi_q);
       row_unpack<P2>(rb2[(J + 1) & 3], f, gg);
-      stage_collide<T, NT>(L.s2, cr, g, lc, k.c, nd2[(J + 1) & 1], f, gg);
+      stage_collide<T, NT, TRT>(L.s2, cr, g, lc, k.c, nd2[(J + 1) & 1], f, gg);
       store_node2<P, BIG>(k, (uint32_t)(cr * g.nx), f, gg, phi_q);
     }
   }
@@ -1359,7 +1360,7 @@ template <> struct Fused2Waves<P_F64> { static constexpr int value = 1; };
 
 // REC: also writes the records of the two states the pass starts from
 // (rec0: the state read, rec1: the state after the first step).
-template <int P, bool BIG, bool REC>
+template <int P, bool BIG, bool REC, bool TRT = false>
 __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
     Pop<P> in, Pop<P> out, Coef<typename PrecT<P>::T> c, Geom g, int width, int nstrips,
     int seg_len, typename PrecT<P>::T* rec0, typename PrecT<P>::T* rec1) {
@@ -1397,16 +1398,16 @@ __global__ __launch_bounds__(256, Fused2Waves<P>::value) void k_step2_fused(
   if (in_stage(k, r0, 0)) load_row<P, BIG>(k, phys_row(r0, g), rb1[0]);
   int s = 0;   // ring slot D1 writes in this iteration: iteration index mod 3
   for (int it = 0; it < nit; it += 4) {
-    fused2_iter<P, BIG, REC, 0, NT>(k, r0 + k.d * (it + 0), s, rb1, rb2, nd1, nd2, L, rec0,
+    fused2_iter<P, BIG, REC, 0, NT, TRT>(k, r0 + k.d * (it + 0), s, rb1, rb2, nd1, nd2, L, rec0,
                                  rec1);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, REC, 1, NT>(k, r0 + k.d * (it + 1), s, rb1, rb2, nd1, nd2, L, rec0,
+    fused2_iter<P, BIG, REC, 1, NT, TRT>(k, r0 + k.d * (it + 1), s, rb1, rb2, nd1, nd2, L, rec0,
                                  rec1);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, REC, 2, NT>(k, r0 + k.d * (it + 2), s, rb1, rb2, nd1, nd2, L, rec0,
+    fused2_iter<P, BIG, REC, 2, NT, TRT>(k, r0 + k.d * (it + 2), s, rb1, rb2, nd1, nd2, L, rec0,
                                  rec1);
     s = s == 2 ? 0 : s + 1;
-    fused2_iter<P, BIG, REC, 3, NT>(k, r0 + k.d * (it + 3), s, rb1, rb2, nd1, nd2, L, rec0,
+    fused2_iter<P, BIG, REC, 3, NT, TRT>(k, r0 + k.d * (it + 3), s, rb1, rb2, nd1, nd2, L, rec0,
                                  rec1);
     s = s == 2 ? 0 : s + 1;
   }
@@ -1601,22 +1602,27 @@ int fused2_resident() {
   return cus * (per_cu > 0 ? per_cu : 1);
 }
 
-template <int P, bool BIG, bool REC>
+template <int P, bool BIG, bool REC, bool TRT = false>
 static void launch_fused2_variant(const Pop<P>& i, const Pop<P>& o,
                                   const Coef<typename PrecT<P>::T>& c, const Geom& g,
                                   const FusedShape& sh, void* rec0, void* rec1, hipStream_t s) {
   using T = typename PrecT<P>::T;
-  hipLaunchKernelGGL((k_step2_fused<P, BIG, REC>), dim3(sh.nstrips * sh.nseg), dim3(sh.threads),
-                     0, s, i, o, c, g, sh.width, sh.nstrips, sh.seg_rows, (T*)rec0, (T*)rec1);
+  hipLaunchKernelGGL((k_step2_fused<P, BIG, REC, TRT>), dim3(sh.nstrips * sh.nseg),
+                     dim3(sh.threads), 0, s, i, o, c, g, sh.width, sh.nstrips, sh.seg_rows,
+                     (T*)rec0, (T*)rec1);
 }
 
 template <int P>
 hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename PrecT<P>::T>& c,
                               const Geom& g, const FusedShape& sh, void* rec0, void* rec1,
-                              hipStream_t s) {
+                              hipStream_t s, bool trt) {
   Pop<P> i{(char*)pin, g.Ns}, o{(char*)pout, g.Ns};
   const bool big = fused_big<P>(g);
-  if (rec0 && rec1) {
+  if (trt) {
+    if (rec0 || rec1) return hipErrorInvalidValue;   // no recording TRT variant
+    if (big) launch_fused2_variant<P, true, false, true>(i, o, c, g, sh, nullptr, nullptr, s);
+    else launch_fused2_variant<P, false, false, true>(i, o, c, g, sh, nullptr, nullptr, s);
+  } else if (rec0 && rec1) {
     if (big) launch_fused2_variant<P, true, true>(i, o, c, g, sh, rec0, rec1, s);
     else launch_fused2_variant<P, false, true>(i, o, c, g, sh, rec0, rec1, s);
   } else {
@@ -1669,7 +1675,7 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
   template int fused2_resident<P>();                                                             \
   template hipError_t launch_step2_fused<P>(const void*, void*, const Coef<PrecT<P>::T>&,        \
                                             const Geom&, const FusedShape&, void*, void*,        \
-                                            hipStream_t);                                        \
+                                            hipStream_t, bool);                                  \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
                                      const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
 
