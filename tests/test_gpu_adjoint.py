@@ -71,7 +71,7 @@ def test_end_to_end_gradients_match_oracle(bc):
     phi = simulate(p0, sig, mob, pb.as_dict(), K, checkpoint=4)
     Lg = ((phi - target.to(dev)) ** 2).sum()
     Lg.backward()
-    assert float(Lg) == pytest.approx(L, rel=1e-12)
+    assert float(Lg.detach()) == pytest.approx(L, rel=1e-12)
     assert float(sig.grad) == pytest.approx(ds, rel=1e-10)
     assert float(mob.grad) == pytest.approx(dm, rel=1e-10)
     assert _rel(p0.grad, dp) <= 1e-10
