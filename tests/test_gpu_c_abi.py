@@ -1,7 +1,8 @@
 """The C ABI from a plain C program (tests/c/abi_example.c, built by the
 package build next to the library): no Python or PyTorch in the process
-that drives the GPU. It runs a 64x64 droplet in FP64 and FP32 and checks
-mass conservation (FP64 to 1e-12, FP32 exactly)."""
+that drives the GPU. It runs a 64x64 droplet in FP64 and FP32 and a 32^3
+droplet through the three-dimensional header (FP64 periodic, FP32 with
+walls and gravity) and checks the phi total (FP64 to 1e-12, FP32 exactly)."""
 import os
 import subprocess
 
