@@ -340,18 +340,35 @@ __device__ __forceinline__ Lane lane_of(uint32_t x, const Geom3& g) {
   return L;
 }
 
+// Rows are taken in blocks of RB x RB (y, z) rows, y fastest inside a block,
+// so that the rows a stencil touches (y +- 1, z +- 1) are processed close
+// together in time and their field values are still in L2.
+constexpr uint32_t RB = 16;
+
+__host__ __device__ inline uint32_t row_blocks(int n) { return ((uint32_t)n + RB - 1) / RB; }
+
+// Waves over the padded block grid: 64-column chunks x (blocks of RB x RB rows).
+__host__ __device__ inline uint32_t row_tasks(const Geom3& g, uint32_t nxc) {
+  return nxc * row_blocks(g.ny) * row_blocks(g.nz) * RB * RB;
+}
+
 // Runs fn(row, lane) for every node, one (row, 64-column chunk) per wave;
-// blocks are placed XCD-contiguously over the tasks.
+// blocks are placed XCD-contiguously over the tasks. Waves on padding rows
+// of the last blocks skip.
 template <int WS, typename Fn>
 __device__ __forceinline__ void for_rows(const Geom3& g, uint32_t nxc, Fn&& fn) {
   const uint32_t lane = threadIdx.x & 63;
   const uint32_t nb = gridDim.x;
   const uint32_t b = (uint32_t)xcd_tile((int)blockIdx.x, (int)nb);
-  const uint32_t ntask = nxc * (uint32_t)g.ny * (uint32_t)g.nz;
+  const uint32_t ntask = row_tasks(g, nxc);
+  const uint32_t nyb = row_blocks(g.ny);
   for (uint32_t t = (uint32_t)__builtin_amdgcn_readfirstlane((int)(b * 4 + (threadIdx.x >> 6)));
        t < ntask; t += nb * 4) {
-    const uint32_t row = t / nxc, xc = t - row * nxc;
-    const uint32_t z = row / (uint32_t)g.ny, y = row - z * (uint32_t)g.ny;
+    const uint32_t r = t / nxc, xc = t - r * nxc;
+    const uint32_t blk = r / (RB * RB), w = r - blk * (RB * RB);
+    const uint32_t bz = blk / nyb, by = blk - bz * nyb;
+    const uint32_t y = by * RB + w % RB, z = bz * RB + w / RB;
+    if (y >= (uint32_t)g.ny || z >= (uint32_t)g.nz) continue;
     const uint32_t x = xc * 64 + lane;
     if (x < (uint32_t)g.nx) fn(row_ctx(y, z, g), lane_of<WS>(x, g));
   }
@@ -1144,7 +1161,7 @@ unsigned grid_of(int64_t N) {
 uint32_t chunks_x(const Geom3& g) { return (uint32_t)((g.nx + 63) / 64); }
 
 unsigned row_grid(const Geom3& g) {
-  const int64_t tasks = (int64_t)chunks_x(g) * g.ny * g.nz;
+  const int64_t tasks = (int64_t)row_tasks(g, chunks_x(g));
   const int64_t b = (tasks + 3) / 4;
   return (unsigned)(b < (1 << 24) ? b : (1 << 24));
 }
