@@ -77,6 +77,28 @@ def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
     return ms, phi, m0, m1, info
 
 
+def copy_gbps(reps: int = 10) -> float:
+    """Achievable HBM rate of a plain device copy (1 GiB read + 1 GiB
+    written per copy), HIP events around `reps` copies."""
+    import torch
+    src = torch.empty(1 << 28, dtype=torch.float32, device="cuda:0").fill_(1.0)
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    a = torch.cuda.Event(enable_timing=True)
+    b = torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    b.record()
+    torch.cuda.synchronize()
+    gbps = 2.0 * (1 << 30) * reps / (a.elapsed_time(b) * 1e-3) / 1e9
+    del src, dst
+    torch.cuda.empty_cache()
+    return gbps
+
+
 def run_trt(pb, phi0, steps: int, warmup: int, magic: float = 0.25):
     """FP32 step with the two-relaxation-time collision of f next to the BGK
     step on the same lattice, both two steps per launch of the fused kernel."""
@@ -436,6 +458,8 @@ def main():
         torch.cuda.synchronize()
         log("copy calibration: 3 x 1 GiB read + 1 GiB write")
 
+    achievable = copy_gbps()
+    log(f"device copy: {achievable:.0f} GB/s")
     precisions = [args.only] if args.only else ["fp32", "fp64", "fp16"]
     res = {}
     for prec in precisions:
@@ -491,6 +515,7 @@ def main():
                      "ms_per_launch": round(ms * per, 5),
                      "alg_bytes_per_launch": alg_bytes,
                      "traffic": None if traffic is None else round(traffic, 0),
+                     "achievable_copy_gbps": round(achievable, 1),
                      "moved_gbps": None if traffic is None
                      else round(traffic / (ms * per * 1e-3) / 1e9, 1)},
     }
