@@ -64,8 +64,9 @@ typedef enum {
 typedef enum {
   LBM_FP64 = 0,        /* populations stored and computed in binary64       */
   LBM_FP32 = 1,        /* f stored as binary32, g as Q2.29 fixed point
-                          (int32, so the lattice total of phi is an exact
-                          integer invariant); arithmetic in binary32        */
+                          (int32: values in [-4, 4) at resolution 2^-29, so
+                          the lattice total of phi is an exact integer
+                          invariant); arithmetic in binary32               */
   LBM_FP16_STORE = 2   /* f_0..8 and g_1..8 stored as binary16 scaled by a
                           power of two per direction, g_0 as Q2.29 int32;
                           arithmetic in binary32                            */

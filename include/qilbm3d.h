@@ -20,8 +20,9 @@
  *     11 (1,0,1) 12 (-1,0,-1) 13 (1,0,-1) 14 (-1,0,1)
  *     15 (0,1,1) 16 (0,-1,-1) 17 (0,1,-1) 18 (0,-1,1).
  *   Precision: LBM_FP64 (binary64 populations) or LBM_FP32 (f binary32, g
- *     Q2.29 fixed point, so the lattice total of phi is an exact integer
- *     invariant); LBM_FP16_STORE is not offered in 3-D.
+ *     Q2.29 fixed point: int32 values in [-4, 4) at resolution 2^-29, so the
+ *     lattice total of phi is an exact integer invariant); LBM_FP16_STORE is
+ *     not offered in 3-D.
  *   Kernels: the populations in a pull layout. FP32 runs one fused kernel
  *     per step (a workgroup sweeps a 64 x 16 column tile along z, phi, mu and
  *     p in LDS plane rings); FP64, and FP32 with LBM_FLAG_UNFUSED, run four
