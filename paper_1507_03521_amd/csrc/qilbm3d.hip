@@ -604,6 +604,23 @@ __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
   });
 }
 
+// Q2.29 sum of the pulled g words of every node (the order parameter the
+// fused FP32 step reads in its stage A).
+template <bool BIG>
+__global__ __launch_bounds__(256) void k3_phiq(Pop3<P_F32> in, int32_t* __restrict__ phiq, Geom3 g,
+                                               uint32_t nxc) {
+  const PopView<P_F32, BIG> v(in);
+  for_rows<4>(g, nxc, [&](const RowCtx& R, const Lane& L) {
+    int32_t q = 0;
+#pragma unroll
+    for (int i = 0; i < 19; ++i) {
+      const Src s = pull_at(i, R, L);
+      q += v.g.ld(s.plane, s.row, s.vo);
+    }
+    phiq[R.rb[1][1] + L.x] = q;
+  });
+}
+
 // ------------------------------------------------------ fused z-sweep step
 // One kernel per time step. A workgroup owns a TX x TY tile of (x, y) and a
 // segment [z0, z1) of planes and sweeps it in z. In the iteration that
@@ -656,6 +673,13 @@ struct FzLds {
   T phi[fz::RPHI][fz::Reg<3>::A];
   T mu[fz::RMU][fz::Reg<2>::A];
   T p[fz::RP][fz::Reg<1>::A];
+};
+
+// With the scattered order parameter: three planes of Q2.29 partial sums of
+// the next step's phi over the core tile.
+template <int P>
+struct FzLdsQ : FzLds<P> {
+  int32_t acc[3][fz::TX * fz::TY];
 };
 
 struct Fz3Shape {
@@ -712,6 +736,11 @@ struct SrcB {
   uint32_t sb, vb;
 };
 
+// a[k] for k in 0..2 as selects (no private array when k is not a constant)
+__device__ __forceinline__ uint32_t pick3(const uint32_t a[3], int k) {
+  return k == 0 ? a[0] : (k == 1 ? a[1] : a[2]);
+}
+
 // Slot of the pre-collision population i of a node (pull; bounce-back
 // from the node's own opposite slot beyond a wall).
 __device__ __forceinline__ SrcB pull_b(int i, const ZP& Z, const XY& q) {
@@ -719,8 +748,8 @@ __device__ __forceinline__ SrcB pull_b(int i, const ZP& Z, const XY& q) {
   const bool beyond = (cz == 1 && Z.below) || (cz == -1 && Z.above);
   SrcB s;
   s.plane = beyond ? OPP(i) : i;
-  s.sb = beyond ? Z.zo[1] : Z.zo[1 - cz];
-  s.vb = beyond ? q.yo[1] + q.xo[1] : q.yo[1 - CY(i)] + q.xo[1 - CX(i)];
+  s.sb = beyond ? Z.zo[1] : pick3(Z.zo, 1 - cz);
+  s.vb = beyond ? q.yo[1] + q.xo[1] : pick3(q.yo, 1 - CY(i)) + pick3(q.xo, 1 - CX(i));
   return s;
 }
 
@@ -747,10 +776,20 @@ __device__ __forceinline__ void lds_stencil(const T* pm, const T* p0, const T* p
   lp *= T(6);
 }
 
-template <int P, bool BIG>
+// PHIQ (FP32 only): stage A reads phi as the Q2.29 sum phiq_in of the
+// pulled g words (formed by the previous step), and stage D scatters each
+// post-collision g word to the node it streams to, accumulating the next
+// step's sum into phiq_out (zero on entry): integer sums, so the order of
+// the additions does not matter and the result equals the pulled sum
+// exactly. Targets inside the core tile accumulate in LDS (three planes,
+// flushed with one atomic add per node once a plane has all its sources);
+// targets outside go to phiq_out by atomic add.
+template <int P, bool BIG, bool PHIQ = false>
 __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3<P> out,
                                                                 Coef3<typename PrecT<P>::T> k,
-                                                                Geom3 g, Fz3Shape sh) {
+                                                                Geom3 g, Fz3Shape sh,
+                                                                const int32_t* __restrict__ phiq_in,
+                                                                int32_t* __restrict__ phiq_out) {
   using T = typename PrecT<P>::T;
   using namespace fz;
   constexpr int NT = FzThreads<P>::value;
@@ -758,7 +797,8 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
   using RA = Reg<3>;
   using RB = Reg<2>;
   using RC = Reg<1>;
-  __shared__ FzLds<P> L;
+  static_assert(!PHIQ || FixedG<P>::value, "scattered phi needs integer g words");
+  __shared__ typename std::conditional<PHIQ, FzLdsQ<P>, FzLds<P>>::type L;
 
   const int ntiles = sh.ntx * sh.nty;
   const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
@@ -779,6 +819,27 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
     return (zz - vbase) % R;
   };
   auto real = [&](int zz) { return wl ? (zz >= 0 && zz < nz) : true; };
+  const uint32_t planeN = (uint32_t)g.nx * (uint32_t)g.ny;
+  // adds the LDS partial sums of virtual plane zf to phiq_out and clears them
+  auto flush = [&](int zf) {
+    if constexpr (PHIQ) {
+      int32_t* acc = L.acc[(zf - vbase) % 3];
+      const bool ok = real(zf);
+      const uint32_t zb = ok ? (uint32_t)wrapm(zf, nz) * planeN : 0u;
+      for (int r = tid; r < TX * TY; r += NT) {
+        const int ly = r / TX, lx = r - ly * TX;
+        const int X = x0 + lx, Y = y0 + ly;
+        const int32_t v = acc[r];
+        acc[r] = 0;
+        if (ok && X < g.nx && Y < g.ny && v != 0)
+          atomicAdd(&phiq_out[zb + (uint32_t)Y * (uint32_t)g.nx + (uint32_t)X], v);
+      }
+    }
+  };
+  if constexpr (PHIQ) {
+    for (int r = tid; r < 3 * TX * TY; r += NT) (&L.acc[0][0])[r] = 0;
+    __syncthreads();
+  }
 
   const int niter = (z1 - z0) + 6;
   for (int it = 0; it < niter; ++it) {
@@ -792,6 +853,13 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
         const int r = tid + rr * NT;
         if (r >= RA::A) break;
         const int ly = r / RA::W, lx = r - ly * RA::W;
+        if constexpr (PHIQ) {
+          const uint32_t e = (uint32_t)wrapm(a, nz) * planeN +
+                             (uint32_t)wrapm(y0 - 3 + ly, g.ny) * (uint32_t)g.nx +
+                             (uint32_t)wrapm(x0 - 3 + lx, g.nx);
+          dst[r] = T(phiq_in[e]) * T(GQI);
+          continue;
+        }
         const XY q = xy_of<WS>(wrapm(x0 - 3 + lx, g.nx), wrapm(y0 - 3 + ly, g.ny), g);
         if constexpr (FixedG<P>::value) {
           int32_t s = 0;
@@ -935,8 +1003,26 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
             const int32_t word = __float2int_rn(gg[i] * GQ);
             rest += word;
             w.g.stb(i, sb, vb, word);
+            if constexpr (PHIQ) {
+              // the word streams to (X, Y, zd) + c_i, or back to this node
+              // (as the opposite population) beyond a wall
+              const int zt = zd + CZ(i);
+              if (wl && (zt < 0 || zt >= nz)) {
+                atomicAdd(&L.acc[(zd - vbase) % 3][r], word);
+              } else {
+                const int tX = wrapm(X + CX(i), g.nx), tY = wrapm(Y + CY(i), g.ny);
+                const int tlx = tX - x0, tly = tY - y0;
+                if (tlx >= 0 && tlx < TX && tly >= 0 && tly < TY)
+                  atomicAdd(&L.acc[(zt - vbase) % 3][tly * TX + tlx], word);
+                else
+                  atomicAdd(&phiq_out[(uint32_t)wrapm(zt, nz) * planeN +
+                                      (uint32_t)tY * (uint32_t)g.nx + (uint32_t)tX],
+                            word);
+              }
+            }
           }
           w.g.stb(0, sb, vb, qs - rest);
+          if constexpr (PHIQ) atomicAdd(&L.acc[(zd - vbase) % 3][r], qs - rest);
         } else {
 #pragma unroll
           for (int i = 0; i < 19; ++i) w.g.stb(i, sb, vb, gg[i]);
@@ -944,6 +1030,14 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
       }
     }
     __syncthreads();
+    if constexpr (PHIQ) {
+      // plane zd - 1 now has the words of all its sources in this tile
+      if (zd >= z0 && zd < z1) flush(zd - 1);
+    }
+  }
+  if constexpr (PHIQ) {
+    flush(z1 - 1);
+    flush(z1);
   }
 }
 
@@ -1075,6 +1169,9 @@ struct lbm3_ctx {
   double* red_out;
   int64_t t;
   int resident;      // workgroups of the fused kernel resident at once (0: not yet known)
+  int32_t* phiq[2];  // Q2.29 phi of the current state (FP32 fused step), double-buffered
+  int qcur;          // phiq[qcur] belongs to pop[cur] when phiq_ok
+  bool phiq_ok;
 };
 
 namespace {
@@ -1112,7 +1209,7 @@ Geom3 geom_of(const lbm3_params* p) {
 }
 
 struct Layout3 {
-  size_t pop0, pop1, fields, part, red, total;
+  size_t pop0, pop1, fields, part, red, phiq, total;
   int nred;
 };
 
@@ -1127,7 +1224,8 @@ Layout3 layout3(const lbm3_params* p) {
   L.fields = 2 * pb;
   L.part = L.fields + up(3 * (size_t)g.Ns * 8);
   L.red = L.part + up((size_t)L.nred * 5 * 8);
-  L.total = L.red + up(8 * 8);
+  L.phiq = L.red + up(8 * 8);
+  L.total = L.phiq + 2 * up((size_t)g.Ns * 4);
   return L;
 }
 
@@ -1219,7 +1317,7 @@ int fused_resident3() {
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_fused<P, false>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_fused<P, false, true>,
                                                    FzThreads<P>::value, 0) != hipSuccess)
     return 0;
   return cus * (per_cu > 0 ? per_cu : 1);
@@ -1248,16 +1346,31 @@ lbm_status step_fused_p(lbm3_ctx* c, int64_t n) {
   const unsigned nblk = (unsigned)(sh.ntx * sh.nty * sh.nseg);
   const Coef3<T> k = coef3<T>(c);
   const bool big = big3<P>(g);
+  if (n > 0 && !c->phiq_ok) {
+    Pop3<P_F32> in{c->pop[c->cur], g.Ns};
+    if (big)
+      hipLaunchKernelGGL(k3_phiq<true>, dim3(row_grid(g)), dim3(256), 0, c->stream, in,
+                         c->phiq[c->qcur], g, chunks_x(g));
+    else
+      hipLaunchKernelGGL(k3_phiq<false>, dim3(row_grid(g)), dim3(256), 0, c->stream, in,
+                         c->phiq[c->qcur], g, chunks_x(g));
+    if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
+    c->phiq_ok = true;
+  }
   for (int64_t s = 0; s < n; ++s) {
     Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
+    int32_t* qin = c->phiq[c->qcur];
+    int32_t* qout = c->phiq[c->qcur ^ 1];
+    if (qilbm::launch_zero(qout, (size_t)g.Ns * 4, c->stream) != hipSuccess) return LBM_EDEVICE;
     if (big)
-      hipLaunchKernelGGL((k3_fused<P, true>), dim3(nblk), dim3(FzThreads<P>::value), 0, c->stream,
-                         in, out, k, g, sh);
+      hipLaunchKernelGGL((k3_fused<P, true, true>), dim3(nblk), dim3(FzThreads<P>::value), 0,
+                         c->stream, in, out, k, g, sh, (const int32_t*)qin, qout);
     else
-      hipLaunchKernelGGL((k3_fused<P, false>), dim3(nblk), dim3(FzThreads<P>::value), 0,
-                         c->stream, in, out, k, g, sh);
+      hipLaunchKernelGGL((k3_fused<P, false, true>), dim3(nblk), dim3(FzThreads<P>::value), 0,
+                         c->stream, in, out, k, g, sh, (const int32_t*)qin, qout);
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     c->cur ^= 1;
+    c->qcur ^= 1;
     c->t += 1;
   }
   return LBM_OK;
@@ -1269,6 +1382,7 @@ lbm_status step_p(lbm3_ctx* c, int64_t n) {
   const Geom3& g = c->geom;
   if constexpr (P == P_F32)
     if (!(c->prm.flags & LBM_FLAG_UNFUSED)) return step_fused_p<P>(c, n);
+  c->phiq_ok = false;
   T* p = (T*)(c->fields + 2 * g.Ns * 8);
   const bool big = big3<P>(g);
   for (int64_t s = 0; s < n; ++s) {
@@ -1360,6 +1474,10 @@ lbm_status lbm3_init(lbm3_ctx** out, const lbm3_params* params, void* ws, size_t
   c->red_out = (double*)(base + L.red);
   c->t = 0;
   c->resident = 0;
+  c->phiq[0] = (int32_t*)(base + L.phiq);
+  c->phiq[1] = (int32_t*)(base + L.phiq + up((size_t)c->geom.Ns * 4));
+  c->qcur = 0;
+  c->phiq_ok = false;
   hipError_t e = qilbm::launch_zero(base, L.fields, c->stream);
   if (e == hipSuccess) {
     const Coef3<double> k = coef3<double>(c);
@@ -1428,6 +1546,7 @@ lbm_status lbm3_get_state(lbm3_ctx* c, double* f, double* g) {
 lbm_status lbm3_set_state(lbm3_ctx* c, const double* f, const double* g) {
   if (!c || !f || !g) return LBM_EINVAL;
   const Geom3& gm = c->geom;
+  c->phiq_ok = false;
   if (c->prm.precision == LBM_FP64)
     hipLaunchKernelGGL(k3_from_canonical<P_F64>, dim3(grid_of(gm.N)), dim3(256), 0, c->stream,
                        f, g, Pop3<P_F64>{c->pop[c->cur], gm.Ns}, gm);
