@@ -637,11 +637,12 @@ __global__ __launch_bounds__(256) void k3_phiq(Pop3<P_F32> in, int32_t* __restri
 // once. Halo nodes and the 3 planes of warm-up at each segment end are
 // recomputed by the neighbouring workgroups. Results equal those of the
 // four-kernel path up to the rounding order of contracted multiply-adds.
-// Used for FP32 only: the halo and warm-up re-reads and the second pull of
-// each population are not caught by L2 (measured 453 B read per node
-// against 365 for the four kernels together), so the kernel gains
-// little over the four-kernel path in FP32, and in FP64 (one 512-lane
-// workgroup per CU, barrier-bound) it was a quarter slower.
+// Used for FP32 only, with stage A reading phi from the Q2.29 words that the
+// previous step scattered (PHIQ below): pulling g there over the halo made
+// the kernel read 453 B per node (those re-reads miss L2), against 252 with
+// the scattered phi. In FP64 (no integer g; LDS rings for one 512-lane
+// workgroup per CU, barrier-bound) the fused form was a quarter slower than
+// the four kernels.
 namespace fz {
 constexpr int TX = 64, TY = 16;
 template <int H>
