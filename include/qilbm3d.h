@@ -62,7 +62,8 @@ typedef struct {
 typedef struct lbm3_ctx lbm3_ctx;
 
 /* Device workspace bytes for these parameters (0 when invalid): two
- * population buffers, the phi/mu/p fields and reduction partials. */
+ * population buffers, the phi/mu/p fields, reduction partials and two int32
+ * buffers of the Q2.29 phi sums of the fused FP32 step. */
 size_t lbm3_workspace_bytes(const lbm3_params* params);
 
 /* Context at t = 0 from phi0_dev (FP64 [nz][ny][nx], device): f = 0 and
