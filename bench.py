@@ -132,7 +132,7 @@ def run_3d(steps: int, warmup: int):
     N = pb.nx * pb.ny * pb.nz
     out = {"workload": "rt3d: Rayleigh-Taylor 256x256x256, walls in z, Atwood 0.5, "
                        "Re 3000, Pe 1000, W 4"}
-    kernels = {"fp32": "k3_fused (one z-sweep kernel per step)",
+    kernels = {"fp32": "k_zero_words (next step's phi words) + k3_fused (one z-sweep kernel)",
                "fp64": "k3_phi, k3_mu, k3_macro, k3_collide"}
     for prec in ("fp32", "fp64"):
         lat = Lattice3D(pb.as_dict(), phi0, precision=prec, device="cuda:0")
