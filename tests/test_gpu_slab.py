@@ -9,9 +9,12 @@ lattice of its own (periodic in y; the wrap only touches ghost rows), one
 two-step pass runs on both, and the band's rows must equal the full
 lattice's: bit for bit in FP64; in FP32 to the rounding-order bounds of the
 other full-size FP32 comparisons (f 2e-3 relative to its maximum, which is
-small near rest, g 1e-6), because the band and the full lattice get
-different segment layouts, and a row's FP32 stencil sums are rounded in the
-order of its segment's sweep (measured: g 1.2e-7, one binary32 unit of phi).
+small near rest, g 1e-6): the band and the full lattice get different
+segment layouts, and in FP32 a row's result depends at the rounding level
+on where it lies in its segment (measured: g 1.2e-7, one binary32 unit;
+FP64 shows no such dependence here). A likely cause, not verified: the
+kernel's unrolled iteration instances are compiled separately and may
+contract multiply-adds differently.
 """
 import pytest
 import torch
