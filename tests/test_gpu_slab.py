@@ -12,9 +12,9 @@ other full-size FP32 comparisons (f 2e-3 relative to its maximum, which is
 small near rest, g 1e-6): the band and the full lattice get different
 segment layouts, and in FP32 a row's result depends at the rounding level
 on where it lies in its segment (measured: g 1.2e-7, one binary32 unit;
-FP64 shows no such dependence here; one step per pass behaves alike). A
-likely cause, not verified: the fused kernels' unrolled iteration instances
-are compiled separately and may contract multiply-adds differently.
+FP64 shows no such dependence here; one step per pass behaves alike; the
+cause is not identified, and it is not multiply-add contraction: a build
+without contraction differs the same way).
 """
 import pytest
 import torch
