@@ -9,12 +9,12 @@ lattice of its own (periodic in y; the wrap only touches ghost rows), one
 two-step pass runs on both, and the band's rows must equal the full
 lattice's: bit for bit in FP64; in FP32 to the rounding-order bounds of the
 other full-size FP32 comparisons (f 2e-3 relative to its maximum, which is
-small near rest, g 1e-6): the band and the full lattice get different
-segment layouts, and in FP32 a row's result depends at the rounding level
-on where it lies in its segment (measured: g 1.2e-7, one binary32 unit;
-FP64 shows no such dependence here; one step per pass behaves alike; the
-cause is not identified, and it is not multiply-add contraction: a build
-without contraction differs the same way).
+small near rest, g 1e-6). In FP32 the band's rows differ from the full
+lattice's at the rounding level (measured: g 1.2e-7, one binary32 unit),
+with one and with two steps per pass; the two lattices differ in height,
+y boundary and segment layout, and which of these matters is not
+identified (not multiply-add contraction: a build without it differs the
+same way). FP64 matches bit for bit.
 """
 import pytest
 import torch
