@@ -162,11 +162,15 @@ lbm_status lbm_moments(lbm_ctx* ctx, double* phi_dev, double* rho_dev,
 lbm_status lbm_mass(lbm_ctx* ctx, double out[4]);
 
 /* Current pre-collision populations in canonical FP64 layout,
- * f_dev and g_dev each [9][ny][nx] (device). Asynchronous. */
+ * f_dev and g_dev each [9][ny][nx] (device), exactly as stored (binary32 f,
+ * Q2.29 g words, scaled binary16 halves converted without rounding), so
+ * lbm_set_state of the result restores the state bit for bit.
+ * Asynchronous. */
 lbm_status lbm_get_state(lbm_ctx* ctx, double* f_dev, double* g_dev);
 
 /* Replaces the current pre-collision populations (canonical FP64 layout);
- * values are rounded to the storage precision. Keeps the time counter. */
+ * each value is rounded once, to nearest, to its storage format (binary32,
+ * Q2.29 or scaled binary16). Keeps the time counter. */
 lbm_status lbm_set_state(lbm_ctx* ctx, const double* f_dev, const double* g_dev);
 
 /* Size in bytes of one step record (see lbm_step_record). */

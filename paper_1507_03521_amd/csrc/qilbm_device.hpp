@@ -85,6 +85,7 @@ template <int P> struct FixedG { static constexpr bool value = P != P_F64; };
 constexpr float GQ = 536870912.0f;            // 2^29
 constexpr float GQI = 1.0f / 536870912.0f;
 constexpr double GQI_D = 1.0 / 536870912.0;
+constexpr double GQ_D = 536870912.0;
 // Q2.29 contribution of a binary16 plane value: its value times 2^29, i.e.
 // the stored half times 2^29 / H_SCALE(i), a power of two.
 __host__ __device__ constexpr float HQ(int i) {
@@ -161,6 +162,14 @@ struct Pop {
       else return double(__half2float(half_ld(half_at(k, idx)))) * double(H_INV(k));
     }
   }
+  // value of plane k at idx in binary64 exactly as stored: binary16 halves
+  // scaled back (not their Q2.29 contribution), Q2.29 words, binary32 f
+  __device__ __forceinline__ double ld_canon(int k, uint32_t idx) const {
+    if constexpr (P == P_F16) {
+      if (k != 9) return double(__half2float(half_ld(half_at(k, idx)))) * double(H_INV(dir(k)));
+    }
+    return ld_exact(k, idx);
+  }
   // Q2.29 contribution of g plane k (9..17) at idx (fixed-point modes only)
   __device__ __forceinline__ int32_t ld_q(int k, uint32_t idx) const {
     if constexpr (P == P_F32) {
@@ -193,6 +202,24 @@ struct Pop {
       const __half h = __float2half_rn(v * H_SCALE(dir(k)));
       *reinterpret_cast<__half*>(half_at(k, idx)) = h;
       return k < 9 ? 0 : __float2int_rn(__half2float(h) * HQ(dir(k)));
+    }
+  }
+  // stores the binary64 value v into plane k with a single rounding to the
+  // storage format: binary32 f, Q2.29 g words, binary16 (scaled) halves;
+  // the inverse of ld_exact for values the format represents
+  __device__ __forceinline__ void st_exact(int k, uint32_t idx, double v) const {
+    if constexpr (P == P_F64) {
+      put<double>(base + k * Ns * 8, idx, v);
+    } else if constexpr (P == P_F32) {
+      if (k < 9) *reinterpret_cast<float*>(word_at(k, idx)) = float(v);
+      else *reinterpret_cast<int32_t*>(word_at(k, idx)) = __double2int_rn(v * GQ_D);
+    } else {
+      if (k == 9) {
+        put<int32_t>(base + 2 * Ns, idx, __double2int_rn(v * GQ_D));
+        return;
+      }
+      const _Float16 h = (_Float16)(v * double(H_SCALE(dir(k))));
+      *reinterpret_cast<_Float16*>(half_at(k, idx)) = h;
     }
   }
   // stores the Q2.29 word q into g_0 (fixed-point modes)

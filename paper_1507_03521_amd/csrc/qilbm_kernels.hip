@@ -98,11 +98,11 @@ __global__ __launch_bounds__(256) void k_from_canonical(const double* __restrict
   const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
   int plane;
   uint32_t idx;
-  using T = typename PrecT<P>::T;
+  // one rounding from binary64 to the storage format (Q2.29 g words exactly)
 #define QILBM_SCATTER(I)                                                   \
   pull_src<I>(x, y, g, plane, idx);                                        \
-  out.st(plane, idx, T(f[(int64_t)(I) * g.N + n]));                        \
-  out.st(9 + plane, idx, T(gg[(int64_t)(I) * g.N + n]));
+  out.st_exact(plane, idx, f[(int64_t)(I) * g.N + n]);                     \
+  out.st_exact(9 + plane, idx, gg[(int64_t)(I) * g.N + n]);
   QILBM_SCATTER(0) QILBM_SCATTER(1) QILBM_SCATTER(2) QILBM_SCATTER(3) QILBM_SCATTER(4)
   QILBM_SCATTER(5) QILBM_SCATTER(6) QILBM_SCATTER(7) QILBM_SCATTER(8)
 #undef QILBM_SCATTER
@@ -115,15 +115,16 @@ __global__ __launch_bounds__(256) void k_to_canonical(Pop<P> in, double* __restr
   const int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (n >= g.N) return;
   const int y = (int)(n / g.nx), x = (int)(n - (int64_t)y * g.nx);
-  using T = typename PrecT<P>::T;
-  T a[9], b[9];
-  pull9<P, 0>(in, x, y, g, a);
-  pull9<P, 9>(in, x, y, g, b);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    f[(int64_t)i * g.N + n] = double(a[i]);
-    gg[(int64_t)i * g.N + n] = double(b[i]);
-  }
+  int plane;
+  uint32_t idx;
+  // the stored values exactly (Q2.29 g words included)
+#define QILBM_GATHER(I)                                                    \
+  pull_src<I>(x, y, g, plane, idx);                                        \
+  f[(int64_t)(I) * g.N + n] = in.ld_canon(plane, idx);                     \
+  gg[(int64_t)(I) * g.N + n] = in.ld_canon(9 + plane, idx);
+  QILBM_GATHER(0) QILBM_GATHER(1) QILBM_GATHER(2) QILBM_GATHER(3) QILBM_GATHER(4)
+  QILBM_GATHER(5) QILBM_GATHER(6) QILBM_GATHER(7) QILBM_GATHER(8)
+#undef QILBM_GATHER
 }
 
 // ------------------------------------------------- unfused step (4 kernels)

@@ -234,6 +234,39 @@ def test_set_get_state_roundtrip():
     assert torch.equal(fg.cpu(), torch.tensor(f)) and torch.equal(gg.cpu(), torch.tensor(g))
 
 
+def test_set_get_state_roundtrip_fp32():
+    """FP32 storage: set_state rounds f once to binary32 and g once to Q2.29
+    (not through binary32, which would drop the low bits of g near 1), and
+    get_state returns exactly what is stored."""
+    pb = _problem(33, 21, wl.WALLS_Y)
+    f, g = wl.random_state(33, 21, seed=4)
+    lat = _lattice(pb, np.full((21, 33), 0.5), precision="fp32")
+    lat.set_state(f, g)
+    fg, gg = lat.get_state()
+    assert torch.equal(fg.cpu(), torch.tensor(f).float().double())
+    assert torch.equal(gg.cpu(), torch.round(torch.tensor(g) * 2.0 ** 29) / 2.0 ** 29)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+def test_get_then_set_state_restores_the_raw_state(precision):
+    """set_state(get_state()) leaves the stored state bit for bit as it was,
+    after a run (values the format represents, including g words near 1
+    whose Q2.29 low bits binary32 cannot hold), and stepping both gives
+    equal results."""
+    pb = wl.droplet64().with_(nx=100, ny=70, bc=wl.WALLS_Y, gy=-1e-5, rho_ref=0.5,
+                              meta=dict(R=15.0, xc=50.0, yc=35.0))
+    a = _lattice(pb, wl.phi0(pb), precision=precision)
+    a.step(40)
+    b = _lattice(pb, wl.phi0(pb), precision=precision)
+    b.set_state(*a.get_state())
+    torch.cuda.synchronize()
+    assert torch.equal(a.save_raw(), b.save_raw())
+    a.step(4)
+    b.step(4)
+    torch.cuda.synchronize()
+    assert torch.equal(a.save_raw(), b.save_raw())
+
+
 def test_nan_input_reports_divergence():
     from paper_1507_03521_amd import QilbmError
     pb = wl.droplet64()
