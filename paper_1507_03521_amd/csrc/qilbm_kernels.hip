@@ -79,10 +79,11 @@ __global__ __launch_bounds__(256) void k_init(const double* __restrict__ phi0, P
   for (int i = 1; i < 9; ++i) h[i] = WGT(i) * amu;
   int plane;
   uint32_t idx;
+  // H_i rounded once to the storage format (Q2.29 words exactly)
 #define QILBM_SCATTER(I)                                                   \
   pull_src<I>(x, y, g, plane, idx);                                        \
-  out.st(plane, idx, typename PrecT<P>::T(0));                             \
-  out.st(9 + plane, idx, typename PrecT<P>::T(h[I]));
+  out.st_exact(plane, idx, 0.0);                                           \
+  out.st_exact(9 + plane, idx, h[I]);
   QILBM_SCATTER(0) QILBM_SCATTER(1) QILBM_SCATTER(2) QILBM_SCATTER(3) QILBM_SCATTER(4)
   QILBM_SCATTER(5) QILBM_SCATTER(6) QILBM_SCATTER(7) QILBM_SCATTER(8)
 #undef QILBM_SCATTER
