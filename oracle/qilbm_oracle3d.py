@@ -69,10 +69,11 @@ class Coefficients:
     gz: float
     rho_ref: float
     bc: int
+    trt_magic: float = 0.0          # 0: BGK for f; > 0: TRT with this magic parameter
 
 
 def coefficients(rho_A, rho_B, sigma, W, M, tau_f, tau_g, gx=0.0, gy=0.0, gz=0.0,
-                 rho_ref=None, bc=PERIODIC, no_gamma=False) -> Coefficients:
+                 rho_ref=None, bc=PERIODIC, no_gamma=False, trt_magic=0.0) -> Coefficients:
     """beta = 12 sigma / W and kappa = 3 sigma W / 2 (the interface-width and
     surface-tension relations of Sec. II), lambda = M, alpha = lambda /
     (c_s^2 (tau_g - 1/2)) (Sec. III), gamma = rho_A / rho_B - 1."""
@@ -82,7 +83,7 @@ def coefficients(rho_A, rho_B, sigma, W, M, tau_f, tau_g, gx=0.0, gy=0.0, gz=0.0
         gamma=0.0 if no_gamma else rho_A / rho_B - 1.0,
         rho_A=rho_A, rho_B=rho_B, drho_dphi=(rho_A - rho_B) / (PHI_A - PHI_B),
         tau_f=tau_f, tau_g=tau_g, gx=gx, gy=gy, gz=gz,
-        rho_ref=rho_A if rho_ref is None else rho_ref, bc=bc)
+        rho_ref=rho_A if rho_ref is None else rho_ref, bc=bc, trt_magic=float(trt_magic))
 
 
 # ------------------------------------------------------------- stencils
@@ -219,17 +220,34 @@ def macroscopic(f, g, co):
 
 def collide(f, g, m, co):
     """BGK collisions with forcing: x_i* = x_i - (x_i - x_i^eq)/tau
-    + (1 - 1/(2 tau)) X_i for both LBEs."""
+    + (1 - 1/(2 tau)) X_i for both LBEs. With ``co.trt_magic`` > 0, f
+    collides with two relaxation times instead: f, f^eq and F_i split into
+    parts even and odd under c_i -> -c_i, the even part relaxed with tau_f,
+    the odd part with tau_- = 1/2 + magic / (tau_f - 1/2), each source part
+    with its own 1 - 1/(2 tau) (a variant beyond the paper, which uses
+    BGK)."""
     kf = 1.0 - 0.5 / co.tau_f
     kg = 1.0 - 0.5 / co.tau_g
-    fs, gs = [], []
+    fs, gs, feqs, Fs = [], [], [], []
     for i in range(Q):
         feq = f_equilibrium(i, m["p"], m["rho"], m["u"])
         Fi = f_source(i, m["u"], m["F"], m["dr"], m["rho"], m["D"], co)
         geq = g_equilibrium(i, m["phi"], m["mu"], m["u"], co)
         Gi = g_source(i, m["phi"], m["rho"], m["u"], m["dp"], m["F"])
+        feqs.append(feq)
+        Fs.append(Fi)
         fs.append(f[i] - (f[i] - feq) / co.tau_f + kf * Fi)
         gs.append(g[i] - (g[i] - geq) / co.tau_g + kg * Gi)
+    if co.trt_magic > 0.0:
+        tm = 0.5 + co.trt_magic / (co.tau_f - 0.5)
+        fs = []
+        for i in range(Q):
+            o = OPPOSITE[i]
+            fp, fm = 0.5 * (f[i] + f[o]), 0.5 * (f[i] - f[o])
+            ep, em = 0.5 * (feqs[i] + feqs[o]), 0.5 * (feqs[i] - feqs[o])
+            sp, sm = 0.5 * (Fs[i] + Fs[o]), 0.5 * (Fs[i] - Fs[o])
+            fs.append(f[i] - (fp - ep) / co.tau_f - (fm - em) / tm
+                      + kf * sp + (1.0 - 0.5 / tm) * sm)
     return torch.stack(fs), torch.stack(gs)
 
 

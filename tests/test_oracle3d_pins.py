@@ -219,3 +219,40 @@ def test_laplace_law_3d():
     ratio = dP * pb.meta["R"] / (2.0 * pb.sigma)
     print("3-D Laplace: Delta P R / (2 sigma) =", ratio)
     assert ratio == pytest.approx(1.0, rel=0.08)
+
+
+# ------------------------------------------------------------ TRT variant
+
+def _trt_state():
+    pb = wl.droplet3d().with_(nx=10, ny=8, nz=6, bc=O.WALLS_Z, gz=-2e-5, rho_ref=0.55,
+                              tau_f=0.9)
+    f, g = wl.random_state3d(10, 8, 6, seed=3)
+    return pb, torch.as_tensor(f), torch.as_tensor(g)
+
+
+def test_trt_3d_bgk_limit():
+    """tau_- = tau_f (magic parameter (tau_f - 1/2)^2) is the BGK step."""
+    pb, f, g = _trt_state()
+    bgk = O.step(f, g, _co(pb))
+    trt = O.step(f, g, _co(pb, trt_magic=(pb.tau_f - 0.5) ** 2))
+    assert float((trt[0] - bgk[0]).abs().max() / bgk[0].abs().max()) < 1e-14
+    assert torch.equal(trt[1], bgk[1])
+
+
+@pytest.mark.parametrize("magic", [3.0 / 16.0, 0.25, 1.0])
+def test_trt_3d_collision_keeps_mass_and_momentum_change(magic):
+    """Post-collision sum f_i and sum c_i f_i do not depend on tau_-:
+    sum c_i f* = sum c_i f + c_s^2 F for any magic parameter."""
+    pb, f, g = _trt_state()
+    m = O.macroscopic(f, g, _co(pb))
+    fb, _ = O.collide(f, g, m, _co(pb))
+    ft, _ = O.collide(f, g, m, _co(pb, trt_magic=magic))
+    scale = float(f.abs().sum(0).max())
+    assert float((ft.sum(0) - fb.sum(0)).abs().max()) < 1e-15 * 19 * scale + 1e-18
+    for a in range(3):
+        c = torch.tensor([O.C[i][a] for i in range(O.Q)], dtype=torch.float64)[:, None, None, None]
+        jt = (c * ft).sum(0)
+        j = (c * f).sum(0)
+        assert float((jt - (j + O.CS2 * m["F"][a])).abs().max()) < 1e-14 * 19 * scale + 1e-18
+        assert float((jt - (c * fb).sum(0)).abs().max()) < 1e-14 * 19 * scale + 1e-18
+    assert float((ft - fb).abs().max()) > 1e-8
