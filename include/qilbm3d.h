@@ -57,6 +57,10 @@ typedef struct {
   int32_t precision;      /* LBM_FP64 or LBM_FP32                              */
   uint32_t flags;         /* LBM_FLAG_NO_GAMMA, LBM_FLAG_UNFUSED (others are
                              rejected)                                        */
+  double trt_magic;       /* 0: the paper's BGK collision of f; > 0: the
+                             two-relaxation-time collision of f with this
+                             magic parameter, as lbm_params.trt_magic (the
+                             D3Q19 opposite pairs). Finite, >= 0.             */
 } lbm3_params;
 
 typedef struct lbm3_ctx lbm3_ctx;

@@ -31,7 +31,7 @@ class Lbm3Params(ctypes.Structure):
                 ("rho_B", c_double), ("sigma", c_double), ("W", c_double), ("M", c_double),
                 ("tau_f", c_double), ("tau_g", c_double), ("gx", c_double), ("gy", c_double),
                 ("gz", c_double), ("rho_ref", c_double), ("bc", c_int32),
-                ("precision", c_int32), ("flags", c_uint32)]
+                ("precision", c_int32), ("flags", c_uint32), ("trt_magic", c_double)]
 
 
 LBM3_BC_WALLS_Z = 1
@@ -141,7 +141,7 @@ def make_params(p: dict, precision="fp64", flags: int = 0) -> LbmParams:
 def make_params3(p: dict, precision="fp64", flags: int = 0) -> Lbm3Params:
     """lbm3_params from a mapping with keys nx, ny, nz, rho_A, rho_B, sigma,
     W, M, tau_f, tau_g and optionally gx, gy, gz, rho_ref (default rho_A),
-    bc (0 periodic, 1 walls normal to z)."""
+    bc (0 periodic, 1 walls normal to z), trt_magic (0: BGK)."""
     prec = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
     rho_ref = p.get("rho_ref")
     return Lbm3Params(int(p["nx"]), int(p["ny"]), int(p["nz"]), float(p["rho_A"]),
@@ -149,4 +149,4 @@ def make_params3(p: dict, precision="fp64", flags: int = 0) -> Lbm3Params:
                       float(p["tau_f"]), float(p["tau_g"]), float(p.get("gx", 0.0)),
                       float(p.get("gy", 0.0)), float(p.get("gz", 0.0)),
                       float(p["rho_A"] if rho_ref is None else rho_ref), int(p.get("bc", 0)),
-                      prec, int(flags))
+                      prec, int(flags), float(p.get("trt_magic", 0.0)))

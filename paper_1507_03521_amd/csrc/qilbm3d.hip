@@ -259,6 +259,63 @@ __device__ __forceinline__ void collide3(T f[19], T gg[19], const Node3<T>& m, c
   }
 }
 
+// Two-relaxation-time variant of the f collision (g keeps BGK): f, f^eq and
+// F_i split into parts even and odd under c_i -> -c_i (the D3Q19 opposite
+// pairs); the even part relaxes with tau_f, the odd part with tau_-, each
+// source part with its own 1 - 1/(2 tau) (Ginzburg, Verhaeghe and
+// d'Humieres, 2008).
+template <typename T>
+__device__ __forceinline__ void collide3_trt(T f[19], T gg[19], const Node3<T>& m, const T dp[3],
+                                             const Coef<T>& c) {
+  const T usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
+  const T gpre = -T(3) * m.phi * recip(m.rho);
+  const T h[3] = {dp[0] - m.F[0], dp[1] - m.F[1], dp[2] - m.F[2]};
+  const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
+  const T amu = c.alpha * m.mu;
+  const T r3 = m.rho * T(1.0 / 3.0);
+  T feq[19], Fs[19];
+#pragma unroll
+  for (int i = 0; i < 19; ++i) {
+    const T w = T(W(i));
+    const T cv[3] = {T(CX(i)), T(CY(i)), T(CZ(i))};
+    const T cu = cv[0] * m.u[0] + cv[1] * m.u[1] + cv[2] * m.u[2];
+    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
+    const T gm = T(1) + s;
+    T fa = T(0), ga = T(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const T cmu = cv[a] - m.u[a];
+      fa += cmu * (gm * m.F[a] + s * m.dr[a] * T(1.0 / 3.0));
+      ga += cmu * h[a];
+    }
+    feq[i] = w * (m.p + r3 * s);
+    Fs[i] = w * (fa + src1);
+    const T H = (i == 0) ? m.phi - T(1.0 - 1.0 / 3.0) * amu : w * amu;
+    const T geq = H + w * m.phi * s;
+    const T Gi = gpre * w * gm * ga;
+    gg[i] = gg[i] - (gg[i] - geq) * c.inv_tau_g + c.kg * Gi;
+  }
+  f[0] = f[0] - (f[0] - feq[0]) * c.inv_tau_f + c.kf * Fs[0];
+#pragma unroll
+  for (int i = 1; i < 19; i += 2) {           // (i, i + 1) are opposite
+    const int o = i + 1;
+    const T fp = T(0.5) * (f[i] + f[o]), fm = T(0.5) * (f[i] - f[o]);
+    const T ep = T(0.5) * (feq[i] + feq[o]), em = T(0.5) * (feq[i] - feq[o]);
+    const T sp = T(0.5) * (Fs[i] + Fs[o]), sm = T(0.5) * (Fs[i] - Fs[o]);
+    const T dpl = c.kf * sp - (fp - ep) * c.inv_tau_f;
+    const T dmi = c.km * sm - (fm - em) * c.inv_tau_m;
+    f[i] = f[i] + dpl + dmi;
+    f[o] = f[o] + dpl - dmi;
+  }
+}
+
+__host__ __device__ constexpr bool opposite_pairs_adjacent() {
+  for (int i = 1; i < 19; i += 2)
+    if (CX(i + 1) != -CX(i) || CY(i + 1) != -CY(i) || CZ(i + 1) != -CZ(i)) return false;
+  return true;
+}
+static_assert(opposite_pairs_adjacent(), "the pair loop assumes (i, i + 1) opposite");
+
 // ------------------------------------------------------------------ kernels
 #define QILBM3_FOR_NODES(n, g)                                                   \
   for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < (g).N;          \
@@ -555,7 +612,7 @@ __global__ __launch_bounds__(256) void k3_macro(Pop3<P> in, const typename PrecT
   });
 }
 
-template <int P, bool BIG>
+template <int P, bool BIG, bool TRT = false>
 __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
                                                   const typename PrecT<P>::T* __restrict__ phi,
                                                   const typename PrecT<P>::T* __restrict__ mu,
@@ -583,7 +640,8 @@ __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
     node_state_r<P, BIG>(v, ph, mf, R, L, k, f, m);
     T p0, dp[3], lapp;
     stencil_r<T>(pf, R, L, p0, dp[0], dp[1], dp[2], lapp);
-    collide3<T>(f, gg, m, dp, k.c);
+    if constexpr (TRT) collide3_trt<T>(f, gg, m, dp, k.c);
+    else collide3<T>(f, gg, m, dp, k.c);
     const uint32_t row = R.rb[1][1], vo = L.xo[1];
 #pragma unroll
     for (int i = 0; i < 19; ++i) w.f.st(i, row, vo, f[i]);
@@ -785,7 +843,7 @@ __device__ __forceinline__ void lds_stencil(const T* pm, const T* p0, const T* p
 // exactly. Targets inside the core tile accumulate in LDS (three planes,
 // flushed with one atomic add per node once a plane has all its sources);
 // targets outside go to phiq_out by atomic add.
-template <int P, bool BIG, bool PHIQ = false>
+template <int P, bool BIG, bool PHIQ = false, bool TRT = false>
 __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3<P> out,
                                                                 Coef3<typename PrecT<P>::T> k,
                                                                 Geom3 g, Fz3Shape sh,
@@ -992,7 +1050,8 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
         lds_stencil<T, RC::W>(qm, q0, qp, (ly + 1) * RC::W + lx + 1, p0, dp[0], dp[1], dp[2], lpp);
         Node3<T> m;
         macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
-        collide3<T>(f, gg, m, dp, k.c);
+        if constexpr (TRT) collide3_trt<T>(f, gg, m, dp, k.c);
+        else collide3<T>(f, gg, m, dp, k.c);
         const uint32_t sb = Z.zo[1], vb = q.yo[1] + q.xo[1];
 #pragma unroll
         for (int i = 0; i < 19; ++i) w.f.stb(i, sb, vb, f[i]);
@@ -1186,7 +1245,7 @@ bool valid3(const lbm3_params* p) {
   const int64_t N = (int64_t)p->nx * p->ny * p->nz;
   if (N > ((int64_t)1 << 29) - 4096) return false;
   const double v[] = {p->rho_A, p->rho_B, p->sigma, p->W, p->M, p->tau_f, p->tau_g,
-                      p->gx,    p->gy,    p->gz,    p->rho_ref};
+                      p->gx,    p->gy,    p->gz,    p->rho_ref, p->trt_magic};
   for (double d : v)
     if (!isfinite(d)) return false;
   if (!(p->rho_A > 0.0) || !(p->rho_B > 0.0)) return false;
@@ -1195,6 +1254,7 @@ bool valid3(const lbm3_params* p) {
   if (p->bc != LBM_BC_PERIODIC && p->bc != 1) return false;
   if (p->precision != LBM_FP64 && p->precision != LBM_FP32) return false;
   if (p->flags & ~(uint32_t)(LBM_FLAG_NO_GAMMA | LBM_FLAG_UNFUSED)) return false;
+  if (!(p->trt_magic >= 0.0)) return false;
   return true;
 }
 
@@ -1248,6 +1308,10 @@ Coef3<T> coef3(const lbm3_ctx* c) {
   k.c.inv_tau_g = T(1.0 / c->prm.tau_g);
   k.c.kf = T(1.0 - 0.5 / c->prm.tau_f);
   k.c.kg = T(1.0 - 0.5 / c->prm.tau_g);
+  const double tau_m =
+      c->prm.trt_magic > 0.0 ? 0.5 + c->prm.trt_magic / (c->prm.tau_f - 0.5) : c->prm.tau_f;
+  k.c.inv_tau_m = T(1.0 / tau_m);
+  k.c.km = T(1.0 - 0.5 / tau_m);
   return k;
 }
 
@@ -1307,9 +1371,15 @@ void launch_collide(lbm3_ctx* c) {
   using T = typename PrecT<P>::T;
   const Geom3& g = c->geom;
   Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
-  hipLaunchKernelGGL((k3_collide<P, BIG>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, out,
-                     (const T*)c->fields, (const T*)(c->fields + g.Ns * 8),
-                     (const T*)(c->fields + 2 * g.Ns * 8), coef3<T>(c), g, chunks_x(g));
+  const T* phi = (const T*)c->fields;
+  const T* mu = (const T*)(c->fields + g.Ns * 8);
+  const T* p = (const T*)(c->fields + 2 * g.Ns * 8);
+  if (c->prm.trt_magic > 0.0)
+    hipLaunchKernelGGL((k3_collide<P, BIG, true>), dim3(row_grid(g)), dim3(256), 0, c->stream,
+                       in, out, phi, mu, p, coef3<T>(c), g, chunks_x(g));
+  else
+    hipLaunchKernelGGL((k3_collide<P, BIG, false>), dim3(row_grid(g)), dim3(256), 0, c->stream,
+                       in, out, phi, mu, p, coef3<T>(c), g, chunks_x(g));
 }
 
 template <int P>
@@ -1347,6 +1417,7 @@ lbm_status step_fused_p(lbm3_ctx* c, int64_t n) {
   const unsigned nblk = (unsigned)(sh.ntx * sh.nty * sh.nseg);
   const Coef3<T> k = coef3<T>(c);
   const bool big = big3<P>(g);
+  const bool trt = c->prm.trt_magic > 0.0;
   if (n > 0 && !c->phiq_ok) {
     Pop3<P_F32> in{c->pop[c->cur], g.Ns};
     if (big)
@@ -1363,12 +1434,19 @@ lbm_status step_fused_p(lbm3_ctx* c, int64_t n) {
     int32_t* qin = c->phiq[c->qcur];
     int32_t* qout = c->phiq[c->qcur ^ 1];
     if (qilbm::launch_zero(qout, (size_t)g.Ns * 4, c->stream) != hipSuccess) return LBM_EDEVICE;
-    if (big)
-      hipLaunchKernelGGL((k3_fused<P, true, true>), dim3(nblk), dim3(FzThreads<P>::value), 0,
-                         c->stream, in, out, k, g, sh, (const int32_t*)qin, qout);
+    const dim3 grid(nblk), block(FzThreads<P>::value);
+    if (big && trt)
+      hipLaunchKernelGGL((k3_fused<P, true, true, true>), grid, block, 0, c->stream, in, out, k,
+                         g, sh, (const int32_t*)qin, qout);
+    else if (big)
+      hipLaunchKernelGGL((k3_fused<P, true, true, false>), grid, block, 0, c->stream, in, out, k,
+                         g, sh, (const int32_t*)qin, qout);
+    else if (trt)
+      hipLaunchKernelGGL((k3_fused<P, false, true, true>), grid, block, 0, c->stream, in, out, k,
+                         g, sh, (const int32_t*)qin, qout);
     else
-      hipLaunchKernelGGL((k3_fused<P, false, true>), dim3(nblk), dim3(FzThreads<P>::value), 0,
-                         c->stream, in, out, k, g, sh, (const int32_t*)qin, qout);
+      hipLaunchKernelGGL((k3_fused<P, false, true, false>), grid, block, 0, c->stream, in, out, k,
+                         g, sh, (const int32_t*)qin, qout);
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     c->cur ^= 1;
     c->qcur ^= 1;
