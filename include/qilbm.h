@@ -303,6 +303,16 @@ void lbm_destroy(lbm_ctx* ctx);
 /* Static description of a status code. */
 const char* lbm_strerror(lbm_status status);
 
+/* Version of this interface: the layouts of lbm_params and lbm3_params
+ * (read through the caller's pointer at the size the headers declare) and
+ * every signature in qilbm.h and qilbm3d.h. It changes whenever one of them
+ * does; a caller built against another value must not use the library (the
+ * structs would be read past their end). lbm_abi_version returns the value
+ * the library was built with. Host only: needs no GPU, enqueues nothing,
+ * may be called before any other function. */
+#define QILBM_ABI_VERSION 1
+int32_t lbm_abi_version(void);
+
 #ifdef __cplusplus
 }
 #endif

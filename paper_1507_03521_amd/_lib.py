@@ -8,6 +8,8 @@ from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_uint32, c_vo
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqilbm.so")
+# QILBM_ABI_VERSION of include/qilbm.h that SIGNATURES and the structs below follow
+ABI_VERSION = 1
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_STORE = 0, 1, 2
@@ -72,6 +74,7 @@ SIGNATURES = {
     "lbm_adjoint_get": (c_int32, [c_void_p, c_void_p, c_void_p, _D]),
     "lbm_destroy": (None, [c_void_p]),
     "lbm_strerror": (ctypes.c_char_p, [c_int32]),
+    "lbm_abi_version": (c_int32, []),
     "lbm3_workspace_bytes": (c_size_t, [_P3]),
     "lbm3_init": (c_int32, [POINTER(c_void_p), _P3, c_void_p, c_size_t, c_void_p, c_void_p]),
     "lbm3_step": (c_int32, [c_void_p, c_int64]),
@@ -115,6 +118,9 @@ def load(path: str | None = None) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
+    if lib.lbm_abi_version() != ABI_VERSION:
+        raise ImportError(f"{p}: interface version {lib.lbm_abi_version()}, the binding expects "
+                          f"{ABI_VERSION} (rebuild with python -m paper_1507_03521_amd.build)")
     if path is None:
         _lib = lib
     return lib

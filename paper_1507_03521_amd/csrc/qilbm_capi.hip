@@ -426,6 +426,8 @@ const char* lbm_strerror(lbm_status s) {
   return "unknown status";
 }
 
+int32_t lbm_abi_version(void) { return QILBM_ABI_VERSION; }
+
 }  // extern "C"
 
 // ------------------------------------------------------------------ adjoint

@@ -100,6 +100,11 @@ static int run3(int precision, int bc, double tol) {
 }
 
 int main(void) {
+  if (lbm_abi_version() != QILBM_ABI_VERSION) {
+    fprintf(stderr, "library interface version %d, header %d\n", (int)lbm_abi_version(),
+            QILBM_ABI_VERSION);
+    return 1;
+  }
   int rc = run(LBM_FP64, 1e-12);
   if (rc == 0) rc = run(LBM_FP32, 0.0);
   if (rc == 0) rc = run3(LBM_FP64, LBM_BC_PERIODIC, 1e-12);

@@ -100,6 +100,15 @@ def test_null_context_calls(lib):
     assert lib.lbm_strerror(_lib.LBM_EDIVERGED).decode().startswith("non-finite")
 
 
+def test_abi_version_matches_header_and_binding():
+    """The library reports the QILBM_ABI_VERSION of the header it was built
+    with, and the binding's structs follow that same version."""
+    hdr = open([h for h in HEADERS if h.endswith("qilbm.h")][0]).read()
+    version = int(re.search(r"#define QILBM_ABI_VERSION (\d+)", hdr).group(1))
+    lib = _lib.load()
+    assert lib.lbm_abi_version() == version == _lib.ABI_VERSION
+
+
 def test_workspace_sizes_scale_with_precision(lib):
     b = {}
     for prec in (0, 1, 2):
