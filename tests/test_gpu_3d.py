@@ -383,3 +383,28 @@ def test_trt_magic_invalid_is_refused(magic):
     pb = _problem(5, 4, 3, wl.PERIODIC)
     with pytest.raises(QilbmError):
         Lattice3D(dict(pb.as_dict(), trt_magic=magic), np.zeros((3, 4, 5)), device="cuda:0")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trt_channel_flow_exact_3d(precision):
+    """Body-force channel between the z walls at tau_f = 2 (4 x 4 x 16,
+    single phase): TRT with magic 3/16 gives the exact parabola u_x = g/(2 nu)
+    (z + 1/2)(nz - 1/2 - z) (FP64 to 1e-10, FP32 to 1e-5), BGK misses it by
+    more than 1 %."""
+    import math
+    from paper_1507_03521_amd import Lattice3D
+    nx, ny, nz, gx, tau = 4, 4, 16, 1e-6, 2.0
+    pb = _problem(nx, ny, nz, wl.WALLS_Z, (gx, 0.0, 0.0)).with_(tau_f=tau, rho_ref=0.0)
+    nu = (tau - 0.5) / 3.0
+    z = np.arange(nz, dtype=float)
+    exact = gx / (2 * nu) * (z + 0.5) * (nz - 0.5 - z)
+    err = {}
+    for magic in (3.0 / 16.0, 0.0):
+        lat = Lattice3D(dict(pb.as_dict(), trt_magic=magic), np.ones((nz, ny, nx)),
+                        precision=precision, device="cuda:0")
+        lat.step(int(40 * nz * nz / (math.pi ** 2 * nu)))
+        ux = lat.moments(("ux",))["ux"].cpu().numpy()
+        assert np.abs(ux - ux[:, :1, :1]).max() <= 1e-12 * exact.max()   # uniform in x, y
+        err[magic] = float(np.abs(ux[:, 0, 0] - exact).max() / exact.max())
+    assert err[3.0 / 16.0] < (1e-10 if precision == "fp64" else 1e-5)
+    assert err[0.0] > 1e-2

@@ -256,3 +256,31 @@ def test_trt_3d_collision_keeps_mass_and_momentum_change(magic):
         assert float((jt - (j + O.CS2 * m["F"][a])).abs().max()) < 1e-14 * 19 * scale + 1e-18
         assert float((jt - (c * fb).sum(0)).abs().max()) < 1e-14 * 19 * scale + 1e-18
     assert float((ft - fb).abs().max()) > 1e-8
+
+
+def test_trt_3d_channel_flow_is_exact_at_magic_three_sixteenths():
+    """Body-force channel between half-way bounce-back walls normal to z
+    (single phase, tau_f = 2, 8 nodes across): the steady profile of the
+    Navier-Stokes limit is the parabola u_x = g/(2 nu) (z + 1/2)(nz - 1/2 - z)
+    with the walls half a node outside the end nodes. The TRT collision with
+    magic parameter 3/16 places the bounce-back walls exactly there, so the
+    lattice profile equals the parabola to round-off (Ginzburg, Verhaeghe and
+    d'Humieres 2008); BGK at this tau_f misses it by a wall-slip error of
+    order (tau_f - 1/2)^2 / nz^2."""
+    nz, tau, gx = 8, 2.0, 1e-6
+    nu = (tau - 0.5) / 3.0
+    pb = wl.droplet3d().with_(nx=1, ny=1, nz=nz, tau_f=tau, bc=O.WALLS_Z, gx=gx, gy=0.0,
+                              gz=0.0, rho_ref=0.0)
+    z = np.arange(nz, dtype=float)
+    exact = gx / (2 * nu) * (z + 0.5) * (nz - 0.5 - z)
+    nsteps = int(40 * nz * nz / (math.pi ** 2 * nu))  # e^-40 of the slowest mode left
+    err = {}
+    for magic in (3.0 / 16.0, 0.0):
+        co = _co(pb, trt_magic=magic)
+        f, g = O.initial_state(torch.ones((nz, 1, 1), dtype=torch.float64), co)
+        for _ in range(nsteps):
+            f, g = O.step(f, g, co)
+        ux = O.macroscopic(f, g, co)["u"][0][:, 0, 0].numpy()
+        err[magic] = float(np.abs(ux - exact).max() / exact.max())
+    assert err[3.0 / 16.0] < 1e-12
+    assert err[0.0] > 1e-2
