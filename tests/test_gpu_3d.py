@@ -185,18 +185,22 @@ def _set_bytes(N, word):
 
 # 256^3 (one descriptor per population set) and lattices whose population
 # sets exceed 4 GiB (one descriptor per plane)
-CROP_CASES = [("fp64", 256, 256), ("fp32", 256, 256), ("fp64", 320, 288), ("fp32", 400, 360)]
+# the last two: the two-relaxation-time collision of f (magic 1/4) at 256^3
+CROP_CASES = [("fp64", 256, 256, 0.0), ("fp32", 256, 256, 0.0), ("fp64", 320, 288, 0.0),
+              ("fp32", 400, 360, 0.0), ("fp64", 256, 256, 0.25), ("fp32", 256, 256, 0.25)]
 
 
-@pytest.mark.parametrize("precision,nx,nz", CROP_CASES)
-def test_full_size_rt3d_crop(precision, nx, nz):
+@pytest.mark.parametrize("precision,nx,nz,magic", CROP_CASES)
+def test_full_size_rt3d_crop(precision, nx, nz, magic):
     """Rayleigh-Taylor box: two steps, then one more step compared on the
     interior of a 24 x 24 x nz crop stepped by the oracle."""
+    from paper_1507_03521_amd import Lattice3D
     pb = wl.rt3d(nx=nx, nz=nz)
     big = _set_bytes(nx * nx * nz, 8 if precision == "fp64" else 4) > 2 ** 32 - 1
     assert big == (nx != 256)
     phi0 = wl.phi0_3d(pb)
-    lat = _lattice(pb, phi0, precision)
+    lat = Lattice3D(dict(pb.as_dict(), trt_magic=magic), phi0, precision=precision,
+                    device="cuda:0")
     lat.step(2)
     fa, ga = lat.get_state()
     x0, y0, w, m = 100, 37, 24, 5
@@ -208,7 +212,9 @@ def test_full_size_rt3d_crop(precision, nx, nz):
     fg = fb[:, :, y0 + m:y0 + w - m, x0 + m:x0 + w - m].cpu()
     gg = gb[:, :, y0 + m:y0 + w - m, x0 + m:x0 + w - m].cpu()
     del fb, gb
-    fr, gr = O.step(fc, gc, _co(pb))
+    co = O.coefficients(pb.rho_A, pb.rho_B, pb.sigma, pb.W, pb.M, pb.tau_f, pb.tau_g,
+                        pb.gx, pb.gy, pb.gz, pb.ref_density, pb.bc, trt_magic=magic)
+    fr, gr = O.step(fc, gc, co)
     fr = fr[:, :, m:w - m, m:w - m]
     gr = gr[:, :, m:w - m, m:w - m]
     tf, tg = TOL[precision]

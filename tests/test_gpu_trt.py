@@ -143,3 +143,49 @@ def test_trt_delays_the_re3000_rayleigh_taylor_divergence():
     lat.step(15000)
     m1 = lat.mass()                   # raises LBM_EDIVERGED if not finite
     assert abs(m1[0] - m0[0]) < 1e-12 * abs(m0[0])
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32"])
+def test_trt_full_size_two_step_pass(precision):
+    """2048 x 8192 Rayleigh-Taylor lattice between walls with the TRT
+    collision (magic 1/4), in the two-steps-per-launch shape the benchmark
+    times: two steps from a random pre-collision state, compared with the
+    oracle on sampled windows (walls, a segment boundary, a strip boundary,
+    the periodic seam, the middle). The oracle steps each window twice; it
+    extends 10 nodes beyond the compared nodes on every side that is not a
+    wall (two steps depend on nodes within 8)."""
+    print(f"case trt full size rt2048 {precision}", flush=True)
+    pb = wl.rt2048()
+    nx, ny, magic, m = pb.nx, pb.ny, 0.25, 10
+    f0, g0 = wl.random_state(nx, ny, seed=41)
+    lat = _lattice(pb, np.full((ny, nx), 0.5), magic, precision)
+    lat.set_state(f0, g0)
+    del f0, g0
+    fa, ga = (t.cpu() for t in lat.get_state())      # the stored state
+    info = lat.pass_info()
+    assert info["steps"] == 2
+    lat.step(2)
+    fs, gs = lat.get_state()
+    seg, width = info["seg_rows"], -(-nx // info["strips"])
+    picks = [(0, 250), (ny - 12, 1000), (seg - 6, width - 6), (ny // 2 - 6, nx - 6),
+             (ny // 2 - 6, nx // 4 - 6)]
+    tf, tg = TOL[precision]
+    for y0, x0 in picks:
+        h = w = 12
+        lo, hi = max(0, y0 - m), min(ny, y0 + h + m)
+        rows = torch.arange(lo, hi)
+        cols = torch.as_tensor(np.arange(x0 - m, x0 + w + m) % nx)
+        co = O.coefficients_of(pb.with_(nx=len(cols), ny=len(rows)), trt_magic=magic)
+        fw = fa[:, rows][:, :, cols]
+        gw = ga[:, rows][:, :, cols]
+        fr, gr = O.step(*O.step(fw, gw, co), co)
+        r0 = y0 - lo
+        fr, gr = fr[:, r0:r0 + h, m:m + w], gr[:, r0:r0 + h, m:m + w]
+        cc = cols[m:m + w].to(fs.device)
+        fg = fs[:, y0:y0 + h][:, :, cc].cpu()
+        gg = gs[:, y0:y0 + h][:, :, cc].cpu()
+        ef, eg = _rel(fg, fr), _rel(gg, gr)
+        print(f"  window y0={y0} x0={x0}: rel f {ef:.2e} g {eg:.2e}", flush=True)
+        assert ef < tf and eg < tg
+    del lat, fs, gs
+    torch.cuda.empty_cache()
