@@ -257,16 +257,78 @@ def cpu_baseline(pb, phi0, rows: int, steps: int):
                                           f"{dt1:.1f} s"))
 
 
+def _crossings(col):
+    """Positions of the phi = 1/2 crossings along a column (linear
+    interpolation between nodes)."""
+    c = col.cpu().numpy()
+    return [y + (0.5 - c[y]) / (c[y + 1] - c[y]) for y in range(len(c) - 1)
+            if (c[y] - 0.5) * (c[y + 1] - 0.5) < 0]
+
+
 def interface_tips(phi, nx):
     """Spike tip: lowest phi = 1/2 crossing along x = nx/2 (heavy fluid
-    falling); bubble tip: highest crossing along x = 0 (light fluid rising);
-    linear interpolation between nodes."""
-    def crossings(col):
-        c = col.cpu().numpy()
-        return [y + (0.5 - c[y]) / (c[y + 1] - c[y]) for y in range(len(c) - 1)
-                if (c[y] - 0.5) * (c[y + 1] - 0.5) < 0]
-    lo, hi = crossings(phi[:, nx // 2]), crossings(phi[:, 0])
+    falling); bubble tip: highest crossing along x = 0 (light fluid rising)."""
+    lo, hi = _crossings(phi[:, nx // 2]), _crossings(phi[:, 0])
     return (min(lo) if lo else float("nan")), (max(hi) if hi else float("nan"))
+
+
+def interface_tips_3d(phi):
+    """The same in the 3-D box ([nz, ny, nx]): spike along the column
+    (nx/2, ny/2), where the initial interface is lowest; bubble along (0, 0),
+    where it is highest."""
+    nz, ny, nx = phi.shape
+    lo, hi = _crossings(phi[:, ny // 2, nx // 2]), _crossings(phi[:, 0, 0])
+    return (min(lo) if lo else float("nan")), (max(hi) if hi else float("nan"))
+
+
+def precision_study_3d(steps: int, every: int):
+    """The 256^3 Rayleigh-Taylor box in FP64 and FP32: tip positions every
+    ``every`` steps, drift of the phi total, and the deviation of the FP32
+    run from the FP64 run."""
+    import torch
+    import workloads as wl
+    from paper_1507_03521_amd import Lattice3D, QilbmError
+    pb = wl.rt3d()
+    phi0 = wl.phi0_3d(pb)
+    t_unit = math.sqrt(abs(pb.gz) / pb.nx)        # t* = t sqrt(g / L), L = nx
+    out, phi64, tips64 = {}, None, None
+    for prec in ("fp64", "fp32"):
+        lat = Lattice3D(pb.as_dict(), phi0, precision=prec, device="cuda:0")
+        m0 = lat.mass()
+        tips, diverged, t0, done = [], None, time.perf_counter(), 0
+        while done < steps:
+            n = min(every, steps - done)
+            lat.step(n)
+            done += n
+            try:
+                m = lat.mass()
+            except QilbmError:
+                m = (float("nan"),)
+            if not math.isfinite(m[0]):
+                diverged = done
+                log(f"  3-D {prec}: non-finite state by step {done}")
+                break
+            s, b = interface_tips_3d(lat.moments(("phi",))["phi"])
+            tips.append((done, round(s, 4), round(b, 4)))
+            log(f"  3-D {prec}: step {done}/{steps} (t* {done * t_unit:.3f}) spike {s:.3f} "
+                f"bubble {b:.3f}, {time.perf_counter() - t0:.0f} s")
+        r = dict(tips_every=every, tips=tips, diverged_at=diverged,
+                 seconds=round(time.perf_counter() - t0, 1))
+        if diverged is None:
+            r["phi_total_drift_rel"] = abs(lat.mass()[0] - m0[0]) / abs(m0[0])
+            phi = lat.moments(("phi",))["phi"]
+            if prec == "fp64":
+                phi64, tips64 = phi, tips
+            elif phi64 is not None:
+                r["phi_max_abs_dev_vs_fp64"] = float((phi - phi64).abs().max())
+                r["phi_rms_dev_vs_fp64"] = float((phi - phi64).square().mean().sqrt())
+                r["tip_max_abs_dev_vs_fp64"] = max(
+                    max(abs(a[1] - b[1]), abs(a[2] - b[2])) for a, b in zip(tips, tips64))
+        out[prec] = r
+        del lat
+        torch.cuda.empty_cache()
+    return dict(study="precision", workload="rt3d 256x256x256", steps=steps,
+                t_star=round(steps * t_unit, 4), **out)
 
 
 def precision_study(pb, phi0, steps: int, every: int):
@@ -426,6 +488,8 @@ def main():
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
                     help="instead of timing: run STEPS steps in each precision and print "
                          "tip positions, mass drift and deviation from FP64 (one JSON line)")
+    ap.add_argument("--precision-study-3d", type=int, default=0, metavar="STEPS",
+                    help="instead of timing: the same for the 256^3 box in FP64 and FP32")
     ap.add_argument("--study-every", type=int, default=5000)
     ap.add_argument("--adjoint-study", type=int, nargs=3, default=None,
                     metavar=("WARM", "WINDOW", "C"),
@@ -453,6 +517,10 @@ def main():
         return
     if args.precision_study:
         print(json.dumps(precision_study(pb, phi0, args.precision_study, args.study_every)),
+              flush=True)
+        return
+    if args.precision_study_3d:
+        print(json.dumps(precision_study_3d(args.precision_study_3d, args.study_every)),
               flush=True)
         return
     if args.copy_calibration:
