@@ -192,3 +192,9 @@ def test_trt_parameter_checks(lib):
     assert lib.lbm_workspace_bytes(byref(p)) == lib.lbm_workspace_bytes(byref(_params()))
     assert lib.lbm_adjoint_workspace_bytes(byref(p)) == 0
     assert lib.lbm_adjoint_workspace_bytes(byref(_params())) > 0
+
+
+def test_binding_refuses_a_library_of_another_abi_version(monkeypatch):
+    monkeypatch.setattr(_lib, "ABI_VERSION", _lib.ABI_VERSION + 1)
+    with pytest.raises(ImportError, match="interface version"):
+        _lib.load(_lib.LIB_PATH)
