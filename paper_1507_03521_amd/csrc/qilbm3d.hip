@@ -735,10 +735,11 @@ struct FzLds {
 };
 
 // With the scattered order parameter: three planes of Q2.29 partial sums of
-// the next step's phi over the core tile.
+// the next step's phi over the core tile and a one-node ring around it (the
+// targets of every word the tile's nodes stream).
 template <int P>
 struct FzLdsQ : FzLds<P> {
-  int32_t acc[3][fz::TX * fz::TY];
+  int32_t acc[3][fz::Reg<1>::A];
 };
 
 struct Fz3Shape {
@@ -840,9 +841,9 @@ __device__ __forceinline__ void lds_stencil(const T* pm, const T* p0, const T* p
 // post-collision g word to the node it streams to, accumulating the next
 // step's sum into phiq_out (zero on entry): integer sums, so the order of
 // the additions does not matter and the result equals the pulled sum
-// exactly. Targets inside the core tile accumulate in LDS (three planes,
-// flushed with one atomic add per node once a plane has all its sources);
-// targets outside go to phiq_out by atomic add.
+// exactly. Every target (core tile plus a one-node ring) accumulates in LDS
+// (three planes, flushed with one atomic add per node once a plane has all
+// its sources from this tile).
 template <int P, bool BIG, bool PHIQ = false, bool TRT = false>
 __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3<P> out,
                                                                 Coef3<typename PrecT<P>::T> k,
@@ -879,24 +880,28 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
   };
   auto real = [&](int zz) { return wl ? (zz >= 0 && zz < nz) : true; };
   const uint32_t planeN = (uint32_t)g.nx * (uint32_t)g.ny;
-  // adds the LDS partial sums of virtual plane zf to phiq_out and clears them
+  // adds the LDS partial sums of virtual plane zf to phiq_out and clears
+  // them; region node (ly, lx) is global column (x0 - 1 + lx, y0 - 1 + ly),
+  // wrapped (positions that wrap onto the same node add up there)
   auto flush = [&](int zf) {
     if constexpr (PHIQ) {
       int32_t* acc = L.acc[(zf - vbase) % 3];
       const bool ok = real(zf);
       const uint32_t zb = ok ? (uint32_t)wrapm(zf, nz) * planeN : 0u;
-      for (int r = tid; r < TX * TY; r += NT) {
-        const int ly = r / TX, lx = r - ly * TX;
-        const int X = x0 + lx, Y = y0 + ly;
+      for (int r = tid; r < RC::A; r += NT) {
+        const int ly = r / RC::W, lx = r - ly * RC::W;
         const int32_t v = acc[r];
         acc[r] = 0;
-        if (ok && X < g.nx && Y < g.ny && v != 0)
-          atomicAdd(&phiq_out[zb + (uint32_t)Y * (uint32_t)g.nx + (uint32_t)X], v);
+        if (ok && v != 0) {
+          const uint32_t X = (uint32_t)wrapm(x0 - 1 + lx, g.nx);
+          const uint32_t Y = (uint32_t)wrapm(y0 - 1 + ly, g.ny);
+          atomicAdd(&phiq_out[zb + Y * (uint32_t)g.nx + X], v);
+        }
       }
     }
   };
   if constexpr (PHIQ) {
-    for (int r = tid; r < 3 * TX * TY; r += NT) (&L.acc[0][0])[r] = 0;
+    for (int r = tid; r < 3 * RC::A; r += NT) (&L.acc[0][0])[r] = 0;
     __syncthreads();
   }
 
@@ -1057,6 +1062,7 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
         for (int i = 0; i < 19; ++i) w.f.stb(i, sb, vb, f[i]);
         if constexpr (FixedG<P>::value) {
           // g_0 closes the node's Q2.29 sum at the pulled total
+          const int er = (ly + 1) * RC::W + lx + 1;    // the node in the ring region
           int32_t rest = 0;
 #pragma unroll
           for (int i = 1; i < 19; ++i) {
@@ -1067,22 +1073,14 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
               // the word streams to (X, Y, zd) + c_i, or back to this node
               // (as the opposite population) beyond a wall
               const int zt = zd + CZ(i);
-              if (wl && (zt < 0 || zt >= nz)) {
-                atomicAdd(&L.acc[(zd - vbase) % 3][r], word);
-              } else {
-                const int tX = wrapm(X + CX(i), g.nx), tY = wrapm(Y + CY(i), g.ny);
-                const int tlx = tX - x0, tly = tY - y0;
-                if (tlx >= 0 && tlx < TX && tly >= 0 && tly < TY)
-                  atomicAdd(&L.acc[(zt - vbase) % 3][tly * TX + tlx], word);
-                else
-                  atomicAdd(&phiq_out[(uint32_t)wrapm(zt, nz) * planeN +
-                                      (uint32_t)tY * (uint32_t)g.nx + (uint32_t)tX],
-                            word);
-              }
+              if (wl && (zt < 0 || zt >= nz))
+                atomicAdd(&L.acc[(zd - vbase) % 3][er], word);
+              else
+                atomicAdd(&L.acc[(zt - vbase) % 3][er + CY(i) * RC::W + CX(i)], word);
             }
           }
           w.g.stb(0, sb, vb, qs - rest);
-          if constexpr (PHIQ) atomicAdd(&L.acc[(zd - vbase) % 3][r], qs - rest);
+          if constexpr (PHIQ) atomicAdd(&L.acc[(zd - vbase) % 3][er], qs - rest);
         } else {
 #pragma unroll
           for (int i = 0; i < 19; ++i) w.g.stb(i, sb, vb, gg[i]);
