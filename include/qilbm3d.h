@@ -24,7 +24,7 @@
  *     lattice total of phi is an exact integer invariant); LBM_FP16_STORE is
  *     not offered in 3-D.
  *   Kernels: the populations in a pull layout. FP32 runs one fused kernel
- *     per step (a workgroup sweeps a 64 x 16 column tile along z, phi, mu and
+ *     per step (a workgroup sweeps a 64 x 8 column tile along z, phi, mu and
  *     p in LDS plane rings; the collision scatters each g word to the node
  *     it streams to, accumulating the next step's phi as an exact Q2.29 sum
  *     in a workspace buffer); FP64, and FP32 with LBM_FLAG_UNFUSED, run four

@@ -702,7 +702,9 @@ __global__ __launch_bounds__(256) void k3_phiq(Pop3<P_F32> in, int32_t* __restri
 // workgroup per CU, barrier-bound) the fused form was a quarter slower than
 // the four kernels.
 namespace fz {
-constexpr int TX = 64, TY = 16;
+// 64 x 8 columns: 48 KB of LDS, so three workgroups per CU (at most 168
+// VGPRs); 64 x 16 (81 KB, two per CU) measured 4 % slower, 32 x 16 11 %
+constexpr int TX = 64, TY = 8;
 template <int H>
 struct Reg {
   static constexpr int W = TX + 2 * H, HT = TY + 2 * H, A = W * HT;
@@ -1380,13 +1382,14 @@ void launch_collide(lbm3_ctx* c) {
                        in, out, phi, mu, p, coef3<T>(c), g, chunks_x(g));
 }
 
-template <int P>
+// workgroups of the kernel that will run resident on the whole GPU at once
+template <int P, bool TRT>
 int fused_resident3() {
   int dev = 0, cus = 0, per_cu = 0;
   if (hipGetDevice(&dev) != hipSuccess) return 0;
   if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
     return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_fused<P, false, true>,
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k3_fused<P, false, true, TRT>,
                                                    FzThreads<P>::value, 0) != hipSuccess)
     return 0;
   return cus * (per_cu > 0 ? per_cu : 1);
@@ -1409,7 +1412,8 @@ template <int P>
 lbm_status step_fused_p(lbm3_ctx* c, int64_t n) {
   using T = typename PrecT<P>::T;
   const Geom3& g = c->geom;
-  if (c->resident == 0) c->resident = fused_resident3<P>();
+  if (c->resident == 0)
+    c->resident = c->prm.trt_magic > 0.0 ? fused_resident3<P, true>() : fused_resident3<P, false>();
   if (c->resident <= 0) return LBM_EDEVICE;
   const Fz3Shape sh = fused_shape3(g, c->resident);
   const unsigned nblk = (unsigned)(sh.ntx * sh.nty * sh.nseg);

@@ -226,12 +226,13 @@ def test_full_size_rt3d_crop(precision, nx, nz, magic):
     assert np.isfinite(mass).all()
 
 
-# shapes for the fused z-sweep kernel: tiles smaller than the 64 x 16 tile
-# (multiple wraps), ragged tiles, several tiles, and segments of one or a
-# few planes (small tile counts give many segments)
+# shapes for the fused z-sweep kernel (64 x 8 column tiles): lattices
+# smaller than a tile (multiple wraps), ragged tiles, several tiles, exactly
+# one and two tiles, and segments of one or a few planes (small tile counts
+# give many segments)
 FUSED_SHAPES = [(3, 3, 3, wl.PERIODIC), (5, 4, 3, wl.WALLS_Z), (17, 9, 6, wl.PERIODIC),
                 (33, 20, 11, wl.WALLS_Z), (70, 17, 9, wl.PERIODIC), (130, 33, 40, wl.WALLS_Z),
-                (64, 16, 300, wl.PERIODIC)]
+                (40, 6, 7, wl.WALLS_Z), (64, 8, 200, wl.PERIODIC), (64, 16, 300, wl.PERIODIC)]
 FUSED_TOL = {"fp32": (3e-5, 1e-6)}
 
 
