@@ -444,3 +444,31 @@ def step_vjp(f, g, problem, fbar, gbar):
           (g1 * torch.as_tensor(gbar, dtype=DTYPE)).sum()
     df, dg, dsig, dmob = torch.autograd.grad(out, (f, g, sig, mob))
     return df, dg, float(dsig), float(dmob)
+
+
+def step_jvp(f, g, problem, df, dg, dsigma=0.0, dM=0.0):
+    """Jacobian-vector product of one step by forward-mode differentiation
+    (dual numbers, ``torch.func.jvp``): the tangent of the state at t+1 for a
+    tangent (df, dg) of the state at t and (dsigma, dM) of the parameters.
+    Independent of the reverse mode of :func:`step_vjp`, so the pair checks
+    <J^T w, v> = <w, J v>."""
+    def one(f, g, sig, mob):
+        return step(f, g, coefficients_of(problem, sigma=sig, M=mob))
+    t = lambda a: torch.as_tensor(a, dtype=DTYPE)
+    _, (tf, tg) = torch.func.jvp(
+        one, (t(f), t(g), t(problem.sigma), t(problem.M)),
+        (t(df), t(dg), t(dsigma), t(dM)))
+    return tf, tg
+
+
+def loss_jvp(phi0, problem, nsteps, loss_of_phi, dphi0, dsigma=0.0, dM=0.0):
+    """Directional derivative of L(phi_K) along (dphi0, dsigma, dM) by
+    forward-mode differentiation through :func:`run`."""
+    def L(p0, sig, mob):
+        co = coefficients_of(problem, sigma=sig, M=mob)
+        f, g = run(p0, co, nsteps)
+        return loss_of_phi(g.sum(dim=0))
+    t = lambda a: torch.as_tensor(a, dtype=DTYPE)
+    _, dL = torch.func.jvp(L, (t(phi0), t(problem.sigma), t(problem.M)),
+                           (t(dphi0), t(dsigma), t(dM)))
+    return float(dL)

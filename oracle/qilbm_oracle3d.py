@@ -124,6 +124,11 @@ def lap(psi, bc):
 
 # ----------------------------------------------------- free energy (Sec. II)
 
+def psi_bulk(phi, co):
+    """Double-well bulk free-energy density beta (phi - phi_A)^2 (phi - phi_B)^2."""
+    return co.beta * (phi - PHI_A) ** 2 * (phi - PHI_B) ** 2
+
+
 def dpsi_dphi(phi, co):
     """4 beta (phi - phi_A)(phi - phi_B)(phi - (phi_A + phi_B)/2)."""
     return 4.0 * co.beta * (phi - PHI_A) * (phi - PHI_B) * (phi - 0.5 * (PHI_A + PHI_B))
@@ -306,8 +311,7 @@ def laplace_pressure(f, g, co):
     outside (phi < 0.01)."""
     m = macroscopic(f, g, co)
     phi = m["phi"]
-    psi = co.beta * (phi - PHI_A) ** 2 * (phi - PHI_B) ** 2
-    p0 = phi * dpsi_dphi(phi, co) - psi
+    p0 = phi * dpsi_dphi(phi, co) - psi_bulk(phi, co)
     gph = grad(phi, co.bc)
     P = (p0 - co.kappa * phi * lap(phi, co.bc)
          + 0.5 * co.kappa * sum(ga * ga for ga in gph) + m["p"])

@@ -1157,7 +1157,8 @@ __global__ __launch_bounds__(256) void k3_mass_partial(Pop3<P> in,
                                                        const typename PrecT<P>::T* __restrict__ phi,
                                                        const typename PrecT<P>::T* __restrict__ mu,
                                                        double* __restrict__ part,
-                                                       Coef3<typename PrecT<P>::T> k, Geom3 g,
+                                                       Coef3<typename PrecT<P>::T> k,
+                                                       double rho_B, double drho, Geom3 g,
                                                        uint32_t nxc) {
   using T = typename PrecT<P>::T;
   const PopView<P, BIG> v(in);
@@ -1175,7 +1176,7 @@ __global__ __launch_bounds__(256) void k3_mass_partial(Pop3<P> in,
       else ex += v.g.ld(s.plane, s.row, s.vo);
     }
     a[0] += ex;
-    a[1] += double(k.c.rho_B) + double(k.c.drho) * ex;
+    a[1] += rho_B + drho * ex;       // binary64 density parameters
     for (int c = 0; c < 3; ++c) a[2 + c] += double(m.rho) * double(m.u[c]);
   });
   __shared__ double red[4][5];
@@ -1500,12 +1501,13 @@ lbm_status mass_p(lbm3_ctx* c) {
   Pop3<P> in{c->pop[c->cur], g.Ns};
   const T* phi = (const T*)c->fields;
   const T* mu = (const T*)(c->fields + g.Ns * 8);
+  const Coef3<double> k64 = coef3<double>(c);
   if (big3<P>(g))
     hipLaunchKernelGGL((k3_mass_partial<P, true>), dim3(c->nred), dim3(256), 0, c->stream, in,
-                       phi, mu, c->part, coef3<T>(c), g, chunks_x(g));
+                       phi, mu, c->part, coef3<T>(c), k64.c.rho_B, k64.c.drho, g, chunks_x(g));
   else
     hipLaunchKernelGGL((k3_mass_partial<P, false>), dim3(c->nred), dim3(256), 0, c->stream, in,
-                       phi, mu, c->part, coef3<T>(c), g, chunks_x(g));
+                       phi, mu, c->part, coef3<T>(c), k64.c.rho_B, k64.c.drho, g, chunks_x(g));
   if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
   hipLaunchKernelGGL(k3_sum5, dim3(1), dim3(256), 0, c->stream, (const double*)c->part, c->nred,
                      c->red_out);

@@ -200,7 +200,7 @@ template <int P>
 lbm_status mass_p(lbm_ctx* c) {
   using T = typename PrecT<P>::T;
   return st(launch_mass<P>(c->pop[c->cur], phi_f(c), mu_f(c), c->part, c->nred, c->red_out,
-                           coef_t<T>(c), c->geom, c->stream));
+                           coef_t<T>(c), coef_t<double>(c), c->geom, c->stream));
 }
 
 }  // namespace

@@ -94,7 +94,8 @@ hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename P
                               hipStream_t s, bool trt = false);
 template <int P>
 hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
-                       const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s);
+                       const Coef<typename PrecT<P>::T>& c, const Coef<double>& c64,
+                       const Geom& g, hipStream_t s);
 hipError_t launch_sum_partials(const double* part, int nb, int width, double* out, hipStream_t s);
 
 }  // namespace qilbm

@@ -309,7 +309,8 @@ __global__ __launch_bounds__(256) void k_mass_partial(Pop<P> in,
                                                       const typename PrecT<P>::T* __restrict__ phi,
                                                       const typename PrecT<P>::T* __restrict__ mu,
                                                       double* __restrict__ part,
-                                                      Coef<typename PrecT<P>::T> c, Geom g) {
+                                                      Coef<typename PrecT<P>::T> c,
+                                                      double rho_B, double drho, Geom g) {
   using T = typename PrecT<P>::T;
   double a[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t n = (int64_t)blockIdx.x * 256 + threadIdx.x; n < g.N;
@@ -318,10 +319,11 @@ __global__ __launch_bounds__(256) void k_mass_partial(Pop<P> in,
     T f[9], S, jx, jy;
     Macro<T> m;
     node_macro<P>(in, phi, mu, x, y, c, g, f, m, S, jx, jy);
-    // phi and rho from the exact stored values (so that the totals show the
-    // scheme's conservation rather than the rounding of the compute type)
+    // phi and rho from the exact stored values and the binary64 density
+    // parameters (so that the totals show the scheme's conservation rather
+    // than the rounding of the compute type)
     const double ph = pull_phi_exact<P>(in, x, y, g);
-    const double rho = double(c.rho_B) + double(c.drho) * ph;
+    const double rho = rho_B + drho * ph;
     a[0] += ph;
     a[1] += rho;
     a[2] += double(m.rho) * double(m.ux);
@@ -1636,13 +1638,14 @@ hipError_t launch_step2_fused(const void* pin, void* pout, const Coef<typename P
 
 template <int P>
 hipError_t launch_mass(const void* pop, void* phi, void* mu, double* part, int nred, double* out,
-                       const Coef<typename PrecT<P>::T>& c, const Geom& g, hipStream_t s) {
+                       const Coef<typename PrecT<P>::T>& c, const Coef<double>& c64,
+                       const Geom& g, hipStream_t s) {
   using T = typename PrecT<P>::T;
   hipError_t e = launch_fields<P>(pop, phi, mu, c, g, s);
   if (e != hipSuccess) return e;
   Pop<P> i{(char*)pop, g.Ns};
   hipLaunchKernelGGL(k_mass_partial<P>, dim3(nred), dim3(256), 0, s, i, (const T*)phi,
-                     (const T*)mu, part, c, g);
+                     (const T*)mu, part, c, c64.rho_B, c64.drho, g);
   hipLaunchKernelGGL(k_sum_partials, dim3(1), dim3(256), 0, s, (const double*)part, nred, 4, out);
   return hipGetLastError();
 }
@@ -1679,7 +1682,8 @@ hipError_t launch_sum_partials(const double* part, int nb, int width, double* ou
                                             const Geom&, const FusedShape&, void*, void*,        \
                                             hipStream_t, bool);                                  \
   template hipError_t launch_mass<P>(const void*, void*, void*, double*, int, double*,           \
-                                     const Coef<PrecT<P>::T>&, const Geom&, hipStream_t);
+                                     const Coef<PrecT<P>::T>&, const Coef<double>&, const Geom&,  \
+                                     hipStream_t);
 
 QILBM_INSTANTIATE(P_F64)
 QILBM_INSTANTIATE(P_F32)

@@ -125,6 +125,34 @@ def test_initial_state_and_moments(bc, precision):
                 assert _rel(mo[k], m["u"][a]) < t["u"], k
 
 
+@pytest.mark.parametrize("precision,tol", [("fp64", (1e-14, 1e-12)), ("fp32", (1e-14, 2e-5))])
+@pytest.mark.parametrize("nx,ny,nz,bc,g", [SHAPES[2], SHAPES[3]])
+def test_mass_totals_match_oracle(nx, ny, nz, bc, g, precision, tol):
+    """All five lbm3_mass totals (sum phi, sum rho, sum rho u) against the
+    oracle's totals of the same stored state (read back exactly), from a
+    random state and after 2 steps. FP32 forms u in binary32: momentum
+    tolerance relative to sum |rho u|."""
+    print(f"case 3-D mass totals {nx}x{ny}x{nz} {precision}", flush=True)
+    pb = _problem(nx, ny, nz, bc, g)
+    f, gg = wl.random_state3d(nx, ny, nz, seed=nx + ny)
+    lat = _lattice(pb, gg.sum(0), precision)
+    lat.set_state(f, gg)
+    co = _co(pb)
+    for k in range(2):
+        m = lat.mass()
+        fs, gs = (t.cpu() for t in lat.get_state())
+        ref = O.mass(fs, gs, co)
+        mac = O.macroscopic(fs, gs, co)
+        for a in range(2):
+            assert m[a] == pytest.approx(ref[a], rel=tol[0]), (k, a)
+        for a in range(3):
+            scale = float((mac["rho"] * mac["u"][a]).abs().sum())
+            err = abs(m[2 + a] - ref[2 + a]) / scale
+            print(f"  step {2 * k}: momentum {a} rel {err:.2e}", flush=True)
+            assert err <= tol[1], (k, a)
+        lat.step(2)
+
+
 def test_droplet_many_steps_fp64():
     """32^3 static droplet, 100 steps: f within 2e-11, g within 1e-12 of the
     oracle; the totals of phi and rho within 1e-12 of their initial values."""

@@ -52,6 +52,57 @@ def test_step_vjp_matches_oracle(nx, ny, bc, gy):
     assert dm == pytest.approx(rm, rel=1e-11)
 
 
+@pytest.mark.parametrize("nx,ny,bc,gy", CASES)
+def test_step_vjp_dot_product_with_forward_mode(nx, ny, bc, gy):
+    """Dot-product test of the hand-written adjoint step: for random state
+    tangents v = (df, dg, dsigma, dM) and cotangents w = (fbar, gbar),
+    <J^T w, v> from the GPU adjoint equals <w, J v> with J v from the
+    oracle's forward mode (dual numbers: no transposition involved)."""
+    print(f"case dot product {nx}x{ny} bc={bc}", flush=True)
+    pb = wl.droplet64().with_(nx=nx, ny=ny, bc=bc, gy=gy, rho_ref=0.5)
+    f, g = wl.random_state(nx, ny, seed=37)
+    rng = np.random.default_rng(11)
+    fbar, gbar, vf, vg = (rng.standard_normal((9, ny, nx)) for _ in range(4))
+    vs, vm = 0.4 * pb.sigma, -0.3 * pb.M
+    lat = _lattice(pb, np.full((ny, nx), 0.5))
+    lat.set_state(f, g)
+    raw = lat.save_raw()
+    lat.adjoint_begin(torch.zeros((ny, nx), dtype=torch.float64, device="cuda:0"))
+    lat.adjoint_set(fbar, gbar)
+    lat.adjoint_step(raw)
+    df, dg, ds, dm = lat.adjoint_get()
+    tf, tg = O.step_jvp(f, g, pb, vf, vg, vs, vm)
+    t = lambda a: torch.as_tensor(a, dtype=torch.float64)
+    lhs = float((t(fbar) * tf).sum() + (t(gbar) * tg).sum())
+    rhs = float((df.cpu() * t(vf)).sum() + (dg.cpu() * t(vg)).sum()) + ds * vs + dm * vm
+    print(f"  <w, Jv> = {lhs:.15e}  <J^T w, v> = {rhs:.15e}", flush=True)
+    assert rhs == pytest.approx(lhs, rel=1e-10)
+
+
+def test_gradient_dot_direction_matches_forward_mode():
+    """End to end (15 steps with checkpoints): the GPU reverse-mode gradient
+    of L dotted with a direction (dphi0, dsigma, dM) equals the directional
+    derivative of the oracle's forward map by forward mode."""
+    from paper_1507_03521_amd import simulate
+    pb = wl.droplets512(small=True).with_(nx=16, ny=13, bc=wl.WALLS_Y, gy=-1e-5)
+    phi0 = wl.random_phi(pb.nx, pb.ny, seed=21, lo=0.1, hi=0.9)
+    target = _loss_target(pb.nx, pb.ny)
+    K = 15
+    loss = lambda ph: ((ph - target.to(ph.device)) ** 2).sum()
+    v = np.random.default_rng(5).standard_normal(phi0.shape)
+    vs, vm = 0.2 * pb.sigma, 0.2 * pb.M
+    dL = O.loss_jvp(phi0, pb, K, loss, v, vs, vm)
+    dev = "cuda:0"
+    p0 = torch.tensor(phi0, device=dev, requires_grad=True)
+    sig = torch.tensor(pb.sigma, dtype=torch.float64, requires_grad=True)
+    mob = torch.tensor(pb.M, dtype=torch.float64, requires_grad=True)
+    loss(simulate(p0, sig, mob, pb.as_dict(), K, checkpoint=4)).backward()
+    got = float((p0.grad.cpu() * torch.as_tensor(v)).sum()) + float(sig.grad) * vs + \
+        float(mob.grad) * vm
+    print(f"  forward mode {dL:.15e}  GPU reverse mode {got:.15e}", flush=True)
+    assert got == pytest.approx(dL, rel=1e-10)
+
+
 def _loss_target(nx, ny, seed=22):
     return torch.as_tensor(wl.random_phi(nx, ny, seed=seed, lo=0.2, hi=0.8))
 

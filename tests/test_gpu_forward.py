@@ -134,6 +134,62 @@ def test_droplet64_2000_steps_fp64():
     ref = O.mass(fr, gr, co)
     for a, b in zip(m1[:2], ref[:2]):
         assert a == pytest.approx(b, rel=1e-13)
+    # momentum totals: zero by symmetry up to the spurious currents; compared
+    # on the scale of sum |rho u| of the oracle's final state
+    _, rho, ux, uy, _, _ = O.moments(fr, gr, co)
+    for a, u in ((2, ux), (3, uy)):
+        scale = float((rho * u).abs().sum())
+        print(f"droplet64 momentum {a - 2}: gpu {m1[a]:.3e} oracle {ref[a]:.3e} scale {scale:.3e}",
+              flush=True)
+        assert abs(m1[a] - ref[a]) <= 1e-11 * scale
+
+
+# lbm_mass on arbitrary states: (precision, tolerance of sum phi and sum rho
+# relative to sum phi and sum rho, tolerance of the momentum totals relative
+# to sum |rho u|). FP32 and FP16 storage form u in binary32: u carries the
+# rounding of F = -phi grad mu with mu ~ 1e-3 from a difference of ~1e-2 terms
+# (binary32 rounding ~1e-9 on it), i.e. ~1e-6 of rho u (measured <= 3e-8).
+# FP32 takes phi from the exact Q2.29 g words. In FP16 storage the order
+# parameter of a node is the integer sum of the Q2.29 images of its g words
+# (g_0 itself, and each scaled binary16 g_i rounded to the nearest multiple of
+# 2^-29), which is what the scheme conserves exactly; the oracle sums the
+# binary16 values themselves, which differ from their images by at most 2^-30
+# each when they are not multiples of 2^-29: a bound of 8 * 2^-30 per node
+# (relative bound 8 * 2^-30 / min phi, min phi = 0.05 here, below).
+MASS_TOL = {"fp64": (1e-14, 1e-12), "fp32": (1e-14, 2e-5), "fp16": (1.5e-7, 2e-5)}
+
+
+@pytest.mark.parametrize("precision", ["fp64", "fp32", "fp16"])
+@pytest.mark.parametrize("nx,ny,bc,gx,gy", [(37, 29, wl.PERIODIC, 2e-5, -1e-5),
+                                            (300, 70, wl.WALLS_Y, 0.0, -3e-5),
+                                            (5, 4, wl.WALLS_Y, 1e-5, -1e-5)])
+def test_mass_totals_match_oracle(nx, ny, bc, gx, gy, precision):
+    """All four lbm_mass totals -- sum phi, sum rho and the momentum totals
+    sum rho u_x, sum rho u_y with rho u = sum_i c_i f_i + c_s^2 F / 2 -- against
+    the oracle's totals of the same stored state (read back exactly with
+    lbm_get_state), from a random state, and again after 3 steps."""
+    print(f"case mass totals {nx}x{ny} bc={bc} {precision}", flush=True)
+    pb = _problem(nx, ny, bc, gy).with_(gx=gx)
+    f, g = wl.random_state(nx, ny, seed=nx + 7 * ny)
+    lat = _lattice(pb, np.full((ny, nx), 0.5), precision=precision)
+    lat.set_state(f, g)
+    co = O.coefficients_of(pb)
+    tm, tu = MASS_TOL[precision]
+    for k in range(2):
+        m = lat.mass()
+        fs, gs = (t.cpu() for t in lat.get_state())
+        with torch.no_grad():
+            ref = O.mass(fs, gs, co)
+            _, rho, ux, uy, _, _ = O.moments(fs, gs, co)
+        for a in range(2):
+            assert m[a] == pytest.approx(ref[a], rel=tm), (k, a)
+        for a, u in ((2, ux), (3, uy)):
+            scale = float((rho * u).abs().sum())
+            err = abs(m[a] - ref[a]) / scale
+            print(f"  {'after 3 steps' if k else 'initial'}: momentum {a - 2} "
+                  f"gpu {m[a]:.6e} oracle {ref[a]:.6e} rel {err:.2e}", flush=True)
+            assert err <= tu, (k, a)
+        lat.step(3)
 
 
 def test_rayleigh_taylor_walls_fp64():

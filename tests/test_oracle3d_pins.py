@@ -129,6 +129,77 @@ def test_mass_conservation_3d(bc):
     assert m1[1] == pytest.approx(m0[1], rel=1e-14)
 
 
+def test_mass_momentum_of_uniform_moving_state_3d():
+    """rho u = sum_i c_i f_i + c_s^2 F / 2: a uniform state with
+    f = f^eq(p, rho, u) - F_i / 2 and only a body force must report
+    sum rho u = N rho u for the chosen u (a velocity without the half-force
+    term misses by N F / 2, here ~10 % of rho u)."""
+    pb = _small(wl.PERIODIC, (3e-3, -2e-3, -4e-3)).with_(rho_ref=1.0)
+    co = _co(pb)
+    shape = (pb.nz, pb.ny, pb.nx)
+    n = pb.nx * pb.ny * pb.nz
+    phi, u0 = 0.3, (0.01, -0.015, -0.02)
+    ph = torch.full(shape, phi, dtype=torch.float64)
+    rho = O.density(ph, co)
+    mu = O.chemical_potential(ph, co)
+    u = tuple(torch.full(shape, a, dtype=torch.float64) for a in u0)
+    zero = torch.zeros(shape, dtype=torch.float64)
+    F = tuple((rho - co.rho_ref) * a for a in (co.gx, co.gy, co.gz))
+    f = torch.stack([O.f_equilibrium(i, zero, rho, u)
+                     - 0.5 * O.f_source(i, u, F, (zero, zero, zero), rho, zero, co)
+                     for i in range(O.Q)])
+    g = torch.stack([O.g_equilibrium(i, ph, mu, u, co) for i in range(O.Q)])
+    m = O.mass(f, g, co)
+    r = float(rho[0, 0, 0])
+    assert m[0] == pytest.approx(n * phi, rel=1e-14)
+    assert m[1] == pytest.approx(n * r, rel=1e-14)
+    for a in range(3):
+        assert m[2 + a] == pytest.approx(n * r * u0[a], rel=1e-12)
+        assert abs(0.5 * n * float(F[a][0, 0, 0])) > 0.05 * abs(m[2 + a])
+
+
+def test_mass_momentum_balance_is_trapezoidal_3d():
+    """Periodic box: the collision adds c_s^2 F to sum_i c_i f_i and
+    streaming permutes populations, so the momentum total of
+    rho u = (j + c_s^2 F / 2) / c_s^2 obeys
+    sum rho u (t+1) - sum rho u (t) = (sum F(t) + sum F(t+1)) / 2 exactly,
+    while F itself changes by ~1e-5 between the levels of a random state."""
+    pb = _small(wl.PERIODIC, (1e-4, 0.0, -2e-4))
+    co = _co(pb)
+    f, g = _random_state(pb, 5)
+    m0, M0 = O.mass(f, g, co), O.macroscopic(f, g, co)
+    f1, g1 = O.step(f, g, co)
+    m1, M1 = O.mass(f1, g1, co), O.macroscopic(f1, g1, co)
+    for a in range(3):
+        F0 = math.fsum(M0["F"][a].reshape(-1).tolist())
+        F1 = math.fsum(M1["F"][a].reshape(-1).tolist())
+        assert abs(F1 - F0) > 3e-6
+        err = (m1[2 + a] - m0[2 + a]) - 0.5 * (F0 + F1)
+        assert abs(err) < 1e-13 * max(abs(m0[2 + a]), 1.0)
+
+
+def test_bulk_free_energy_3d():
+    """psi = beta (phi - phi_A)^2 (phi - phi_B)^2: zero in both phases,
+    beta / 16 at phi = 1/2 (p_0 = -beta / 16 there), derivative equal to the
+    chemical-potential term, and along the tanh profile int 2 psi dz = sigma
+    (equipartition of the interface free energy, Sec. II)."""
+    pb = _small(wl.PERIODIC)
+    co = _co(pb)
+    for ph in (O.PHI_A, O.PHI_B):
+        assert float(O.psi_bulk(torch.tensor(ph, dtype=torch.float64), co)) == 0.0
+    half = torch.tensor(0.5, dtype=torch.float64)
+    assert float(O.psi_bulk(half, co)) == pytest.approx(co.beta / 16, rel=1e-15)
+    assert float(half * O.dpsi_dphi(half, co) - O.psi_bulk(half, co)) == \
+        pytest.approx(-co.beta / 16, rel=1e-15)
+    x = torch.linspace(-0.3, 1.3, 33, dtype=torch.float64).requires_grad_(True)
+    (d,) = torch.autograd.grad(O.psi_bulk(x, co).sum(), x)
+    torch.testing.assert_close(d, O.dpsi_dphi(x.detach(), co), rtol=1e-13, atol=1e-18)
+    z = np.linspace(-5 * pb.W, 5 * pb.W, 8001)
+    phi = 0.5 + 0.5 * np.tanh(2 * z / pb.W)
+    psi = O.psi_bulk(torch.tensor(phi), co).numpy()
+    assert np.trapezoid(2 * psi, z) == pytest.approx(pb.sigma, rel=1e-6)
+
+
 def test_uniform_state_is_fixed_point_3d():
     pb = _small(wl.PERIODIC)
     co = _co(pb)

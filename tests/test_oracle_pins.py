@@ -333,6 +333,98 @@ def test_mass_conserved(bc):
     assert abs(m1[1] - m0[1]) <= 1e-13 * abs(m0[1])
 
 
+def _fsum(t):
+    return math.fsum(t.reshape(-1).tolist())
+
+
+def test_mass_momentum_of_uniform_moving_state():
+    """Sec. III velocity: rho u = sum_i c_i f_i + c_s^2 F / 2. A uniform
+    state whose f is f^eq(p, rho, u) - F_i / 2 (the form the Appendix's
+    first-order moments give, with only a body force acting) must report
+    sum rho u = N rho u for the chosen u; j / c_s^2 alone would be off by
+    N F / 2, j + F by another factor."""
+    nx, ny = 7, 5
+    phi, ux, uy = 0.3, 0.01, -0.02
+    co = O.coefficients(1.0, 0.1, 0.01, 4.0, 0.1, 0.8, 0.9, gx=3e-3, gy=-4e-3,
+                        rho_ref=1.0)
+    ph = torch.full((ny, nx), phi, dtype=torch.float64)
+    rho = O.density(ph, co)
+    mu = O.chemical_potential(ph, co)
+    Ux = torch.full_like(ph, ux)
+    Uy = torch.full_like(ph, uy)
+    zero = torch.zeros_like(ph)
+    Fx, Fy = (rho - co.rho_ref) * co.gx, (rho - co.rho_ref) * co.gy
+    f = torch.stack([O.f_equilibrium(i, zero, rho, Ux, Uy)
+                     - 0.5 * O.f_source(i, Ux, Uy, Fx, Fy, zero, zero, rho, zero, co)
+                     for i in range(9)])
+    g = torch.stack([O.g_equilibrium(i, ph, mu, Ux, Uy, co) for i in range(9)])
+    m = O.mass(f, g, co)
+    r = float(rho[0, 0])
+    assert m[0] == pytest.approx(nx * ny * phi, rel=1e-14)
+    assert m[1] == pytest.approx(nx * ny * r, rel=1e-14)
+    assert m[2] == pytest.approx(nx * ny * r * ux, rel=1e-12)
+    assert m[3] == pytest.approx(nx * ny * r * uy, rel=1e-12)
+    # the force term matters here: it is ~10 % of rho u
+    assert abs(nx * ny * 0.5 * float(Fx[0, 0])) > 0.05 * abs(m[2])
+
+
+@pytest.mark.parametrize("magic", [0.0, 0.25])
+def test_mass_momentum_balance_is_trapezoidal(magic):
+    """Periodic lattice: the f collision adds c_s^2 F to sum_i c_i f_i (the
+    Appendix moments sum c_i f^eq = c_s^2 rho u, sum c_i F_i = c_s^2 F) and
+    streaming permutes populations, so with rho u = (j + c_s^2 F / 2) / c_s^2
+    the lattice momentum obeys
+    sum rho u (t+1) - sum rho u (t) = (sum F(t) + sum F(t+1)) / 2 exactly.
+    A random state makes F change by ~1e-5 between the two levels, so a
+    velocity without (or with twice) the half-force term misses it by that
+    much, far above rounding."""
+    pb = wl.droplet64().with_(nx=20, ny=14, gx=3e-5, gy=-1e-4, rho_ref=0.5)
+    co = O.coefficients_of(pb, trt_magic=magic)
+    f, g = (_t(a) for a in wl.random_state(20, 14, seed=5))
+    with torch.no_grad():
+        m0, M0 = O.mass(f, g, co), O.macroscopic(f, g, co)
+        f1, g1 = O.step(f, g, co)
+        m1, M1 = O.mass(f1, g1, co), O.macroscopic(f1, g1, co)
+    for a, key in enumerate(("Fx", "Fy")):
+        F0, F1 = _fsum(M0[key]), _fsum(M1[key])
+        assert abs(F1 - F0) > 1e-5                  # the check can tell the forms apart
+        err = (m1[2 + a] - m0[2 + a]) - 0.5 * (F0 + F1)
+        assert abs(err) < 1e-15 * max(abs(m0[2 + a]), 1.0) * 20
+
+
+def test_bulk_free_energy():
+    """Sec. II double well psi = beta (phi - phi_A)^2 (phi - phi_B)^2:
+    zero in both bulk phases, psi(1/2) = beta / 16 so the bulk pressure
+    p_0 = phi psi' - psi is -beta / 16 there (psi'(1/2) = 0); psi' is the
+    oracle's chemical-potential term (its autograd derivative); along the
+    tanh profile the free energy splits equally, psi = kappa phi'^2 / 2, so
+    int 2 psi dz is the surface tension sigma; and the full pressure
+    P = p_0 - kappa phi phi'' + kappa phi'^2 / 2 of the exact profile is
+    constant (zero) across the interface (dP/dz = phi dmu/dz = 0)."""
+    for sigma, W in [(0.01, 4.0), (1e-3, 6.0)]:
+        co = O.coefficients(1.0, 0.2, sigma, W, 0.1, 1.0, 1.0)
+        for ph in (O.PHI_A, O.PHI_B):
+            assert float(O.psi_bulk(_t(ph), co)) == 0.0
+        half = _t(0.5)
+        assert float(O.psi_bulk(half, co)) == pytest.approx(co.beta / 16, rel=1e-15)
+        p0 = half * O.dpsi_dphi(half, co) - O.psi_bulk(half, co)
+        assert float(p0) == pytest.approx(-co.beta / 16, rel=1e-15)
+        x = _t(np.linspace(-0.3, 1.3, 33)).requires_grad_(True)
+        (d,) = torch.autograd.grad(O.psi_bulk(x, co).sum(), x)
+        torch.testing.assert_close(d, O.dpsi_dphi(x.detach(), co), rtol=1e-13, atol=1e-18)
+        z = np.linspace(-5 * W, 5 * W, 8001)
+        th = np.tanh(2 * z / W)
+        phi = 0.5 + 0.5 * th
+        d1 = (1 - th ** 2) / W
+        d2 = -4 * th * (1 - th ** 2) / W ** 2
+        psi = O.psi_bulk(_t(phi), co).numpy()
+        assert np.trapezoid(2 * psi, z) == pytest.approx(sigma, rel=1e-6)
+        np.testing.assert_allclose(psi, 0.5 * co.kappa * d1 ** 2, rtol=0, atol=1e-15 * co.beta)
+        P = (phi * O.dpsi_dphi(_t(phi), co).numpy() - psi
+             - co.kappa * phi * d2 + 0.5 * co.kappa * d1 ** 2)
+        assert np.abs(P).max() < 1e-14 * co.beta
+
+
 def test_uniform_state_is_fixed_point():
     pb = wl.droplet64().with_(nx=8, ny=6)
     co = O.coefficients_of(pb)
@@ -588,6 +680,45 @@ def test_gradients_match_central_differences():
         e[yy, xx] = 1e-6
         fd = (Lof(ph=phi0 + e) - Lof(ph=phi0 - e)) / 2e-6
         assert float(dp[yy, xx]) == pytest.approx(fd, rel=1e-5, abs=1e-9)
+
+
+@pytest.mark.parametrize("bc", [O.PERIODIC, O.WALLS_Y])
+def test_step_adjoint_passes_dot_product_test(bc):
+    """Dot-product test of the adjoint: for random tangents v = (df, dg,
+    dsigma, dM) and cotangents w = (fbar, gbar) of one step,
+    <J^T w, v> = <w, J v>, with J v by forward mode (dual numbers) and J^T w
+    by reverse mode -- two independent differentiations of the same map."""
+    pb = wl.droplet64().with_(nx=11, ny=9, bc=bc, gy=-2e-5 * bc, rho_ref=0.5)
+    f, g = wl.random_state(pb.nx, pb.ny, seed=17)
+    rng = np.random.default_rng(3)
+    df, dg, fbar, gbar = (rng.standard_normal((9, pb.ny, pb.nx)) for _ in range(4))
+    dsig, dmob = 0.3 * pb.sigma, -0.2 * pb.M
+    tf, tg = O.step_jvp(f, g, pb, df, dg, dsig, dmob)
+    rf, rg, rs, rm = O.step_vjp(f, g, pb, fbar, gbar)
+    lhs = float((_t(fbar) * tf).sum() + (_t(gbar) * tg).sum())
+    rhs = float((rf * _t(df)).sum() + (rg * _t(dg)).sum()) + rs * dsig + rm * dmob
+    assert lhs == pytest.approx(rhs, rel=1e-12)
+    # each part on its own (a wrong parameter derivative cannot hide behind the rest)
+    tf0, tg0 = O.step_jvp(f, g, pb, 0 * df, 0 * dg, dsig, 0.0)
+    assert float((_t(fbar) * tf0).sum() + (_t(gbar) * tg0).sum()) == pytest.approx(rs * dsig, rel=1e-11)
+    tf0, tg0 = O.step_jvp(f, g, pb, 0 * df, 0 * dg, 0.0, dmob)
+    assert float((_t(fbar) * tf0).sum() + (_t(gbar) * tg0).sum()) == pytest.approx(rm * dmob, rel=1e-11)
+
+
+def test_loss_directional_derivative_matches_reverse_mode():
+    """Over a whole run: dL along (dphi0, dsigma, dM) by forward mode equals
+    the reverse-mode gradient dotted with the same direction."""
+    pb = _tiny_problem()
+    phi0 = _tiny_phi0(pb)
+    target = _t(wl.random_phi(pb.nx, pb.ny, seed=22, lo=0.2, hi=0.8))
+    loss = lambda phi: ((phi - target) ** 2).sum()
+    K = 20
+    _, ds, dm, dp = O.loss_and_gradients(phi0, pb, K, loss)
+    rng = np.random.default_rng(8)
+    v = rng.standard_normal(phi0.shape)
+    dsig, dmob = 0.1 * pb.sigma, 0.1 * pb.M
+    dL = O.loss_jvp(phi0, pb, K, loss, v, dsig, dmob)
+    assert dL == pytest.approx(float((dp * _t(v)).sum()) + ds * dsig + dm * dmob, rel=1e-11)
 
 
 def test_sigma_gradient_matches_complex_step():
