@@ -32,7 +32,8 @@
  *     boundary row into the ghost row).
  *   Memory: every pointer marked _dev is device memory owned by the caller.
  *     The library never allocates or frees device memory; all state lives
- *     in the caller's workspace. The library owns only the host context.
+ *     in the caller's workspace. The library owns only the host context and
+ *     one static device array per GPU (the scratch of lbm_mass_noalloc).
  *   Streams: every call enqueues its work on the context's HIP stream and
  *     returns without synchronising, except lbm_mass, lbm_adjoint_init and
  *     lbm_adjoint_get (host outputs), which synchronise that stream.
@@ -160,6 +161,34 @@ lbm_status lbm_moments(lbm_ctx* ctx, double* phi_dev, double* rho_dev,
  * quasi-incompressible model is conserved exactly by the scheme (Sec. II,
  * local mass conservation), so sum phi and sum rho are invariants. */
 lbm_status lbm_mass(lbm_ctx* ctx, double out[4]);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the four
+ * lbm_mass totals of a raw state, without a context or workspace, and
+ * without allocating anything.
+ * params: the parameters the state was made with (validated as for
+ *   lbm_init; nx * ny must not exceed LBM_MASS_NOALLOC_MAX_NODES, else
+ *   LBM_EINVAL).
+ * state_dev: a raw state in the layout of lbm_save_raw for these parameters
+ *   (lbm_state_bytes bytes, device memory, 256-byte aligned), read only.
+ * out_dev: device memory for 4 doubles (8-byte aligned), written with sum
+ *   phi, sum rho, sum rho ux, sum rho uy -- bit for bit the values lbm_mass
+ *   reports for a context holding that state (same kernels, same order).
+ * stream: a hipStream_t of the current device (NULL = default stream).
+ * Asynchronous: no synchronisation, no host output, no divergence check
+ * (the caller reads out_dev after the stream has run).
+ * Scratch: the kernels keep their intermediate phi and mu fields and block
+ * partials in one static device array of LBM_MASS_NOALLOC_SCRATCH_BYTES
+ * (32 MiB + 64 KiB) per GPU, held from the first call on that GPU until the
+ * process ends and looked up once per GPU. Every call on a GPU uses that
+ * GPU's one array, whichever thread or stream makes it: calls whose work
+ * overlaps on one GPU (concurrent streams, threads) race and give wrong
+ * totals; serialise them. The array keeps the last call's contents, and
+ * every call overwrites all of what it reads before reading it. */
+#define LBM_MASS_NOALLOC_MAX_NODES (1 << 21)
+#define LBM_MASS_NOALLOC_SCRATCH_BYTES (((size_t)2 << 24) + 65536)
+lbm_status lbm_mass_noalloc(const lbm_params* params, const void* state_dev, double* out_dev,
+                            void* stream);
 
 /* Current pre-collision populations in canonical FP64 layout,
  * f_dev and g_dev each [9][ny][nx] (device), exactly as stored (binary32 f,
@@ -310,7 +339,7 @@ const char* lbm_strerror(lbm_status status);
  * structs would be read past their end). lbm_abi_version returns the value
  * the library was built with. Host only: needs no GPU, enqueues nothing,
  * may be called before any other function. */
-#define QILBM_ABI_VERSION 1
+#define QILBM_ABI_VERSION 2
 int32_t lbm_abi_version(void);
 
 #ifdef __cplusplus

@@ -9,7 +9,7 @@ from ctypes import POINTER, c_double, c_int32, c_int64, c_size_t, c_uint32, c_vo
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libqilbm.so")
 # QILBM_ABI_VERSION of include/qilbm.h that SIGNATURES and the structs below follow
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 LBM_OK, LBM_EINVAL, LBM_ENOMEM, LBM_EDEVICE, LBM_EDIVERGED, LBM_ESTATE = 0, -1, -2, -3, -4, -5
 LBM_FP64, LBM_FP32, LBM_FP16_STORE = 0, 1, 2
@@ -52,6 +52,7 @@ SIGNATURES = {
     "lbm_step_record": (c_int32, [c_void_p, c_void_p]),
     "lbm_moments": (c_int32, [c_void_p] + [c_void_p] * 6),
     "lbm_mass": (c_int32, [c_void_p, _D]),
+    "lbm_mass_noalloc": (c_int32, [_P, c_void_p, c_void_p, c_void_p]),
     "lbm_get_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "lbm_set_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
     "lbm_state_bytes": (c_size_t, [c_void_p]),

@@ -2,6 +2,7 @@
 // Host code only: argument validation, derivation of the model coefficients,
 // workspace layout, and dispatch of the kernels on the context's stream.
 #include <math.h>
+#include <mutex>
 #include <new>
 #include <string.h>
 
@@ -108,29 +109,36 @@ Layout layout(const lbm_params* p) {
   return L;
 }
 
+// Kernel coefficients in the compute type from the parameters and their
+// derived coefficients d[6] (derive()).
 template <typename T>
-Coef<T> coef_t(const lbm_ctx* c) {
+Coef<T> coef_of(const lbm_params& p, const double d[6]) {
   Coef<T> k;
-  k.beta4 = T(4.0 * c->beta);
-  k.kappa = T(c->kappa);
-  k.lam = T(c->lam);
-  k.alpha = T(c->alpha);
-  k.gamma = T(c->gamma);
-  k.drho = T(c->drho);
-  k.rho_B = T(c->prm.rho_B);
-  k.rho_ref = T(c->prm.rho_ref);
-  k.gx = T(c->prm.gx);
-  k.gy = T(c->prm.gy);
-  k.inv_tau_f = T(1.0 / c->prm.tau_f);
-  k.inv_tau_g = T(1.0 / c->prm.tau_g);
-  k.kf = T(1.0 - 0.5 / c->prm.tau_f);
-  k.kg = T(1.0 - 0.5 / c->prm.tau_g);
+  k.beta4 = T(4.0 * d[0]);
+  k.kappa = T(d[1]);
+  k.lam = T(d[2]);
+  k.alpha = T(d[3]);
+  k.gamma = T(d[4]);
+  k.drho = T(d[5]);
+  k.rho_B = T(p.rho_B);
+  k.rho_ref = T(p.rho_ref);
+  k.gx = T(p.gx);
+  k.gy = T(p.gy);
+  k.inv_tau_f = T(1.0 / p.tau_f);
+  k.inv_tau_g = T(1.0 / p.tau_g);
+  k.kf = T(1.0 - 0.5 / p.tau_f);
+  k.kg = T(1.0 - 0.5 / p.tau_g);
   // odd part of the TRT collision: tau_- = 1/2 + magic / (tau_f - 1/2)
-  const double tau_m =
-      c->prm.trt_magic > 0.0 ? 0.5 + c->prm.trt_magic / (c->prm.tau_f - 0.5) : c->prm.tau_f;
+  const double tau_m = p.trt_magic > 0.0 ? 0.5 + p.trt_magic / (p.tau_f - 0.5) : p.tau_f;
   k.inv_tau_m = T(1.0 / tau_m);
   k.km = T(1.0 - 0.5 / tau_m);
   return k;
+}
+
+template <typename T>
+Coef<T> coef_t(const lbm_ctx* c) {
+  const double d[6] = {c->beta, c->kappa, c->lam, c->alpha, c->gamma, c->drho};
+  return coef_of<T>(c->prm, d);
 }
 
 bool trt_of(const lbm_ctx* c) { return c->prm.trt_magic > 0.0; }
@@ -201,6 +209,59 @@ lbm_status mass_p(lbm_ctx* c) {
   using T = typename PrecT<P>::T;
   return st(launch_mass<P>(c->pop[c->cur], phi_f(c), mu_f(c), c->part, c->nred, c->red_out,
                            coef_t<T>(c), coef_t<double>(c), c->geom, c->stream));
+}
+
+// ------------------------------------------- totals without any allocation
+// lbm_mass_noalloc runs lbm_mass's kernels on a caller's raw state with their
+// scratch -- the phi and mu fields and the per-block partials -- in a static
+// device array instead of a context workspace.
+constexpr int64_t NOALLOC_MAX_NODES = int64_t(1) << 21;
+constexpr size_t NOALLOC_FIELD_BYTES = size_t(NOALLOC_MAX_NODES) * 8;
+constexpr int NOALLOC_MAX_PARTS = 2048;   // the workspace layout's cap of nred
+constexpr size_t NOALLOC_BYTES = 2 * NOALLOC_FIELD_BYTES + size_t(NOALLOC_MAX_PARTS) * 4 * 8;
+
+}  // namespace
+
+// One copy per GPU for the life of the process. Host code never passes this
+// name to a kernel: it is a host-side stand-in, not the device address; the
+// address comes from hipGetSymbolAddress, per device (noalloc_scratch).
+static __device__ __align__(256) char scratch[NOALLOC_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+std::mutex g_noalloc_mu;
+char* g_noalloc_ptr[NOALLOC_MAX_DEVICES];   // device address of scratch, per device
+
+// Device address of the current device's copy of scratch, looked up once per
+// device with that device current.
+lbm_status noalloc_scratch(char** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return LBM_EDEVICE;
+  if (dev < 0 || dev >= NOALLOC_MAX_DEVICES) return LBM_EDEVICE;
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* ptr = nullptr;
+    if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return LBM_EDEVICE;
+    g_noalloc_ptr[dev] = (char*)ptr;
+  }
+  *out = g_noalloc_ptr[dev];
+  return LBM_OK;
+}
+
+template <int P>
+hipError_t mass_noalloc_p(const lbm_params& p, const void* state, double* out, char* sc,
+                          hipStream_t s) {
+  using T = typename PrecT<P>::T;
+  double d[6];
+  derive(&p, d);
+  const Geom g = make_geom(&p);
+  // same partial count as a context's workspace (layout()), so the totals
+  // are those of lbm_mass bit for bit
+  int nred = (int)((g.N + 255) / 256);
+  if (nred > NOALLOC_MAX_PARTS) nred = NOALLOC_MAX_PARTS;
+  return launch_mass<P>(state, sc, sc + NOALLOC_FIELD_BYTES, (double*)(sc + 2 * NOALLOC_FIELD_BYTES),
+                        nred, out, coef_of<T>(p, d), coef_of<double>(p, d), g, s);
 }
 
 }  // namespace
@@ -327,6 +388,18 @@ lbm_status lbm_mass(lbm_ctx* c, double out[4]) {
   for (int k = 0; k < 4; ++k)
     if (!isfinite(out[k])) return LBM_EDIVERGED;
   return LBM_OK;
+}
+
+lbm_status lbm_mass_noalloc(const lbm_params* params, const void* state_dev, double* out_dev,
+                            void* stream) {
+  if (!valid(params) || !state_dev || !out_dev) return LBM_EINVAL;
+  if ((uintptr_t)state_dev % ALIGN != 0 || (uintptr_t)out_dev % 8 != 0) return LBM_EINVAL;
+  if ((int64_t)params->nx * params->ny > NOALLOC_MAX_NODES) return LBM_EINVAL;
+  char* sc = nullptr;
+  lbm_status s = noalloc_scratch(&sc);
+  if (s != LBM_OK) return s;
+  return st(QILBM_DISPATCH(params->precision, mass_noalloc_p, *params, state_dev, out_dev, sc,
+                           (hipStream_t)stream));
 }
 
 lbm_status lbm_get_state(lbm_ctx* c, double* f, double* g) {

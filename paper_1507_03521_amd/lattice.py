@@ -15,6 +15,24 @@ def _ptr(t: torch.Tensor) -> int:
     return t.data_ptr()
 
 
+MASS_NOALLOC_MAX_NODES = 1 << 21
+
+
+def mass_noalloc(params: dict, precision: str, state: torch.Tensor, out: torch.Tensor,
+                 flags: int = 0, stream: torch.cuda.Stream | None = None) -> None:
+    """lbm_mass_noalloc: the four totals of a raw state (``Lattice.save_raw``
+    layout, device uint8 tensor) into ``out`` (device float64 tensor of 4),
+    asynchronously on ``stream``, with no context and no allocation (the
+    kernels' scratch is the library's static device array)."""
+    lib = _lib.load()
+    prm = _lib.make_params(params, precision, flags)
+    assert state.is_cuda and state.is_contiguous()
+    assert out.is_cuda and out.dtype == torch.float64 and out.numel() >= 4
+    stream = stream or torch.cuda.current_stream(state.device)
+    _lib.check(lib.lbm_mass_noalloc(byref(prm), _ptr(state), _ptr(out),
+                                    c_void_p(stream.cuda_stream)), "lbm_mass_noalloc")
+
+
 class Lattice:
     """A D2Q9 lattice of the quasi-incompressible phase-field LBE on one GPU.
 
