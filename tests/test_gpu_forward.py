@@ -7,8 +7,13 @@ FP64: 1e-12 for one step (measured ~5e-13 for f, ~1e-15 for g). f is small
 a difference of two ~1e-2 terms that nearly cancel at an equilibrium
 interface; each side rounds it in its own order. Over many steps that
 difference accumulates in f only (measured on the 64x64 droplet: 1.0e-12 at
-step 1000, 8.5e-12 at step 2000, while g, phi and the totals stay at
-~1e-15), so multi-step runs bound f by 2e-11 and g by 1e-12.
+step 1000, 8.5e-12 .. 1.0e-11 at step 2000, while g, phi and the totals stay
+at ~1e-15). That is the FP64 noise floor of the problem, not a defect of
+either side: the oracle against itself with its stencil sums taken in
+reverse direction order differs by 8.7e-12 at step 2000, and by 9.0e-12
+when phi0 moves by one ulp (test_oracle_pins), and a build without
+multiply-add contraction changes nothing (9.5e-12). Multi-step runs bound f
+by 2e-11 and g by 1e-12.
 
 FP32: storing g_0 ~ phi in binary32 perturbs phi by ~3e-8 and mu by
 ~kappa (10/3) 3e-8 ~ 1e-8. From a random state (mu ~ 1e-3) that bounds f to
