@@ -8,11 +8,15 @@ streaming). FP64 and FP32 run two steps per launch of the fused kernel
 (the state between them stays on chip); FP16 storage one step per launch.
 
 Printed: ONE JSON line. ``value`` is the FP32 rate in MLUPS (million lattice
-updates per second); the line also carries the FP64 and FP16-storage rates
-with their deviation from the FP64 GPU run, the adjoint/forward step-time
-ratio, the roofline position of the fused kernel, the CPU-oracle rate, the
-rate with the two-relaxation-time collision variant and the
-three-dimensional (D3Q19, 256^3 box) step's rates.
+updates per second), the median of five timed windows of ``--steps`` steps;
+the line also carries the FP64 and FP16-storage rates, the adjoint/forward
+step-time ratio, the roofline position of the fused kernel, the 4096 x 8192
+rising bubble's FP32 rate and its gradient cost with checkpoint-and-recompute,
+the stated error of FP32 and FP16 storage against FP64 (tip positions and
+phi on the 256 x 1024 Rayleigh-Taylor problem over 10 000 steps), the
+CPU-oracle rates (host model and core count stated), the rate with the
+two-relaxation-time collision variant and the three-dimensional (D3Q19,
+256^3 box) step's rates.
 """
 from __future__ import annotations
 
@@ -48,17 +52,33 @@ def source_digest() -> str:
     return h.hexdigest()[:16]
 
 
-def timed_steps(lat, steps: int, warmup: int):
+REPEATS = 5
+
+
+def timed_runs(lat, steps: int, warmup: int, repeats: int = REPEATS):
+    """``warmup`` untimed steps, then ``repeats`` timed windows of exactly
+    ``steps`` steps, each bracketed by device synchronisations and timed with
+    HIP events on the lattice's stream: ms per step of each window."""
     import torch
     lat.step(warmup)
     torch.cuda.synchronize()
     start = torch.cuda.Event(enable_timing=True)
     stop = torch.cuda.Event(enable_timing=True)
-    start.record(lat.stream)
-    lat.step(steps)
-    stop.record(lat.stream)
-    torch.cuda.synchronize()
-    return start.elapsed_time(stop) / steps          # ms per step
+    runs = []
+    for _ in range(repeats):
+        torch.cuda.synchronize()
+        start.record(lat.stream)
+        lat.step(steps)
+        stop.record(lat.stream)
+        torch.cuda.synchronize()
+        runs.append(start.elapsed_time(stop) / steps)
+    return runs
+
+
+def timed_steps(lat, steps: int, warmup: int):
+    """Median ms per step over the timed windows of :func:`timed_runs`."""
+    import statistics
+    return statistics.median(timed_runs(lat, steps, warmup))
 
 
 def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
@@ -69,12 +89,11 @@ def run_precision(pb, phi0, precision, steps, warmup, seg_rows, pass_steps):
     if seg_rows and lat.pass_info()["steps"] == 1:
         lat.set_launch(seg_rows)
     m0 = lat.mass()
-    ms = timed_steps(lat, steps, warmup)
+    runs = timed_runs(lat, steps, warmup)
     m1 = lat.mass()
-    phi = lat.moments(("phi",))["phi"]
     info = lat.pass_info()
     del lat
-    return ms, phi, m0, m1, info
+    return runs, m0, m1, info
 
 
 def copy_gbps(reps: int = 10) -> float:
@@ -220,41 +239,99 @@ def traffic_from_profile(pass_steps):
         return None
 
 
-def _oracle_rate(pb, phi0, rows: int, steps: int):
+def _cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    import platform
+    return platform.processor() or "unknown"
+
+
+def _oracle_crop_rate(pb, phi0, rows: int, target_s: float, threads: int):
+    """Oracle rate (MLUPS) on the middle ``rows`` rows of the lattice (all
+    columns, walls), with ``threads`` torch threads; steps chosen so that the
+    timed part takes about ``target_s`` seconds (at least 2)."""
     import torch
     from oracle import qilbm_oracle as O
-    y0 = pb.ny // 2 - rows // 2
-    sub = pb.with_(ny=rows)
-    crop = phi0[y0:y0 + rows]
-    co = O.coefficients_of(sub)
-    with torch.no_grad():
-        f, g = O.initial_state(crop, co)
-        f, g = O.step(f, g, co)               # first touch outside the timing
-        t0 = time.perf_counter()
-        for _ in range(steps):
-            f, g = O.step(f, g, co)
-        dt = time.perf_counter() - t0
-    return sub.nx * rows * steps / dt / 1e6, dt
-
-
-def cpu_baseline(pb, phi0, rows: int, steps: int):
-    """The oracle as it stands, on a crop of the same workload (all columns,
-    the middle ``rows`` rows between walls), FP64, timed on the host with all
-    torch threads, and on a smaller crop with one thread."""
-    import torch
-    cores = torch.get_num_threads()
-    rate, dt = _oracle_rate(pb, phi0, rows, steps)
-    torch.set_num_threads(1)
+    saved = torch.get_num_threads()
+    torch.set_num_threads(threads)
     try:
-        rate1, dt1 = _oracle_rate(pb, phi0, max(rows // 8, 8), 2)
+        y0 = pb.ny // 2 - rows // 2
+        sub = pb.with_(ny=rows)
+        co = O.coefficients_of(sub)
+        with torch.no_grad():
+            f, g = O.initial_state(phi0[y0:y0 + rows], co)
+            t0 = time.perf_counter()
+            f, g = O.step(f, g, co)               # first touch, also sizes the run
+            one = time.perf_counter() - t0
+            steps = max(2, min(50, int(target_s / max(one, 1e-6))))
+            t0 = time.perf_counter()
+            for _ in range(steps):
+                f, g = O.step(f, g, co)
+            dt = time.perf_counter() - t0
+        return dict(value=round(sub.nx * rows * steps / dt / 1e6, 4), unit="MLUPS",
+                    cores=torch.get_num_threads(), steps=steps, seconds=round(dt, 2))
     finally:
-        torch.set_num_threads(cores)
-    return dict(value=round(rate, 4), unit="MLUPS", cores=cores, kind="oracle",
-                sample=f"{steps} FP64 steps of a {pb.nx}x{rows} crop (middle rows, walls) "
-                       f"of the {pb.nx}x{pb.ny} Rayleigh-Taylor lattice, {dt:.1f} s",
-                single_thread=dict(value=round(rate1, 4), unit="MLUPS", cores=1,
-                                   sample=f"2 FP64 steps of a {pb.nx}x{max(rows // 8, 8)} crop, "
-                                          f"{dt1:.1f} s"))
+        torch.set_num_threads(saved)
+
+
+def _oracle_droplet_run(threads: int, repeats: int = 3):
+    """The 64x64 static droplet's full 2000-step run by the oracle; median
+    wall time of up to ``repeats`` runs (one more run only while a run takes
+    under 15 s)."""
+    import statistics
+    import torch
+    import workloads as wl
+    from oracle import qilbm_oracle as O
+    pb = wl.droplet64()
+    co = O.coefficients_of(pb)
+    saved = torch.get_num_threads()
+    torch.set_num_threads(threads)
+    times = []
+    try:
+        for _ in range(repeats):
+            t0 = time.perf_counter()
+            with torch.no_grad():
+                O.run(wl.phi0(pb), co, pb.steps)
+            times.append(time.perf_counter() - t0)
+            if times[-1] > 15.0:
+                break
+    finally:
+        torch.set_num_threads(saved)
+    med = statistics.median(times)
+    return dict(value=round(pb.nx * pb.ny * pb.steps / med / 1e6, 4), unit="MLUPS",
+                cores=threads, seconds=[round(t, 2) for t in times])
+
+
+def cpu_baseline(pb, phi0, rows: int, target_s: float):
+    """The oracle as it stands (plain PyTorch-CPU FP64, never tuned) on the
+    host: the headline rate on a crop of the same workload (all columns, the
+    middle ``rows`` rows between walls) with all the threads torch uses, the
+    same crop with one thread, and the 64x64 droplet's full 2000-step run
+    with one thread and all threads. Small lattices gain nothing from
+    threads (each operation on 4096 nodes is shorter than a thread hand-off),
+    so the crop is what shows the host's throughput."""
+    import torch
+    threads = torch.get_num_threads()
+    allc = _oracle_crop_rate(pb, phi0, rows, target_s, threads)
+    one = _oracle_crop_rate(pb, phi0, rows, target_s / 2, 1)
+    c0 = {"all_threads": _oracle_droplet_run(threads), "single_thread": _oracle_droplet_run(1)}
+    try:
+        affinity = len(os.sched_getaffinity(0))
+    except AttributeError:
+        affinity = None
+    return dict(value=allc["value"], unit="MLUPS", cores=allc["cores"], kind="oracle",
+                sample=f"{allc['steps']} FP64 steps of a {pb.nx}x{rows} crop (middle rows, "
+                       f"walls) of the {pb.nx}x{pb.ny} Rayleigh-Taylor lattice, "
+                       f"{allc['seconds']} s",
+                cpu_model=_cpu_model(), host_cpus=os.cpu_count(), affinity_cpus=affinity,
+                single_thread=dict(one, sample=f"{one['steps']} FP64 steps of the same crop"),
+                droplet64_full_run=dict(c0, workload="64x64 static droplet, 2000 FP64 steps "
+                                                     "(median of up to 3 runs)"))
 
 
 def _crossings(col):
@@ -377,6 +454,117 @@ def precision_study(pb, phi0, steps: int, every: int):
                 t_star=round(steps * t_unit, 4), **out)
 
 
+def exact_phi(lat):
+    """phi = sum_i g_i from the stored populations, read back exactly in
+    binary64 (not the compute type's moment)."""
+    return lat.get_state()[1].sum(0)
+
+
+def precision_window(steps: int, every: int):
+    """The stated error of the reduced-precision runs on the 256 x 1024
+    Rayleigh-Taylor problem (Re 3000, Pe 1000, walls): FP32 and FP16 storage
+    against the FP64 GPU run (which test_gpu_physics compares with the
+    oracle), from the same initial interface for ``steps`` steps: the
+    largest deviation of the spike and bubble tips sampled every ``every``
+    steps, the largest |phi - phi_FP64| at the end (phi summed exactly from
+    the stored g) and the mass drift."""
+    import torch
+    import workloads as wl
+    from paper_1507_03521_amd import Lattice
+    pb = wl.rt256()
+    phi0 = wl.phi0(pb)
+    t_unit = math.sqrt(abs(pb.gy) / pb.nx)
+    out, ref = {}, None
+    for prec in ("fp64", "fp32", "fp16"):
+        lat = Lattice(pb.as_dict(), phi0, precision=prec, device="cuda:0")
+        m0 = lat.mass()
+        tips, done = [], 0
+        while done < steps:
+            n = min(every, steps - done)
+            lat.step(n)
+            done += n
+            tips.append(interface_tips(exact_phi(lat), pb.nx))
+        m1 = lat.mass()
+        phi = exact_phi(lat)
+        r = dict(mass_drift_rel=abs(m1[1] - m0[1]) / abs(m0[1]),
+                 spike_tip=round(tips[-1][0], 4), bubble_tip=round(tips[-1][1], 4))
+        if ref is None:
+            ref = (phi, tips)
+        else:
+            r["tip_max_abs_dev_vs_fp64"] = round(max(
+                max(abs(a[0] - b[0]), abs(a[1] - b[1])) for a, b in zip(tips, ref[1])), 5)
+            r["phi_max_abs_dev_vs_fp64"] = float((phi - ref[0]).abs().max())
+        out[prec] = r
+        del lat
+        torch.cuda.empty_cache()
+        log(f"  {prec}: {r}")
+    return dict(workload="rt256: Rayleigh-Taylor 256x1024, walls in y, Atwood 0.5, Re 3000, "
+                         "Pe 1000, W 4", steps=steps, t_star=round(steps * t_unit, 4),
+                tips_every=every, initial_tips=(wl.rt256().meta["h0"] - wl.rt256().meta["amp"],
+                                                wl.rt256().meta["h0"] + wl.rt256().meta["amp"]),
+                **out)
+
+
+def bubble_leg(steps: int, warmup: int, window: int, C: int):
+    """The 4096 x 8192 rising bubble in FP32: the forward rate (two steps per
+    launch), and the gradient's cost by checkpoint-and-recompute over a
+    ``window`` of steps with a raw checkpoint every ``C`` steps (replay of
+    each segment with step records, then the adjoint steps in reverse) over
+    the forward window with its checkpoints."""
+    import statistics
+    import torch
+    import workloads as wl
+    from paper_1507_03521_amd import Lattice
+    pb = wl.bubble4096()
+    N = pb.nx * pb.ny
+    lat = Lattice(pb.as_dict(), wl.phi0(pb), precision="fp32", device="cuda:0")
+    runs = timed_runs(lat, steps, warmup)
+    ms = statistics.median(runs)
+    info = lat.pass_info()
+    y = torch.arange(pb.ny, device="cuda:0", dtype=torch.float64)[:, None].expand(pb.ny, pb.nx)
+    records = [torch.empty(lat.record_bytes, dtype=torch.uint8, device="cuda:0")
+               for _ in range(C)]
+    snaps = [torch.empty(lat.state_bytes, dtype=torch.uint8, device="cuda:0")
+             for _ in range(-(-window // C))]
+    lat.adjoint_begin((-y).contiguous())
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    fwd, bwd = [], []
+    for _ in range(REPEATS):
+        t = lat.time
+        torch.cuda.synchronize()
+        ev0.record(lat.stream)
+        for k in range(len(snaps)):
+            lat.save_raw(snaps[k])
+            lat.step(min(C, window - k * C))
+        ev1.record(lat.stream)
+        torch.cuda.synchronize()
+        fwd.append(ev0.elapsed_time(ev1))
+        lat.adjoint_seed((-y).contiguous())
+        torch.cuda.synchronize()
+        ev0.record(lat.stream)
+        for k in reversed(range(len(snaps))):
+            n = min(C, window - k * C)
+            lat.load_raw(snaps[k], t + k * C)
+            lat.step_records(records[:n])
+            for j in reversed(range(n)):
+                lat.adjoint_step_record(records[j])
+        ev1.record(lat.stream)
+        torch.cuda.synchronize()
+        bwd.append(ev0.elapsed_time(ev1))
+    fwd_ms, bwd_ms = statistics.median(fwd), statistics.median(bwd)
+    del records, snaps, lat
+    torch.cuda.empty_cache()
+    return dict(workload="bubble4096: rising bubble 4096x8192, walls in y, R 256, Eo 10, "
+                         "Mo 1e-3, W 5", precision="fp32",
+                mlups=round(N / ms / 1e3, 2), ms_per_step=round(ms, 5),
+                ms_per_step_runs=[round(r, 5) for r in runs], launch=info,
+                hbm_roofline_frac=round(BYTES_PER_LU["fp32"] * N / (ms * 1e-3) / 1e9
+                                        / PEAK_HBM_GBS, 4),
+                adjoint=dict(window=window, checkpoint=C, forward_window_ms=round(fwd_ms, 3),
+                             backward_ms=round(bwd_ms, 3),
+                             ratio_with_recompute=round(bwd_ms / fwd_ms, 3)))
+
+
 def adjoint_study(warm: int, window: int, C: int, precision: str = "fp64", h: float = 1e-6):
     """The 4096 x 8192 rising-bubble problem: ``warm`` forward steps, then
     the gradient of L = sum_x y (1 - phi_K) (the bubble's height moment)
@@ -481,8 +669,17 @@ def main():
     ap.add_argument("--steps-3d", type=int, default=200)
     ap.add_argument("--no-trt", action="store_true",
                     help="skip the two-relaxation-time (FP32) leg")
-    ap.add_argument("--cpu-rows", type=int, default=2048)
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-rows", type=int, default=512,
+                    help="rows of the crop of the workload that the CPU oracle steps")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0,
+                    help="about how long the oracle's all-thread crop run takes")
+    ap.add_argument("--no-bubble", action="store_true",
+                    help="skip the 4096x8192 rising-bubble leg (rate and adjoint cost)")
+    ap.add_argument("--bubble-window", type=int, nargs=2, default=(32, 16),
+                    metavar=("WINDOW", "C"))
+    ap.add_argument("--no-precision-window", action="store_true",
+                    help="skip the FP32/FP16-vs-FP64 error run on the 256x1024 lattice")
+    ap.add_argument("--window-steps", type=int, default=10000)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a 1 GiB device copy (PMC byte-counter calibration)")
     ap.add_argument("--precision-study", type=int, default=0, metavar="STEPS",
@@ -535,24 +732,24 @@ def main():
     log(f"device copy: {achievable:.0f} GB/s")
     precisions = [args.only] if args.only else ["fp32", "fp64", "fp16"]
     res = {}
+    import statistics
     for prec in precisions:
-        log(f"timing {prec}: {args.steps} steps after {args.warmup} warm-up")
-        ms, phi, m0, m1, info = run_precision(pb, phi0, prec, args.steps, args.warmup,
-                                              args.seg_rows,
-                                              args.pass_steps)
-        res[prec] = dict(ms=ms, phi=phi, m0=m0, m1=m1, info=info)
-        log(f"  {prec}: {ms:.4f} ms/step, {N / ms / 1e3:.1f} MLUPS, launch {info}")
+        log(f"timing {prec}: {REPEATS} x {args.steps} steps after {args.warmup} warm-up")
+        runs, m0, m1, info = run_precision(pb, phi0, prec, args.steps, args.warmup,
+                                           args.seg_rows, args.pass_steps)
+        ms = statistics.median(runs)
+        res[prec] = dict(ms=ms, runs=runs, m0=m0, m1=m1, info=info)
+        log(f"  {prec}: {ms:.4f} ms/step (median; runs {[round(r, 4) for r in runs]}), "
+            f"{N / ms / 1e3:.1f} MLUPS, launch {info}")
 
     def entry(prec):
         r = res[prec]
-        out = dict(mlups=round(N / r["ms"] / 1e3, 2), ms_per_step=round(r["ms"], 5),
-                   steps_per_launch=r["info"]["steps"],
-                   hbm_roofline_frac=round(BYTES_PER_LU[prec] * N / (r["ms"] * 1e-3) / 1e9
-                                           / PEAK_HBM_GBS, 4),
-                   mass_drift_rel=abs(r["m1"][1] - r["m0"][1]) / abs(r["m0"][1]))
-        if "fp64" in res and prec != "fp64":
-            out["phi_max_abs_dev_vs_fp64"] = float((r["phi"] - res["fp64"]["phi"]).abs().max())
-        return out
+        return dict(mlups=round(N / r["ms"] / 1e3, 2), ms_per_step=round(r["ms"], 5),
+                    ms_per_step_runs=[round(x, 5) for x in r["runs"]],
+                    steps_per_launch=r["info"]["steps"],
+                    hbm_roofline_frac=round(BYTES_PER_LU[prec] * N / (r["ms"] * 1e-3) / 1e9
+                                            / PEAK_HBM_GBS, 4),
+                    mass_drift_rel=abs(r["m1"][1] - r["m0"][1]) / abs(r["m0"][1]))
 
     main_prec = args.only or "fp32"
     ms = res[main_prec]["ms"]
@@ -600,12 +797,19 @@ def main():
     if not args.no_trt:
         log("timing the two-relaxation-time collision variant")
         line["trt"] = run_trt(pb, phi0, 200, 20)
+    if not args.no_bubble and not args.only:
+        log("timing the 4096x8192 rising bubble (FP32 rate, adjoint with checkpoints)")
+        line["bubble4096"] = bubble_leg(args.steps, args.warmup, *args.bubble_window)
+    if not args.no_precision_window and not args.only:
+        log(f"reduced-precision error window: 256x1024, {args.window_steps} steps")
+        line["precision_error"] = precision_window(args.window_steps,
+                                                   max(1, args.window_steps // 10))
     if not args.no_3d:
         log("timing the three-dimensional step")
         line["d3q19"] = run_3d(args.steps_3d, max(1, args.steps_3d // 10))
     if not args.no_cpu_baseline:
         log("timing CPU oracle sample")
-        line["cpu_baseline"] = cpu_baseline(pb, phi0, args.cpu_rows, args.cpu_steps)
+        line["cpu_baseline"] = cpu_baseline(pb, phi0, args.cpu_rows, args.cpu_seconds)
     print(json.dumps(line), flush=True)
 
 
