@@ -365,36 +365,147 @@ __device__ __forceinline__ void macro_node(T phi, T mu, T gphx, T gphy, T gmux, 
   m.p = S + T(1.0 / 6.0) * (m.ux * m.drx + m.uy * m.dry - c.gamma * m.rho * m.D);
 }
 
+// Fused multiply-add in the compute type.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+// c.(x, y) for the direction (CX, CY) known at compile time: signs and
+// sums only (a product with a zero component is not folded away in IEEE
+// arithmetic, so the generic form would multiply).
+template <int CX, int CY, typename T>
+__device__ __forceinline__ T cdot(T x, T y) {
+  static_assert(CX != 0 || CY != 0, "rest direction");
+  if constexpr (CX == 0) return CY > 0 ? y : -y;
+  else if constexpr (CY == 0) return CX > 0 ? x : -x;
+  else if constexpr (CX > 0) return CY > 0 ? x + y : x - y;
+  else return CY > 0 ? y - x : -(x + y);
+}
+
+// What every direction of one node's collision shares.
+template <typename T>
+struct CollNode {
+  T ux, uy, usq15;     // u and 1.5 |u|^2
+  T Fx, Fy, uF;        // F and u.F
+  T dx, dy, ud;        // grad rho / 3 and u.(grad rho / 3)
+  T qx, qy, uq;        // grad p - F and u.(grad p - F)
+};
+
+template <typename T>
+__device__ __forceinline__ CollNode<T> coll_node(const Macro<T>& m, T dpx, T dpy) {
+  CollNode<T> n;
+  n.ux = m.ux;
+  n.uy = m.uy;
+  n.usq15 = T(1.5) * fmad(m.uy, m.uy, m.ux * m.ux);
+  n.Fx = m.Fx;
+  n.Fy = m.Fy;
+  n.uF = fmad(m.uy, m.Fy, m.ux * m.Fx);
+  n.dx = m.drx * T(1.0 / 3.0);
+  n.dy = m.dry * T(1.0 / 3.0);
+  n.ud = fmad(m.uy, n.dy, m.ux * n.dx);
+  n.qx = dpx - m.Fx;
+  n.qy = dpy - m.Fy;
+  n.uq = fmad(m.uy, n.qy, m.ux * n.qx);
+  return n;
+}
+
+// Direction I of the Sec. III algebra: s = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2,
+// X = (c - u).(Gamma F + s grad rho / 3) and Y = Gamma (c - u).(grad p - F)
+// with Gamma = 1 + s, i.e. with A = (c-u).F, B = (c-u).grad rho / 3,
+// Q = (c-u).(grad p - F): X = A + s (A + B), Y = Q + s Q.
+template <int I, typename T>
+__device__ __forceinline__ void coll_dir(const CollNode<T>& n, T& s, T& X, T& Y) {
+  T A, B, Q;
+  if constexpr (I == 0) {
+    s = -n.usq15;
+    A = -n.uF;
+    B = -n.ud;
+    Q = -n.uq;
+  } else {
+    constexpr int cx = CXS(I), cy = CYS(I);
+    const T cu = cdot<cx, cy>(n.ux, n.uy);
+    s = fmad(cu, fmad(T(4.5), cu, T(3)), -n.usq15);
+    A = cdot<cx, cy>(n.Fx, n.Fy) - n.uF;
+    B = cdot<cx, cy>(n.dx, n.dy) - n.ud;
+    Q = cdot<cx, cy>(n.qx, n.qy) - n.uq;
+  }
+  X = fmad(s, A + B, A);
+  Y = fmad(s, Q, Q);
+}
+
+// Per-node factors of the relaxation for one weight class j (rest, axis,
+// diagonal; w_j = 4/9, 1/9, 1/36):
+//   f* = (1 - 1/tau_f) f + w [p/tau_f + kf src1] + w rho/(3 tau_f) s + w kf X
+//   g* = (1 - 1/tau_g) g + H/tau_g + w phi/tau_g s + w kg K Y
+// with src1 = -rho gamma D / 3, K = -3 phi / rho, kf, kg = 1 - 1/(2 tau),
+// H_0 = phi - (1 - w_0) alpha mu, H_j = w_j alpha mu (j > 0). They are
+// formed just before the class's directions, so only one class's are live.
+template <typename T>
+struct CollNodeF {
+  T pf, rf, amu, ph, K;    // p/tau_f + kf src1, rho/(3 tau_f), alpha mu, phi/tau_g, K
+  T phi;
+};
+
+template <typename T>
+__device__ __forceinline__ CollNodeF<T> coll_nodef(const Macro<T>& m, const Coef<T>& c) {
+  CollNodeF<T> q;
+  q.pf = fmad(m.p, c.inv_tau_f, -(m.rho * m.D) * (c.kf * c.gamma * T(1.0 / 3.0)));
+  q.rf = m.rho * (c.inv_tau_f * T(1.0 / 3.0));
+  q.amu = c.alpha * m.mu;
+  q.ph = m.phi * c.inv_tau_g;
+  q.K = -T(3) * m.phi * recip(m.rho);
+  q.phi = m.phi;
+  return q;
+}
+
+template <typename T>
+struct CollClass {
+  T f0, fs, fx;   // f: constant part, factor of s, factor of X
+  T g0, gs, gy;   // g: constant part, factor of s, factor of Y
+};
+
+template <int J, typename T>
+__device__ __forceinline__ CollClass<T> coll_class(const CollNodeF<T>& q, const Coef<T>& c) {
+  constexpr double wd = J == 0 ? 4.0 / 9.0 : (J == 1 ? 1.0 / 9.0 : 1.0 / 36.0);
+  const T w = T(wd);
+  CollClass<T> k;
+  k.f0 = w * q.pf;
+  k.fs = w * q.rf;
+  k.fx = w * c.kf;
+  k.gs = w * q.ph;
+  k.gy = q.K * (w * c.kg);
+  if constexpr (J == 0) k.g0 = fmad(-T(1.0 - wd), q.amu, q.phi) * c.inv_tau_g;
+  else k.g0 = q.amu * (w * c.inv_tau_g);
+  return k;
+}
+
+template <int I> __host__ __device__ constexpr int wclass() { return I == 0 ? 0 : (I <= 4 ? 1 : 2); }
+
+template <int I = 0, typename T>
+__device__ __forceinline__ void collide_dirs(T f[9], T g[9], const CollNode<T>& n,
+                                             const CollNodeF<T>& q, CollClass<T> k,
+                                             const Coef<T>& c, T af, T ag) {
+  if constexpr (I < 9) {
+    if constexpr (I == 0 || I == 1 || I == 5) k = coll_class<wclass<I>()>(q, c);
+    T s, X, Y;
+    coll_dir<I>(n, s, X, Y);
+    f[I] = fmad(af, f[I], fmad(k.fx, X, fmad(k.fs, s, k.f0)));
+    g[I] = fmad(ag, g[I], fmad(k.gy, Y, fmad(k.gs, s, k.g0)));
+    collide_dirs<I + 1>(f, g, n, q, k, c, af, ag);
+  }
+}
+
 // BGK collision of both populations with the source terms (Sec. III):
 // s_i = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2, Gamma_i = 1 + s_i,
 // f^eq = w (p + rho s / 3), F_i = w (c-u).(Gamma F + s grad rho / 3) - w rho gamma D / 3,
 // g^eq = H_i + w phi s, G_i = -3 (phi/rho) w Gamma (c-u).(grad p - F),
-// x* = x - (x - x^eq)/tau + (1 - 1/(2 tau)) X_i.
+// x* = x - (x - x^eq)/tau + (1 - 1/(2 tau)) X_i,
+// evaluated through the shared per-node and per-weight-class factors above.
 template <typename T>
 __device__ __forceinline__ void collide_node(T f[9], T g[9], const Macro<T>& m, T dpx, T dpy,
                                              const Coef<T>& c) {
-  const T usq = m.ux * m.ux + m.uy * m.uy;
-  const T gpre = -T(3) * m.phi * recip(m.rho);
-  const T hx = dpx - m.Fx, hy = dpy - m.Fy;
-  const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
-  const T amu = c.alpha * m.mu;
-  const T r3 = m.rho * T(1.0 / 3.0);
-  const T dx3 = m.drx * T(1.0 / 3.0), dy3 = m.dry * T(1.0 / 3.0);
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T w = T(WGT(i));
-    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
-    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
-    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T gm = T(1) + s;
-    const T feq = w * (m.p + r3 * s);
-    const T Fi = w * (cxu * (gm * m.Fx + s * dx3) + cyu * (gm * m.Fy + s * dy3) + src1);
-    const T H = (i == 0) ? m.phi - T(1.0 - 4.0 / 9.0) * amu : w * amu;
-    const T geq = H + w * m.phi * s;
-    const T Gi = gpre * w * gm * (cxu * hx + cyu * hy);
-    f[i] = f[i] - (f[i] - feq) * c.inv_tau_f + c.kf * Fi;
-    g[i] = g[i] - (g[i] - geq) * c.inv_tau_g + c.kg * Gi;
-  }
+  const CollNode<T> n = coll_node(m, dpx, dpy);
+  const CollNodeF<T> q = coll_nodef(m, c);
+  collide_dirs(f, g, n, q, CollClass<T>{}, c, T(1) - c.inv_tau_f, T(1) - c.inv_tau_g);
 }
 
 // Two-relaxation-time variant of the f collision (g keeps BGK): f, f^eq and
@@ -403,31 +514,30 @@ __device__ __forceinline__ void collide_node(T f[9], T g[9], const Macro<T>& m, 
 // (tau_f - 1/2)(tau_- - 1/2)), and each source part takes its own
 // 1 - 1/(2 tau) (Ginzburg, Verhaeghe and d'Humieres, 2008). The rest
 // population has no odd part.
+template <int I = 0, typename T>
+__device__ __forceinline__ void trt_terms(T g[9], T feq[9], T Fs[9], const CollNode<T>& n,
+                                          const CollNodeF<T>& q, CollClass<T> k,
+                                          const Macro<T>& m, const Coef<T>& c, T src1, T ag) {
+  if constexpr (I < 9) {
+    if constexpr (I == 0 || I == 1 || I == 5) k = coll_class<wclass<I>()>(q, c);
+    const T w = T(WGT(I));
+    T s, X, Y;
+    coll_dir<I>(n, s, X, Y);
+    feq[I] = w * fmad(m.rho * T(1.0 / 3.0), s, m.p);
+    Fs[I] = w * (X + src1);
+    g[I] = fmad(ag, g[I], fmad(k.gy, Y, fmad(k.gs, s, k.g0)));
+    trt_terms<I + 1>(g, feq, Fs, n, q, k, m, c, src1, ag);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void collide_node_trt(T f[9], T g[9], const Macro<T>& m, T dpx,
                                                  T dpy, const Coef<T>& c) {
-  const T usq = m.ux * m.ux + m.uy * m.uy;
-  const T gpre = -T(3) * m.phi * recip(m.rho);
-  const T hx = dpx - m.Fx, hy = dpy - m.Fy;
+  const CollNode<T> n = coll_node(m, dpx, dpy);
+  const CollNodeF<T> q = coll_nodef(m, c);
   const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
-  const T amu = c.alpha * m.mu;
-  const T r3 = m.rho * T(1.0 / 3.0);
-  const T dx3 = m.drx * T(1.0 / 3.0), dy3 = m.dry * T(1.0 / 3.0);
   T feq[9], Fs[9];
-#pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T w = T(WGT(i));
-    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
-    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
-    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T gm = T(1) + s;
-    feq[i] = w * (m.p + r3 * s);
-    Fs[i] = w * (cxu * (gm * m.Fx + s * dx3) + cyu * (gm * m.Fy + s * dy3) + src1);
-    const T H = (i == 0) ? m.phi - T(1.0 - 4.0 / 9.0) * amu : w * amu;
-    const T geq = H + w * m.phi * s;
-    const T Gi = gpre * w * gm * (cxu * hx + cyu * hy);
-    g[i] = g[i] - (g[i] - geq) * c.inv_tau_g + c.kg * Gi;
-  }
+  trt_terms(g, feq, Fs, n, q, CollClass<T>{}, m, c, src1, T(1) - c.inv_tau_g);
   f[0] = f[0] - (f[0] - feq[0]) * c.inv_tau_f + c.kf * Fs[0];
 #pragma unroll
   for (int i = 1; i < 9; ++i) {
