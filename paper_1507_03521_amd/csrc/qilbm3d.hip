@@ -29,6 +29,7 @@ using qilbm::P_F64;
 using qilbm::PrecT;
 using qilbm::mu_bulk;
 using qilbm::recip;
+using qilbm::fmad;
 using qilbm::BUF_WORD3;
 using qilbm::buf_ld;
 using qilbm::buf_st;
@@ -225,37 +226,154 @@ __device__ __forceinline__ void macro3(T phi, T mu, const T gph[3], const T gmu[
   m.p = S + T(1.0 / 6.0) * (ud - c.gamma * m.rho * m.D);
 }
 
-// BGK collisions of both populations with their sources (Sec. III).
+// c.(x, y, z) for a D3Q19 direction known at compile time (at most two
+// nonzero components): signs and one sum, no products.
+template <int CXV, int CYV, int CZV, typename T>
+__device__ __forceinline__ T cdot3(T x, T y, T z) {
+  static_assert(CXV == 0 || CYV == 0 || CZV == 0, "D3Q19: at most two nonzero components");
+  if constexpr (CXV == 0) return qilbm::cdot<CYV, CZV>(y, z);
+  else if constexpr (CYV == 0) return qilbm::cdot<CXV, CZV>(x, z);
+  else return qilbm::cdot<CXV, CYV>(x, y);
+}
+
+// What every direction of one node's collision shares (three components):
+// u, 1.5 |u|^2, F, grad rho / 3, grad p - F and their dot products with u.
+template <typename T>
+struct CollNode3 {
+  T u[3], usq15;
+  T F[3], uF;
+  T d[3], ud;
+  T q[3], uq;
+};
+
+template <typename T>
+__device__ __forceinline__ CollNode3<T> coll_node3(const Node3<T>& m, const T dp[3]) {
+  CollNode3<T> n;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    n.u[a] = m.u[a];
+    n.F[a] = m.F[a];
+    n.d[a] = m.dr[a] * T(1.0 / 3.0);
+    n.q[a] = dp[a] - m.F[a];
+  }
+  n.usq15 = T(1.5) * fmad(m.u[2], m.u[2], fmad(m.u[1], m.u[1], m.u[0] * m.u[0]));
+  n.uF = fmad(m.u[2], n.F[2], fmad(m.u[1], n.F[1], m.u[0] * n.F[0]));
+  n.ud = fmad(m.u[2], n.d[2], fmad(m.u[1], n.d[1], m.u[0] * n.d[0]));
+  n.uq = fmad(m.u[2], n.q[2], fmad(m.u[1], n.q[1], m.u[0] * n.q[0]));
+  return n;
+}
+
+// Direction I: s = 3 c.u + 4.5 (c.u)^2 - 1.5 u^2, X = (c-u).(Gamma F +
+// s grad rho / 3) = A + s (A + B), Y = Gamma (c-u).(grad p - F) = Q + s Q.
+template <int I, typename T>
+__device__ __forceinline__ void coll_dir3(const CollNode3<T>& n, T& s, T& X, T& Y) {
+  T A, B, Q;
+  if constexpr (I == 0) {
+    s = -n.usq15;
+    A = -n.uF;
+    B = -n.ud;
+    Q = -n.uq;
+  } else {
+    constexpr int cx = CX(I), cy = CY(I), cz = CZ(I);
+    const T cu = cdot3<cx, cy, cz>(n.u[0], n.u[1], n.u[2]);
+    s = fmad(cu, fmad(T(4.5), cu, T(3)), -n.usq15);
+    A = cdot3<cx, cy, cz>(n.F[0], n.F[1], n.F[2]) - n.uF;
+    B = cdot3<cx, cy, cz>(n.d[0], n.d[1], n.d[2]) - n.ud;
+    Q = cdot3<cx, cy, cz>(n.q[0], n.q[1], n.q[2]) - n.uq;
+  }
+  X = fmad(s, A + B, A);
+  Y = fmad(s, Q, Q);
+}
+
+// Relaxation factors of one weight class J (rest 1/3, axis 1/18, edge 1/36):
+//   f* = (1 - 1/tau_f) f + w [p/tau_f + kf src1] + w rho/(3 tau_f) s + w kf X
+//   g* = (1 - 1/tau_g) g + H/tau_g + w phi/tau_g s + w kg K Y,
+// src1 = -rho gamma D / 3, K = -3 phi / rho, H_0 = phi - (1 - w_0) alpha mu,
+// H_J = w_J alpha mu; formed just before the class's directions.
+template <typename T>
+struct CollF3 {
+  T pf, rf, amu, ph, K, phi;
+};
+
+template <typename T>
+struct CollK3 {
+  T f0, fs, fx, g0, gs, gy;
+};
+
+template <typename T>
+__device__ __forceinline__ CollF3<T> coll_f3(const Node3<T>& m, const Coef<T>& c) {
+  CollF3<T> q;
+  q.pf = fmad(m.p, c.inv_tau_f, -(m.rho * m.D) * (c.kf * c.gamma * T(1.0 / 3.0)));
+  q.rf = m.rho * (c.inv_tau_f * T(1.0 / 3.0));
+  q.amu = c.alpha * m.mu;
+  q.ph = m.phi * c.inv_tau_g;
+  q.K = -T(3) * m.phi * recip(m.rho);
+  q.phi = m.phi;
+  return q;
+}
+
+template <int J> __host__ __device__ constexpr double wclass3() {
+  return J == 0 ? 1.0 / 3.0 : (J == 1 ? 1.0 / 18.0 : 1.0 / 36.0);
+}
+template <int I> __host__ __device__ constexpr int wclass3_of() {
+  return I == 0 ? 0 : (I <= 6 ? 1 : 2);
+}
+
+template <int J, typename T>
+__device__ __forceinline__ CollK3<T> coll_k3(const CollF3<T>& q, const Coef<T>& c) {
+  constexpr double wd = wclass3<J>();
+  const T w = T(wd);
+  CollK3<T> k;
+  k.f0 = w * q.pf;
+  k.fs = w * q.rf;
+  k.fx = w * c.kf;
+  k.gs = w * q.ph;
+  k.gy = q.K * (w * c.kg);
+  if constexpr (J == 0) k.g0 = fmad(-T(1.0 - wd), q.amu, q.phi) * c.inv_tau_g;
+  else k.g0 = q.amu * (w * c.inv_tau_g);
+  return k;
+}
+
+template <int I = 0, typename T>
+__device__ __forceinline__ void collide3_dirs(T f[19], T gg[19], const CollNode3<T>& n,
+                                              const CollF3<T>& q, CollK3<T> k,
+                                              const Coef<T>& c, T af, T ag) {
+  if constexpr (I < 19) {
+    if constexpr (I == 0 || I == 1 || I == 7) k = coll_k3<wclass3_of<I>()>(q, c);
+    T s, X, Y;
+    coll_dir3<I>(n, s, X, Y);
+    f[I] = fmad(af, f[I], fmad(k.fx, X, fmad(k.fs, s, k.f0)));
+    gg[I] = fmad(ag, gg[I], fmad(k.gy, Y, fmad(k.gs, s, k.g0)));
+    collide3_dirs<I + 1>(f, gg, n, q, k, c, af, ag);
+  }
+}
+
+// BGK collisions of both populations with their sources (Sec. III):
+// f^eq = w (p + rho s / 3), F_i = w (c-u).(Gamma F + s grad rho / 3)
+// - w rho gamma D / 3, g^eq = H_i + w phi s, G_i = -3 (phi/rho) w Gamma
+// (c-u).(grad p - F), x* = x - (x - x^eq)/tau + (1 - 1/(2 tau)) X_i, through
+// the shared per-node and per-weight-class factors above.
 template <typename T>
 __device__ __forceinline__ void collide3(T f[19], T gg[19], const Node3<T>& m, const T dp[3],
                                          const Coef<T>& c) {
-  const T usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-  const T gpre = -T(3) * m.phi * recip(m.rho);
-  const T h[3] = {dp[0] - m.F[0], dp[1] - m.F[1], dp[2] - m.F[2]};
-  const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
-  const T amu = c.alpha * m.mu;
-  const T r3 = m.rho * T(1.0 / 3.0);
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const T w = T(W(i));
-    const T cv[3] = {T(CX(i)), T(CY(i)), T(CZ(i))};
-    const T cu = cv[0] * m.u[0] + cv[1] * m.u[1] + cv[2] * m.u[2];
-    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T gm = T(1) + s;
-    T fa = T(0), ga = T(0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T cmu = cv[a] - m.u[a];
-      fa += cmu * (gm * m.F[a] + s * m.dr[a] * T(1.0 / 3.0));
-      ga += cmu * h[a];
-    }
-    const T feq = w * (m.p + r3 * s);
-    const T Fi = w * (fa + src1);
-    const T H = (i == 0) ? m.phi - T(1.0 - 1.0 / 3.0) * amu : w * amu;
-    const T geq = H + w * m.phi * s;
-    const T Gi = gpre * w * gm * ga;
-    f[i] = f[i] - (f[i] - feq) * c.inv_tau_f + c.kf * Fi;
-    gg[i] = gg[i] - (gg[i] - geq) * c.inv_tau_g + c.kg * Gi;
+  const CollNode3<T> n = coll_node3(m, dp);
+  const CollF3<T> q = coll_f3(m, c);
+  collide3_dirs(f, gg, n, q, CollK3<T>{}, c, T(1) - c.inv_tau_f, T(1) - c.inv_tau_g);
+}
+
+template <int I = 0, typename T>
+__device__ __forceinline__ void trt3_terms(T gg[19], T feq[19], T Fs[19], const CollNode3<T>& n,
+                                           const CollF3<T>& q, CollK3<T> k, const Node3<T>& m,
+                                           const Coef<T>& c, T src1, T ag) {
+  if constexpr (I < 19) {
+    if constexpr (I == 0 || I == 1 || I == 7) k = coll_k3<wclass3_of<I>()>(q, c);
+    const T w = T(W(I));
+    T s, X, Y;
+    coll_dir3<I>(n, s, X, Y);
+    feq[I] = w * fmad(m.rho * T(1.0 / 3.0), s, m.p);
+    Fs[I] = w * (X + src1);
+    gg[I] = fmad(ag, gg[I], fmad(k.gy, Y, fmad(k.gs, s, k.g0)));
+    trt3_terms<I + 1>(gg, feq, Fs, n, q, k, m, c, src1, ag);
   }
 }
 
@@ -267,34 +385,11 @@ __device__ __forceinline__ void collide3(T f[19], T gg[19], const Node3<T>& m, c
 template <typename T>
 __device__ __forceinline__ void collide3_trt(T f[19], T gg[19], const Node3<T>& m, const T dp[3],
                                              const Coef<T>& c) {
-  const T usq = m.u[0] * m.u[0] + m.u[1] * m.u[1] + m.u[2] * m.u[2];
-  const T gpre = -T(3) * m.phi * recip(m.rho);
-  const T h[3] = {dp[0] - m.F[0], dp[1] - m.F[1], dp[2] - m.F[2]};
+  const CollNode3<T> n = coll_node3(m, dp);
+  const CollF3<T> q = coll_f3(m, c);
   const T src1 = -m.rho * c.gamma * m.D * T(1.0 / 3.0);
-  const T amu = c.alpha * m.mu;
-  const T r3 = m.rho * T(1.0 / 3.0);
   T feq[19], Fs[19];
-#pragma unroll
-  for (int i = 0; i < 19; ++i) {
-    const T w = T(W(i));
-    const T cv[3] = {T(CX(i)), T(CY(i)), T(CZ(i))};
-    const T cu = cv[0] * m.u[0] + cv[1] * m.u[1] + cv[2] * m.u[2];
-    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T gm = T(1) + s;
-    T fa = T(0), ga = T(0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      const T cmu = cv[a] - m.u[a];
-      fa += cmu * (gm * m.F[a] + s * m.dr[a] * T(1.0 / 3.0));
-      ga += cmu * h[a];
-    }
-    feq[i] = w * (m.p + r3 * s);
-    Fs[i] = w * (fa + src1);
-    const T H = (i == 0) ? m.phi - T(1.0 - 1.0 / 3.0) * amu : w * amu;
-    const T geq = H + w * m.phi * s;
-    const T Gi = gpre * w * gm * ga;
-    gg[i] = gg[i] - (gg[i] - geq) * c.inv_tau_g + c.kg * Gi;
-  }
+  trt3_terms(gg, feq, Fs, n, q, CollK3<T>{}, m, c, src1, T(1) - c.inv_tau_g);
   f[0] = f[0] - (f[0] - feq[0]) * c.inv_tau_f + c.kf * Fs[0];
 #pragma unroll
   for (int i = 1; i < 19; i += 2) {           // (i, i + 1) are opposite
