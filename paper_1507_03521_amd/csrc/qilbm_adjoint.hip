@@ -136,11 +136,16 @@ __device__ __forceinline__ double wsum(double v) {
 }
 
 __device__ __forceinline__ void block_add(double v, int slot, double* acc_part) {
-  __shared__ double red[4];
+  __shared__ double red[4];     // one per wavefront of a workgroup of 64 to 256 lanes
   v = wsum(v);
   if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
   __syncthreads();
-  if (threadIdx.x == 0) acc_part[4 * blockIdx.x + slot] += (red[0] + red[1]) + (red[2] + red[3]);
+  if (threadIdx.x == 0) {
+    const int nw = (int)(blockDim.x >> 6);
+    double s = nw > 1 ? red[0] + red[1] : red[0];
+    if (nw > 2) s += nw > 3 ? red[2] + red[3] : red[2];
+    acc_part[4 * blockIdx.x + slot] += s;
+  }
   __syncthreads();
 }
 
@@ -193,87 +198,117 @@ struct NodeBar {
   T p, rho, ux, uy, Fx, Fy, drx, dry, D, phi, mu, dpx, dpy, alpha;
 };
 
+// The collision in the form the forward kernels evaluate it (per node:
+// u.F, u.(grad rho / 3), u.(grad p - F); per direction: s, A = (c-u).F,
+// B = (c-u).grad rho / 3, Q = (c-u).(grad p - F), X = A + s (A + B),
+// Y = Q + s Q;
+//   f* = (1 - 1/tau_f) f + (1/tau_f) w (p + rho s / 3) + kf w (X + src1),
+//   g* = (1 - 1/tau_g) g + (1/tau_g) (H + w phi s) + kg w K Y,
+// src1 = -rho gamma D / 3, K = -3 phi / rho), transposed. With the weighted
+// cotangents a = w fbar*, b = w gbar*:
+//   sbar = a (rho/(3 tau_f) + kf (A + B)) + b (phi/tau_g + kg K Q),
+//   Abar = kf a (1 + s), Bbar = kf a s, Qbar = kg K b (1 + s),
+//   (c.u)bar = sbar (3 + 9 c.u), (1.5 u^2)bar = -sbar,
+// and Abar, Bbar, Qbar go to F, grad rho, grad p - F through c - u. The
+// sums over directions are carried per node and turned into the node
+// cotangents once.
+template <int I = 0, typename T>
+__device__ __forceinline__ void coll_T_dirs(T fh[9], T gh[9], const CollNode<T>& n, T rp, T pp,
+                                            T Kk, T kf, T af, T ag, T (&acc)[17]) {
+  if constexpr (I < 9) {
+    const T w = T(WGT(I));
+    const T a = w * fh[I], b = w * gh[I];
+    fh[I] = af * fh[I];
+    gh[I] = ag * gh[I];
+    T s, cu, A, B, Q;
+    if constexpr (I == 0) {
+      s = -n.usq15;
+      cu = T(0);
+      A = -n.uF;
+      B = -n.ud;
+      Q = -n.uq;
+    } else {
+      constexpr int cx = CXS(I), cy = CYS(I);
+      cu = cdot<cx, cy>(n.ux, n.uy);
+      s = fmad(cu, fmad(T(4.5), cu, T(3)), -n.usq15);
+      A = cdot<cx, cy>(n.Fx, n.Fy) - n.uF;
+      B = cdot<cx, cy>(n.dx, n.dy) - n.ud;
+      Q = cdot<cx, cy>(n.qx, n.qy) - n.uq;
+    }
+    const T sbar = fmad(a, fmad(kf, A + B, rp), b * fmad(Kk, Q, pp));
+    acc[0] += a;                       // sum a
+    acc[1] = fmad(s, a, acc[1]);       // sum s a
+    acc[2] = fmad(s, b, acc[2]);       // sum s b
+    if constexpr (I != 0) acc[3] += b; // sum over i > 0 of b
+    acc[4] = fmad(fmad(s, Q, Q), b, acc[4]);   // sum Y b
+    const T Au = fmad(s, a, a), Bu = s * a, Qu = fmad(s, b, b);
+    acc[5] += Au;
+    acc[8] += Bu;
+    acc[11] += Qu;
+    if constexpr (I != 0) {
+      constexpr int cx = CXS(I), cy = CYS(I);
+      if constexpr (cx != 0) {
+        acc[6] = cx > 0 ? acc[6] + Au : acc[6] - Au;
+        acc[9] = cx > 0 ? acc[9] + Bu : acc[9] - Bu;
+        acc[12] = cx > 0 ? acc[12] + Qu : acc[12] - Qu;
+      }
+      if constexpr (cy != 0) {
+        acc[7] = cy > 0 ? acc[7] + Au : acc[7] - Au;
+        acc[10] = cy > 0 ? acc[10] + Bu : acc[10] - Bu;
+        acc[13] = cy > 0 ? acc[13] + Qu : acc[13] - Qu;
+      }
+      const T cbar = sbar * fmad(T(9), cu, T(3));
+      if constexpr (cx != 0) acc[14] = cx > 0 ? acc[14] + cbar : acc[14] - cbar;
+      if constexpr (cy != 0) acc[15] = cy > 0 ? acc[15] + cbar : acc[15] - cbar;
+    }
+    acc[16] += sbar;
+    coll_T_dirs<I + 1>(fh, gh, n, rp, pp, Kk, kf, af, ag, acc);
+  }
+}
+
 template <typename T>
 __device__ __forceinline__ void collide_node_T(T fh[9], T gh[9], const Macro<T>& m, T dpx, T dpy,
                                                const Coef<T>& c, NodeBar<T>& nb) {
-  const T usq = m.ux * m.ux + m.uy * m.uy;
-  const T gpre = -T(3) * m.phi / m.rho;
-  const T hx = dpx - m.Fx, hy = dpy - m.Fy;
-  const T r3 = m.rho * T(1.0 / 3.0);
-  const T dx3 = m.drx * T(1.0 / 3.0), dy3 = m.dry * T(1.0 / 3.0);
-  T b_p = 0, b_r3 = 0, b_Fx = 0, b_Fy = 0, b_dx3 = 0, b_dy3 = 0, b_src1 = 0, b_amu = 0;
-  T b_phi = 0, b_gpre = 0, b_hx = 0, b_hy = 0, b_ux = 0, b_uy = 0, b_usq = 0;
+  const CollNode<T> n = coll_node(m, dpx, dpy);
+  const T itf = c.inv_tau_f, itg = c.inv_tau_g;
+  const T rinv = recip(m.rho);
+  const T K = -T(3) * m.phi * rinv;
+  const T Kk = K * c.kg;
+  const T rp = m.rho * (itf * T(1.0 / 3.0));
+  const T pp = m.phi * itg;
+  const T b0 = gh[0];
+  T acc[17];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T w = T(WGT(i));
-    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
-    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
-    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T gm = T(1) + s;
-    const T a = fh[i] * c.inv_tau_f;   // cotangent of f^eq_i
-    const T b = fh[i] * c.kf;          // cotangent of F_i
-    const T a2 = gh[i] * c.inv_tau_g;  // cotangent of g^eq_i
-    const T b2 = gh[i] * c.kg;         // cotangent of G_i
-    fh[i] = fh[i] * (T(1) - c.inv_tau_f);
-    gh[i] = gh[i] * (T(1) - c.inv_tau_g);
-    T b_s = 0, b_gm = 0, b_cxu = 0, b_cyu = 0;
-    // f^eq = w (p + r3 s)
-    b_p += a * w;
-    b_r3 += a * w * s;
-    b_s += a * w * r3;
-    // F_i = w (cxu (gm Fx + s dx3) + cyu (gm Fy + s dy3) + src1)
-    const T bw = b * w;
-    b_cxu += bw * (gm * m.Fx + s * dx3);
-    b_cyu += bw * (gm * m.Fy + s * dy3);
-    b_gm += bw * (cxu * m.Fx + cyu * m.Fy);
-    b_Fx += bw * cxu * gm;
-    b_Fy += bw * cyu * gm;
-    b_s += bw * (cxu * dx3 + cyu * dy3);
-    b_dx3 += bw * cxu * s;
-    b_dy3 += bw * cyu * s;
-    b_src1 += bw;
-    // g^eq = H_i + w phi s, H_0 = phi - (5/9) amu, H_i = w amu
-    b_phi += a2 * w * s;
-    b_s += a2 * w * m.phi;
-    if (i == 0) {
-      b_phi += a2;
-      b_amu -= T(1.0 - 4.0 / 9.0) * a2;
-    } else {
-      b_amu += w * a2;
-    }
-    // G_i = gpre w gm E, E = cxu hx + cyu hy
-    const T E = cxu * hx + cyu * hy;
-    b_gpre += b2 * w * gm * E;
-    b_gm += b2 * gpre * w * E;
-    const T bE = b2 * gpre * w * gm;
-    b_cxu += bE * hx;
-    b_cyu += bE * hy;
-    b_hx += bE * cxu;
-    b_hy += bE * cyu;
-    // gm = 1 + s; s = 3 cu + 4.5 cu^2 - 1.5 usq; cu = c.u; cxu = c_x - ux
-    b_s += b_gm;
-    const T b_cu = b_s * (T(3) + T(9) * cu);
-    b_usq -= T(1.5) * b_s;
-    b_ux += b_cu * T(CXS(i)) - b_cxu;
-    b_uy += b_cu * T(CYS(i)) - b_cyu;
-  }
-  b_ux += T(2) * m.ux * b_usq;
-  b_uy += T(2) * m.uy * b_usq;
-  nb.p = b_p;
-  nb.rho = b_r3 * T(1.0 / 3.0) - b_src1 * c.gamma * m.D * T(1.0 / 3.0) +
-           b_gpre * T(3) * m.phi / (m.rho * m.rho);
-  nb.D = -b_src1 * m.rho * c.gamma * T(1.0 / 3.0);
-  nb.drx = b_dx3 * T(1.0 / 3.0);
-  nb.dry = b_dy3 * T(1.0 / 3.0);
-  nb.mu = c.alpha * b_amu;
-  nb.alpha = m.mu * b_amu;
-  nb.phi = b_phi - T(3) * b_gpre / m.rho;
-  nb.dpx = b_hx;
-  nb.dpy = b_hy;
-  nb.Fx = b_Fx - b_hx;
-  nb.Fy = b_Fy - b_hy;
-  nb.ux = b_ux;
-  nb.uy = b_uy;
+  for (int j = 0; j < 17; ++j) acc[j] = T(0);
+  coll_T_dirs(fh, gh, n, rp, pp, Kk, c.kf, T(1) - itf, T(1) - itg, acc);
+  const T src1_bar = c.kf * acc[0];
+  const T K_bar = c.kg * acc[4];
+  // A, B, Q cotangents through c - u
+  const T uF_bar = -c.kf * acc[5], ud_bar = -c.kf * acc[8], uq_bar = -Kk * acc[11];
+  const T qx_bar = fmad(uq_bar, n.ux, Kk * acc[12]);
+  const T qy_bar = fmad(uq_bar, n.uy, Kk * acc[13]);
+  const T dx_bar = fmad(ud_bar, n.ux, c.kf * acc[9]);
+  const T dy_bar = fmad(ud_bar, n.uy, c.kf * acc[10]);
+  const T usq_bar = -acc[16];     // cotangent of 1.5 |u|^2
+  nb.p = itf * acc[0];
+  nb.rho = fmad(itf * T(1.0 / 3.0), acc[1],
+                fmad(src1_bar, -c.gamma * m.D * T(1.0 / 3.0), K_bar * (T(3) * m.phi) * rinv * rinv));
+  nb.D = -src1_bar * m.rho * c.gamma * T(1.0 / 3.0);
+  nb.drx = dx_bar * T(1.0 / 3.0);
+  nb.dry = dy_bar * T(1.0 / 3.0);
+  // H_0 = phi - (1 - w_0) alpha mu, H_i = w_i alpha mu: (alpha mu)bar
+  const T amu_bar = itg * fmad(-T(1.0 - 4.0 / 9.0), b0, acc[3]);
+  nb.mu = c.alpha * amu_bar;
+  nb.alpha = m.mu * amu_bar;
+  nb.phi = fmad(itg, acc[2] + b0, -T(3) * K_bar * rinv);
+  nb.dpx = qx_bar;
+  nb.dpy = qy_bar;
+  nb.Fx = fmad(uF_bar, n.ux, c.kf * acc[6]) - qx_bar;
+  nb.Fy = fmad(uF_bar, n.uy, c.kf * acc[7]) - qy_bar;
+  nb.ux = fmad(T(3) * n.ux, usq_bar,
+               fmad(uq_bar, n.qx, fmad(ud_bar, n.dx, fmad(uF_bar, n.Fx, acc[14]))));
+  nb.uy = fmad(T(3) * n.uy, usq_bar,
+               fmad(uq_bar, n.qy, fmad(ud_bar, n.dy, fmad(uF_bar, n.Fy, acc[15]))));
 }
 
 // Forward node state from the record of step t (same arithmetic as the
@@ -385,23 +420,17 @@ __device__ __forceinline__ void gradp_cot_at(const T* rec, const T* hat, int n, 
   fwd_node<T>(rec, k, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
   T gh[9];
   post_hat9<T>(hat, 9, k, g.Ns, gh);
-  const T usq = m.ux * m.ux + m.uy * m.uy;
-  const T gpre = -T(3) * m.phi / m.rho;
-  T b_hx = 0, b_hy = 0;
+  T fh[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) {
-    const T w = T(WGT(i));
-    const T cxu = T(CXS(i)) - m.ux, cyu = T(CYS(i)) - m.uy;
-    const T cu = T(CXS(i)) * m.ux + T(CYS(i)) * m.uy;
-    const T s = T(3) * cu + T(4.5) * cu * cu - T(1.5) * usq;
-    const T gm = T(1) + s;
-    const T b2 = gh[i] * c.kg;
-    const T bE = b2 * gpre * w * gm;
-    b_hx += bE * cxu;
-    b_hy += bE * cyu;
-  }
-  bx = b_hx;
-  by = b_hy;
+  for (int i = 0; i < 9; ++i) fh[i] = T(0);
+  // grad p enters the collision only through Q = (c-u).(grad p - F), and
+  // its cotangent (c-u) Qbar does not depend on grad p itself: the grad p
+  // cotangent of collide_node_T, computed here with zero f cotangents and
+  // without grad p (whose value reaches only outputs not used)
+  NodeBar<T> nb;
+  collide_node_T(fh, gh, m, T(0), T(0), c, nb);
+  bx = nb.dpx;
+  by = nb.dpy;
 }
 
 // grad^T of the grad p cotangent at interior position (ly, lx), global row
@@ -667,7 +696,13 @@ __global__ __launch_bounds__(256) void k_hat_to(const T* __restrict__ hat, doubl
 // Stage s (A' = 1 ... D' = 4) runs on lanes [s, wi + 8 - s) and rows
 // [y0 - 4 + s, y1 + 4 - s); the record rows reach 4 beyond the segment.
 constexpr int AH = 4;
-constexpr int ANT = 256;
+#ifndef QILBM_ANT
+#define QILBM_ANT 256
+#endif
+#ifndef QILBM_ADJ_WAVES32
+#define QILBM_ADJ_WAVES32 2
+#endif
+constexpr int ANT = QILBM_ANT;
 
 template <typename T>
 struct AdjLds {
@@ -966,7 +1001,7 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
 }
 
 template <typename T>
-struct AdjWaves { static constexpr int value = sizeof(T) == 8 ? 1 : 2; };
+struct AdjWaves { static constexpr int value = sizeof(T) == 8 ? 1 : QILBM_ADJ_WAVES32; };
 
 // BIG: the 18 cotangent planes span 4 GiB or more (one descriptor per plane).
 template <typename T, bool BIG>
@@ -1112,11 +1147,11 @@ lbm_status adj_core(const CtxView& v, const T* rec) {
     const int ntiles = nstrips * nseg;
     const int nblk = ntiles < a.nred ? ntiles : a.nred;
     if (18 * g.Ns * (int64_t)sizeof(T) > (int64_t)UINT32_MAX)
-      hipLaunchKernelGGL((k_adj_fused<T, true>), dim3(nblk), blk, 0, v.stream, rec, hin, hout,
-                         a.part, k, g, width, nstrips, seg, ntiles);
+      hipLaunchKernelGGL((k_adj_fused<T, true>), dim3(nblk), dim3(ANT), 0, v.stream, rec, hin,
+                         hout, a.part, k, g, width, nstrips, seg, ntiles);
     else
-      hipLaunchKernelGGL((k_adj_fused<T, false>), dim3(nblk), blk, 0, v.stream, rec, hin, hout,
-                         a.part, k, g, width, nstrips, seg, ntiles);
+      hipLaunchKernelGGL((k_adj_fused<T, false>), dim3(nblk), dim3(ANT), 0, v.stream, rec, hin,
+                         hout, a.part, k, g, width, nstrips, seg, ntiles);
   }
   if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
   a.cur ^= 1;
