@@ -100,12 +100,12 @@ __device__ __forceinline__ void gt_term(const T* vx, const T* vy, const T* ws, c
   const int r = k.rt[1 - cy];
   if (r >= 0) {
     const int m = r + k.cl[1 - cx];
-    if constexpr (GR) gacc += w3 * (T(cx) * vx[m] + T(cy) * vy[m]);
+    if constexpr (GR) gacc += w3 * cdot<cx, cy>(vx[m], vy[m]);
     if constexpr (LP) lacc += w6 * ws[m];
   }
   if ((cy == -1 && k.lo) || (cy == 1 && k.hi)) {
     const int m = k.rs[1] + k.cl[1 - cx];
-    if constexpr (GR) gacc += w3 * (T(cx) * vx[m] + T(cy) * vy[m]);
+    if constexpr (GR) gacc += w3 * cdot<cx, cy>(vx[m], vy[m]);
     if constexpr (LP) lacc += w6 * ws[m];
   }
 }
@@ -186,6 +186,18 @@ __device__ __forceinline__ void post_hat9(const T* hat, int koff, const NodeIdx&
   if constexpr (I < 9) {
     v[I] = post_hat<T, I>(hat, koff, k, Ns);
     post_hat9<T, I + 1>(hat, koff, k, Ns, v);
+  }
+}
+
+// The f cotangents of the pre-collision state: the direct part fd_i plus the
+// moment transposes Sbar + c_i.jbar, handed to store(i, value).
+template <int I = 0, typename T, typename St>
+__device__ __forceinline__ void fbar_out(const St& store, const T fd[9], T bS, T bjx, T bjy) {
+  if constexpr (I < 9) {
+    T v = fd[I] + bS;
+    if constexpr (I != 0) v += cdot<CXS(I), CYS(I)>(bjx, bjy);
+    store(I, v);
+    fbar_out<I + 1>(store, fd, bS, bjx, bjy);
   }
 }
 
@@ -442,9 +454,9 @@ __device__ __forceinline__ void gpT_term(const CmLds<T>& L, int ly, int lx, int 
   const T w3 = T(3.0 * WGT(I));
   const int ys = y - cy;
   if (!g.walls || (ys >= 0 && ys < g.ny))
-    acc += w3 * (T(cx) * L.dpx[ly - cy][lx - cx] + T(cy) * L.dpy[ly - cy][lx - cx]);
+    acc += w3 * cdot<cx, cy>(L.dpx[ly - cy][lx - cx], L.dpy[ly - cy][lx - cx]);
   if (g.walls && ((cy == -1 && y == 0) || (cy == 1 && y == g.ny - 1)))
-    acc += w3 * (T(cx) * L.dpx[ly][lx - cx] + T(cy) * L.dpy[ly][lx - cx]);
+    acc += w3 * cdot<cx, cy>(L.dpx[ly][lx - cx], L.dpy[ly][lx - cx]);
 }
 
 template <typename T>
@@ -495,9 +507,8 @@ __device__ __forceinline__ double macro_T_at(const T* rec, int n, const NodeBar<
   const T b_gmux = -m.phi * b_Fx, b_gmuy = -m.phi * b_Fy;
   b_rho += b_Fx * c.gx + b_Fy * c.gy;
   // D = lambda lap mu; grad rho = drho grad phi; rho = rho_B + drho phi
-#pragma unroll
-  for (int i = 0; i < 9; ++i)
-    hat_out[(int64_t)i * g.Ns + n] = fd[i] + b_S + T(CXS(i)) * b_jx + T(CYS(i)) * b_jy;
+  fbar_out(
+      [&](int i, T v) { hat_out[(int64_t)i * g.Ns + n] = v; }, fd, b_S, b_jx, b_jy);
   af[A_GMUX][n] = b_gmux;
   af[A_GMUY][n] = b_gmuy;
   af[A_LMU][n] = c.lam * b_D;
@@ -823,11 +834,11 @@ __device__ __forceinline__ void gtl_term(const T (*vx)[ANT], const T (*vy)[ANT],
   const T w3 = T(3.0 * WGT(I)), w6 = T(6.0 * WGT(I));
   if constexpr (src) {
     const int ys = (v - cy) & 3;
-    if constexpr (GR) gacc += w3 * (T(cx) * vx[ys][lc - cx] + T(cy) * vy[ys][lc - cx]);
+    if constexpr (GR) gacc += w3 * cdot<cx, cy>(vx[ys][lc - cx], vy[ys][lc - cx]);
     if constexpr (LP) lacc += w6 * ws[ys][lc - cx];
   }
   if constexpr (ghost) {
-    if constexpr (GR) gacc += w3 * (T(cx) * vx[v & 3][lc - cx] + T(cy) * vy[v & 3][lc - cx]);
+    if constexpr (GR) gacc += w3 * cdot<cx, cy>(vx[v & 3][lc - cx], vy[v & 3][lc - cx]);
     if constexpr (LP) lacc += w6 * ws[v & 3][lc - cx];
   }
 }
@@ -873,6 +884,15 @@ __device__ __forceinline__ void fwd_node_l(const AdjLds<T>& L, int v, int lc, co
   macro_node(ph, w[1][1], gphx, gphy, gmux, gmuy, lapmu, S, jx, jy, c, m);
 }
 
+// Forward node state of a row as A' forms it, kept in registers for B' of the
+// next iteration (the same row and lane: B' runs on a subset of A's rows and
+// lanes).
+template <typename T>
+struct FwdState {
+  Macro<T> m;
+  T jx, jy, gmux, gmuy, lapmu;
+};
+
 // Whether the direct part of the g cotangents waits from A' to D' in
 // registers (FP32) or is gathered again in D' (FP64, whose registers are
 // full; the values are the same).
@@ -881,6 +901,7 @@ template <typename T> struct KeepGd { static constexpr bool value = sizeof(T) ==
 template <typename T, bool BIG, int J>
 __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<T>& L, T (&rrec)[6],
                                          T (&hf)[9], T (&hg)[9], NodeBar<T> (&nbr)[2],
+                                         FwdState<T> (&fst)[2],
                                          T (&fdr)[2][9], T (&gdr)[4][9], T (&p2)[2], T (&m1)[2],
                                          T (&p3)[2], double (&acc)[4]) {
   const Geom& g = k.g;
@@ -899,13 +920,13 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   __syncthreads();
   // A': collision transpose of row a
   if (k.in(a, 1)) {
-    T S, jx, jy, gmux, gmuy, lapmu;
-    Macro<T> m;
-    fwd_node_l<T>(L, a, lc, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+    FwdState<T>& fs = fst[J & 1];
+    T S;
+    fwd_node_l<T>(L, a, lc, c, g, fs.m, S, fs.jx, fs.jy, fs.gmux, fs.gmuy, fs.lapmu);
     T w[3][3], dpx, dpy, lapp;
     lds3x3<T, ANT>(L.p, 3, a, g.ny, g.walls, lc, w);
     stencil(w, dpx, dpy, lapp);
-    collide_node_T(hf, hg, m, dpx, dpy, c, nbr[J & 1]);
+    collide_node_T(hf, hg, fs.m, dpx, dpy, c, nbr[J & 1]);
     // the direct part of the f cotangents, (1 - 1/tau_f) times the
     // post-collision ones, waits for B' in registers
 #pragma unroll
@@ -922,9 +943,10 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   if (k.in(b, 2)) {
     const NodeBar<T>& nb = nbr[(J + 1) & 1];
     const T b_p = nb.p + stencil_Tl<T, true, false>(L.gpx, L.gpy, nullptr, b, lc, k.wall(b));
-    T S, jx, jy, gmux, gmuy, lapmu;
-    Macro<T> m;
-    fwd_node_l<T>(L, b, lc, c, g, m, S, jx, jy, gmux, gmuy, lapmu);
+    // the forward state of row b, formed by A' in the previous iteration
+    const FwdState<T>& fs = fst[(J + 1) & 1];
+    const Macro<T>& m = fs.m;
+    const T jx = fs.jx, jy = fs.jy, gmux = fs.gmux, gmuy = fs.gmuy, lapmu = fs.lapmu;
     T b_rho = nb.rho, b_ux = nb.ux, b_uy = nb.uy;
     T b_Fx = nb.Fx, b_Fy = nb.Fy, b_drx = nb.drx, b_dry = nb.dry;
     T b_D = nb.D, b_phi = nb.phi;
@@ -935,12 +957,13 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     b_dry += b_p * m.uy * T(1.0 / 6.0);
     b_rho -= b_p * c.gamma * m.D * T(1.0 / 6.0);
     b_D -= b_p * c.gamma * m.rho * T(1.0 / 6.0);
-    const T inv = T(3) / m.rho;
+    const T rinv = recip(m.rho);
+    const T inv = T(3) * rinv;
     const T b_jx = b_ux * inv, b_jy = b_uy * inv;
     b_Fx += b_ux * inv * T(1.0 / 6.0);
     b_Fy += b_uy * inv * T(1.0 / 6.0);
     const T b_inv = b_ux * (jx + m.Fx * T(1.0 / 6.0)) + b_uy * (jy + m.Fy * T(1.0 / 6.0));
-    b_rho -= b_inv * inv / m.rho;
+    b_rho -= b_inv * inv * rinv;
     b_phi -= b_Fx * gmux + b_Fy * gmuy;
     L.gmx[b & 3][lc] = -m.phi * b_Fx;
     L.gmy[b & 3][lc] = -m.phi * b_Fy;
@@ -952,10 +975,8 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     m1[J & 1] = nb.mu;
     if (k.owns(b)) {
       const uint32_t ro = (uint32_t)(b * g.nx);
-#pragma unroll
-      for (int i = 0; i < 9; ++i)
-        k.hout.st(i, ro, (uint32_t)k.x,
-                  fdr[(J + 1) & 1][i] + b_S + T(CXS(i)) * b_jx + T(CYS(i)) * b_jy);
+      fbar_out([&](int i, T v) { k.hout.st(i, ro, (uint32_t)k.x, v); }, fdr[(J + 1) & 1], b_S,
+               b_jx, b_jy);
       acc[AP_LAMBDA] += double(b_D) * double(lapmu);
     }
   }
@@ -1035,6 +1056,7 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
     k.col[2] = wrap_x(k.x + 1, g.nx);
     T rrec[6], hf[9], hg[9], fdr[2][9], gdr[4][9], p2[2], m1[2], p3[2];
     NodeBar<T> nbr[2];
+    FwdState<T> fst[2];
     const int r0 = k.d > 0 ? k.y0 - AH : k.y1 + AH - 1;
     const int nit = (k.y1 - k.y0) + 2 * AH + 1;
     if (k.in(r0, 0)) {
@@ -1043,13 +1065,13 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
       for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
     }
     for (int it = 0; it < nit; it += 4) {
-      adj_iter<T, BIG, 0>(k, r0 + k.d * (it + 0), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+      adj_iter<T, BIG, 0>(k, r0 + k.d * (it + 0), L, rrec, hf, hg, nbr, fst, fdr, gdr, p2, m1,
                             p3, acc);
-      adj_iter<T, BIG, 1>(k, r0 + k.d * (it + 1), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+      adj_iter<T, BIG, 1>(k, r0 + k.d * (it + 1), L, rrec, hf, hg, nbr, fst, fdr, gdr, p2, m1,
                             p3, acc);
-      adj_iter<T, BIG, 2>(k, r0 + k.d * (it + 2), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+      adj_iter<T, BIG, 2>(k, r0 + k.d * (it + 2), L, rrec, hf, hg, nbr, fst, fdr, gdr, p2, m1,
                             p3, acc);
-      adj_iter<T, BIG, 3>(k, r0 + k.d * (it + 3), L, rrec, hf, hg, nbr, fdr, gdr, p2, m1,
+      adj_iter<T, BIG, 3>(k, r0 + k.d * (it + 3), L, rrec, hf, hg, nbr, fst, fdr, gdr, p2, m1,
                             p3, acc);
     }
     __syncthreads();
