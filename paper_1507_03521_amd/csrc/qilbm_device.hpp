@@ -294,6 +294,10 @@ __device__ __forceinline__ void pull_src(int x, int y, const Geom& g, int& plane
 }
 
 // --------------------------------------------------------- per-node algebra
+// Fused multiply-add in the compute type.
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // 1/x: correctly rounded in FP64; the hardware reciprocal (1 ulp) in FP32.
 __device__ __forceinline__ double recip(double x) { return 1.0 / x; }
 __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -302,23 +306,24 @@ __device__ __forceinline__ float recip(float x) { return __builtin_amdgcn_rcpf(x
 // with phi_A = 1, phi_B = 0 (Sec. II).
 template <typename T>
 __device__ __forceinline__ T mu_bulk(T phi, const Coef<T>& c) {
-  return c.beta4 * (phi - T(1)) * phi * (phi - T(0.5));
+  // (phi - 1) phi (phi - 1/2) = phi (phi (phi - 3/2) + 1/2)
+  return c.beta4 * (phi * fmad(phi, phi - T(1.5), T(0.5)));
 }
 
 // Isotropic central stencils on a 3x3 neighbourhood v[dy+1][dx+1]:
 // grad = 3 sum_i w_i c_i v(c_i), lap = 6 sum_i w_i (v(c_i) - v(0)).
 template <typename T>
 __device__ __forceinline__ void stencil(const T v[3][3], T& gx, T& gy, T& lap) {
-  const T a = T(1.0 / 9.0), d = T(1.0 / 36.0);
+  // with w = 1/9 (axis), 1/36 (diagonal): 3 w = 1/3, 1/12 and 6 w = 2/3, 1/6
   const T ex = v[1][2] - v[1][0];
   const T ey = v[2][1] - v[0][1];
   const T d1 = v[2][2] - v[0][0];   // (1,1) - (-1,-1)
   const T d2 = v[0][2] - v[2][0];   // (1,-1) - (-1,1)
-  gx = T(3) * (a * ex + d * (d1 + d2));
-  gy = T(3) * (a * ey + d * (d1 - d2));
+  gx = fmad(T(1.0 / 12.0), d1 + d2, T(1.0 / 3.0) * ex);
+  gy = fmad(T(1.0 / 12.0), d1 - d2, T(1.0 / 3.0) * ey);
   const T sa = (v[1][2] + v[1][0]) + (v[2][1] + v[0][1]);
   const T sd = (v[2][2] + v[0][0]) + (v[0][2] + v[2][0]);
-  lap = T(6) * (a * sa + d * sd - T(5.0 / 9.0) * v[1][1]);
+  lap = fmad(T(2.0 / 3.0), sa, fmad(T(1.0 / 6.0), sd, T(-10.0 / 3.0) * v[1][1]));
 }
 
 // The same stencil's 3x3 neighbourhood from a ring of rows in LDS: row v of
@@ -364,10 +369,6 @@ __device__ __forceinline__ void macro_node(T phi, T mu, T gphx, T gphy, T gmux, 
   m.uy = (jy + m.Fy * T(1.0 / 6.0)) * inv;
   m.p = S + T(1.0 / 6.0) * (m.ux * m.drx + m.uy * m.dry - c.gamma * m.rho * m.D);
 }
-
-// Fused multiply-add in the compute type.
-__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
-__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
 // c.(x, y) for the direction (CX, CY) known at compile time: signs and
 // sums only (a product with a zero component is not folded away in IEEE
