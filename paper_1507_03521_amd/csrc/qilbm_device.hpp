@@ -329,17 +329,20 @@ __device__ __forceinline__ void stencil(const T v[3][3], T& gx, T& gy, T& lap) {
 // The same stencil's 3x3 neighbourhood from a ring of rows in LDS: row v of
 // the lattice sits in ring[v & mask], lane lc holds the lane's column (the
 // neighbours at lc -+ 1); at a wall the mirrored ghost row is the row itself.
+// walls is 0 or 1: the ghost-row shift as integer arithmetic stays in scalar
+// registers (as a boolean select the compiler formed it per lane), and one
+// lane address per row serves its three reads.
 template <typename T, int NT>
 __device__ __forceinline__ void lds3x3(const T (*ring)[NT], int mask, int v, int ny, int walls,
                                        int lc, T out[3][3]) {
-  const int vm = (walls && v == 0) ? v : v - 1;
-  const int vp = (walls && v == ny - 1) ? v : v + 1;
-  const T* a = ring[vm & mask];
-  const T* b = ring[v & mask];
-  const T* d = ring[vp & mask];
-  out[0][0] = a[lc - 1]; out[0][1] = a[lc]; out[0][2] = a[lc + 1];
-  out[1][0] = b[lc - 1]; out[1][1] = b[lc]; out[1][2] = b[lc + 1];
-  out[2][0] = d[lc - 1]; out[2][1] = d[lc]; out[2][2] = d[lc + 1];
+  const int vm = v - 1 + (walls & (int)(v == 0));
+  const int vp = v + 1 - (walls & (int)(v == ny - 1));
+  const T* a = &ring[vm & mask][lc - 1];
+  const T* b = &ring[v & mask][lc - 1];
+  const T* d = &ring[vp & mask][lc - 1];
+  out[0][0] = a[0]; out[0][1] = a[1]; out[0][2] = a[2];
+  out[1][0] = b[0]; out[1][1] = b[1]; out[1][2] = b[2];
+  out[2][0] = d[0]; out[2][1] = d[1]; out[2][2] = d[2];
 }
 
 // Macroscopic state of one node needed by the collision.
