@@ -828,6 +828,12 @@ __device__ __forceinline__ void fused_iter(const FusedCtx<P, BIG>& k, int r,
   T f[9], gg[9];
   if constexpr (PAIR) {
     unpack_row<P>(gb[(J + 1) & 3], f0b[(J + 1) & 3], f, gg);
+    // the converted values are formed here, before the next rows' loads
+    // below reuse the registers of these words: otherwise the compiler
+    // defers the conversions into the collision and copies the words aside
+    // (FP16 storage: 0.317 -> 0.312 ms per step)
+#pragma unroll
+    for (int i = 0; i < 9; ++i) asm volatile("" ::"v"(f[i]), "v"(gg[i]));
   } else {
 #pragma unroll
     for (int i = 0; i < 9; ++i) {
