@@ -162,7 +162,8 @@ class Lattice:
 
     def set_pass(self, steps: int, seg_rows: int = 0) -> None:
         """Time steps per fused launch in step() (2: temporal blocking, the
-        default for fp32 and fp16 storage; 1: one launch per step)."""
+        default for fp64 and fp32; 1: one launch per step, the default for
+        fp16 storage)."""
         _lib.check(self.lib.lbm_set_pass(self.ctx, int(steps), int(seg_rows)), "lbm_set_pass")
 
     def pass_info(self) -> dict:
