@@ -781,13 +781,13 @@ __global__ __launch_bounds__(256) void k3_phiq(Pop3<P_F32> in, int32_t* __restri
 //   A: forms phi(a) from the pulled g over the tile plus 3 halo nodes,
 //   B: forms mu(a-1) from the phi planes a-2..a over the tile plus 2,
 //   C: forms the pressure p(a-2) from its pulled f and the phi, mu stencils
-//      over the tile plus 1,
-//   D: collides plane a-3 of the tile (grad p from the p planes a-4..a-2)
-//      and writes both post-collision populations.
-// phi, mu and p live in LDS rings of 5, 4 and 3 planes; the populations
-// are read from HBM where a stage needs them (the re-reads of D follow
-// those of A and C closely enough to be served by the caches) and written
-// once. Halo nodes and the 3 planes of warm-up at each segment end are
+//      over the tile plus 1, and on the tile itself collides f (its
+//      collision needs no grad p) and writes it,
+//   D: collides g of plane a-3 of the tile (grad p from the p planes
+//      a-4..a-2, u and F from the j that C kept in registers) and writes it.
+// phi, mu and p live in LDS rings of 5, 4 and 3 planes; each population set
+// is pulled from HBM once (f by C, g by D) and written once. Halo nodes and
+// the 3 planes of warm-up at each segment end are
 // recomputed by the neighbouring workgroups. Results equal those of the
 // four-kernel path up to the rounding order of contracted multiply-adds.
 // Used for FP32 only, with stage A reading phi from the Q2.29 words that the
@@ -813,11 +813,7 @@ struct FzThreads {
 };
 
 // node rounds of stages C and D unrolled together (loads of several nodes
-// in flight at once), within the register budget of two waves per SIMD
-template <int P>
-struct FzUnrollC {
-  static constexpr int value = 5;
-};
+// in flight at once)
 template <int P>
 struct FzUnrollD {
   static constexpr int value = 2;
@@ -1003,6 +999,10 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
   }
 
   const int niter = (z1 - z0) + 6;
+  // j of the core nodes (two per lane): formed by stage C, used by stage D
+  // one iteration later
+  static_assert((TX * TY + NT - 1) / NT == 2, "two core nodes per lane");
+  T jn[2][3] = {}, jd[2][3] = {};
   for (int it = 0; it < niter; ++it) {
     const int a = vbase + it;
     // A: phi(a) over the tile plus 3
@@ -1060,7 +1060,10 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
       }
     }
     __syncthreads();
-    // C: p(a-2) over the tile plus 1
+    // C: p(a-2) over the tile plus 1; the core nodes of an owned plane also
+    // collide f here (f's collision needs no grad p) and store it, so that f
+    // is pulled once: the core nodes in stage D's lane mapping, whose j waits
+    // in registers for D of the next iteration, then the one-node ring
     const int zc = a - 2;
     if (zc >= z0 - 1 && zc < z1 + 1 && real(zc)) {
       const ZP Z = zp_of<WS>(wrapm(zc, nz), g);
@@ -1071,19 +1074,17 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
       const T* m0 = L.mu[slot(zc, RMU)];
       const T* mp = L.mu[slot(zc + 1, RMU)];
       T* dst = L.p[slot(zc, RP)];
-#pragma unroll FzUnrollC<P>::value
-      for (int rr = 0; rr < (RC::A + NT - 1) / NT; ++rr) {
-        const int r = tid + rr * NT;
-        if (r >= RC::A) break;
-        const int ly = r / RC::W, lx = r - ly * RC::W;
-        const XY q = xy_of<WS>(wrapm(x0 - 1 + lx, g.nx), wrapm(y0 - 1 + ly, g.ny), g);
-        T f[19];
+      const bool own = zc >= z0 && zc < z1;
+      // pulled f of region node (ly, lx) (tile + 1 coordinates) and its state
+      auto node_c = [&](int ly, int lx, T f[19], Node3<T>& m, T j[3], XY& q) {
+        q = xy_of<WS>(wrapm(x0 - 1 + lx, g.nx), wrapm(y0 - 1 + ly, g.ny), g);
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
           const SrcB o = pull_b(i, Z, q);
           f[i] = v.f.ldb(o.plane, o.sb, o.vb);
         }
-        T S = f[0], j[3] = {T(0), T(0), T(0)};
+        T S = f[0];
+        j[0] = j[1] = j[2] = T(0);
 #pragma unroll
         for (int i = 1; i < 19; ++i) {
           S += f[i];
@@ -1096,13 +1097,55 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
                               lphi);
         lds_stencil<T, RB::W>(mm, m0, mp, (ly + 1) * RB::W + lx + 1, mu, gmu[0], gmu[1], gmu[2],
                               lmu);
-        Node3<T> m;
         macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
-        dst[r] = m.p;
+        dst[ly * RC::W + lx] = m.p;
+      };
+#pragma unroll FzUnrollD<P>::value
+      for (int rr = 0; rr < (TX * TY + NT - 1) / NT; ++rr) {
+        const int r = tid + rr * NT;
+        const int ly = r / TX, lx = r - ly * TX;
+        T f[19], j[3];
+        Node3<T> m;
+        XY q;
+        node_c(ly + 1, lx + 1, f, m, j, q);
+        jn[rr][0] = j[0];
+        jn[rr][1] = j[1];
+        jn[rr][2] = j[2];
+        if (own && x0 + lx < g.nx && y0 + ly < g.ny) {
+          const T dp0[3] = {T(0), T(0), T(0)};
+          T gd[19];
+#pragma unroll
+          for (int i = 0; i < 19; ++i) gd[i] = T(0);
+          if constexpr (TRT) collide3_trt<T>(f, gd, m, dp0, k.c);
+          else collide3<T>(f, gd, m, dp0, k.c);
+          const uint32_t sb = Z.zo[1], vb = q.yo[1] + q.xo[1];
+#pragma unroll
+          for (int i = 0; i < 19; ++i) w.f.stb(i, sb, vb, f[i]);
+        }
+      }
+      constexpr int RING = RC::A - TX * TY;    // 2 (TX + 2) + 2 TY
+      for (int r = tid; r < RING; r += NT) {
+        int ly, lx;
+        if (r < RC::W) {
+          ly = 0;
+          lx = r;
+        } else if (r < 2 * RC::W) {
+          ly = RC::HT - 1;
+          lx = r - RC::W;
+        } else {
+          const int e = r - 2 * RC::W;
+          ly = 1 + (e >> 1);
+          lx = (e & 1) ? RC::W - 1 : 0;
+        }
+        T f[19], j[3];
+        Node3<T> m;
+        XY q;
+        node_c(ly, lx, f, m, j, q);
       }
     }
     __syncthreads();
-    // D: collide plane a-3 of the tile
+    // D: collide g of plane a-3 of the tile (grad p from the p planes
+    // a-4..a-2; u and F from the j that stage C kept) and store it
     const int zd = a - 3;
     if (zd >= z0 && zd < z1) {
       const ZP Z = zp_of<WS>(zd, g);
@@ -1122,12 +1165,11 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
         const int X = x0 + lx, Y = y0 + ly;
         if (X >= g.nx || Y >= g.ny) continue;
         const XY q = xy_of<WS>(X, Y, g);
-        T f[19], gg[19];
+        T gg[19];
         int32_t qs = 0;
 #pragma unroll
         for (int i = 0; i < 19; ++i) {
           const SrcB o = pull_b(i, Z, q);
-          f[i] = v.f.ldb(o.plane, o.sb, o.vb);
           if constexpr (FixedG<P>::value) {
             const int32_t word = v.g.ldb(o.plane, o.sb, o.vb);
             qs += word;
@@ -1136,27 +1178,23 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
             gg[i] = v.g.ldb(o.plane, o.sb, o.vb);
           }
         }
-        T S = f[0], j[3] = {T(0), T(0), T(0)};
-#pragma unroll
-        for (int i = 1; i < 19; ++i) {
-          S += f[i];
-          if (CX(i) != 0) j[0] += T(CX(i)) * f[i];
-          if (CY(i) != 0) j[1] += T(CY(i)) * f[i];
-          if (CZ(i) != 0) j[2] += T(CZ(i)) * f[i];
-        }
         T phi, mu, gph[3], gmu[3], lphi, lmu, p0, dp[3], lpp;
         lds_stencil<T, RA::W>(fm, f0, fp, (ly + 3) * RA::W + lx + 3, phi, gph[0], gph[1], gph[2],
                               lphi);
         lds_stencil<T, RB::W>(mm, m0, mp, (ly + 2) * RB::W + lx + 2, mu, gmu[0], gmu[1], gmu[2],
                               lmu);
         lds_stencil<T, RC::W>(qm, q0, qp, (ly + 1) * RC::W + lx + 1, p0, dp[0], dp[1], dp[2], lpp);
+        // the node state as stage C formed it (u, F from the same j and
+        // stencils; the pressure, which g does not use, left out)
+        const T j[3] = {jd[rr][0], jd[rr][1], jd[rr][2]};
         Node3<T> m;
-        macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
-        if constexpr (TRT) collide3_trt<T>(f, gg, m, dp, k.c);
-        else collide3<T>(f, gg, m, dp, k.c);
-        const uint32_t sb = Z.zo[1], vb = q.yo[1] + q.xo[1];
+        macro3<T>(phi, mu, gph, gmu, lmu, T(0), j, k, m);
+        T fd[19];
 #pragma unroll
-        for (int i = 0; i < 19; ++i) w.f.stb(i, sb, vb, f[i]);
+        for (int i = 0; i < 19; ++i) fd[i] = T(0);
+        if constexpr (TRT) collide3_trt<T>(fd, gg, m, dp, k.c);
+        else collide3<T>(fd, gg, m, dp, k.c);
+        const uint32_t sb = Z.zo[1], vb = q.yo[1] + q.xo[1];
         if constexpr (FixedG<P>::value) {
           // g_0 closes the node's Q2.29 sum at the pulled total
           const int er = (ly + 1) * RC::W + lx + 1;    // the node in the ring region
@@ -1183,6 +1221,13 @@ __global__ __launch_bounds__(FzThreads<P>::value) void k3_fused(Pop3<P> in, Pop3
           for (int i = 0; i < 19; ++i) w.g.stb(i, sb, vb, gg[i]);
         }
       }
+    }
+    // stage C's j of this iteration's plane is stage D's in the next
+#pragma unroll
+    for (int rr = 0; rr < 2; ++rr) {
+      jd[rr][0] = jn[rr][0];
+      jd[rr][1] = jn[rr][1];
+      jd[rr][2] = jn[rr][2];
     }
     __syncthreads();
     if constexpr (PHIQ) {
