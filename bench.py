@@ -152,7 +152,7 @@ def run_3d(steps: int, warmup: int):
     out = {"workload": "rt3d: Rayleigh-Taylor 256x256x256, walls in z, Atwood 0.5, "
                        "Re 3000, Pe 1000, W 4"}
     kernels = {"fp32": "k_zero_words (next step's phi words) + k3_fused (one z-sweep kernel)",
-               "fp64": "k3_phi, k3_mu, k3_macro, k3_collide"}
+               "fp64": "k3_phi, k3_mu, k3_pf (pressure, f collision), k3_g (g collision)"}
     # key, storage precision, TRT magic parameter of the f collision (0: BGK)
     for key, prec, magic in (("fp32", "fp32", 0.0), ("fp64", "fp64", 0.0),
                              ("fp32_trt", "fp32", 0.25)):

@@ -5,8 +5,9 @@
 // The step runs as four node-per-thread kernels, like the unfused
 // two-dimensional path: phi (the pulled g), mu (bulk part minus kappa times
 // the 19-point Laplacian of phi), the pressure (moments of the pulled f,
-// the stencils of phi and mu, force, velocity), and the collision with
-// streaming (grad p from the pressure field). Populations live in a pull
+// the stencils of phi and mu, force, velocity) with the collision of f,
+// which needs no grad p, and the collision of g (grad p from the pressure
+// field); or, in FP32, as one fused z-sweep kernel. Populations live in a pull
 // layout: slot (i, x) holds the post-collision population i produced at x,
 // so the pre-collision value at x is slot (i, x - c_i), or slot (opp(i), x)
 // when x - c_i lies beyond a wall.
@@ -657,7 +658,8 @@ __device__ __forceinline__ void node_state_r(const PopView<P, BIG>& v,
                                              const RowCtx& R, const Lane& L,
                                              const Coef3<typename PrecT<P>::T>& k,
                                              typename PrecT<P>::T f[19],
-                                             Node3<typename PrecT<P>::T>& m) {
+                                             Node3<typename PrecT<P>::T>& m,
+                                             typename PrecT<P>::T* jout = nullptr) {
   using T = typename PrecT<P>::T;
 #pragma unroll
   for (int i = 0; i < 19; ++i) {
@@ -676,6 +678,11 @@ __device__ __forceinline__ void node_state_r(const PopView<P, BIG>& v,
   stencil_r<T>(ph, R, L, phi, gph[0], gph[1], gph[2], lphi);
   stencil_r<T>(mf, R, L, mu, gmu[0], gmu[1], gmu[2], lmu);
   macro3<T>(phi, mu, gph, gmu, lmu, S, j, k, m);
+  if (jout) {
+    jout[0] = j[0];
+    jout[1] = j[1];
+    jout[2] = j[2];
+  }
 }
 
 struct MomentOut3 {
@@ -707,18 +714,59 @@ __global__ __launch_bounds__(256) void k3_macro(Pop3<P> in, const typename PrecT
   });
 }
 
+// The collision in two kernels, so that each population set is pulled once:
+// f's collision needs no grad p, so k3_pf collides f where it forms the
+// pressure (and keeps j for k3_g); k3_g, after every p is written, pulls g
+// and collides it with grad p and with u and F re-formed from j and the
+// phi, mu stencils (the same arithmetic as in k3_pf; the pressure, which g
+// does not use, is left out).
 template <int P, bool BIG, bool TRT = false>
-__global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
-                                                  const typename PrecT<P>::T* __restrict__ phi,
-                                                  const typename PrecT<P>::T* __restrict__ mu,
-                                                  const typename PrecT<P>::T* __restrict__ p,
-                                                  Coef3<typename PrecT<P>::T> k, Geom3 g,
-                                                  uint32_t nxc) {
+__global__ __launch_bounds__(256) void k3_pf(Pop3<P> in, Pop3<P> out,
+                                             const typename PrecT<P>::T* __restrict__ phi,
+                                             const typename PrecT<P>::T* __restrict__ mu,
+                                             typename PrecT<P>::T* __restrict__ p,
+                                             typename PrecT<P>::T* __restrict__ jx,
+                                             typename PrecT<P>::T* __restrict__ jy,
+                                             typename PrecT<P>::T* __restrict__ jz,
+                                             Coef3<typename PrecT<P>::T> k, Geom3 g, uint32_t nxc) {
   using T = typename PrecT<P>::T;
   const PopView<P, BIG> v(in), w(out);
   const Planes<T, false> ph(phi, g.Ns, 1), mf(mu, g.Ns, 1), pf(p, g.Ns, 1);
+  const Planes<T, false> jf[3] = {{jx, g.Ns, 1}, {jy, g.Ns, 1}, {jz, g.Ns, 1}};
   for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
-    T f[19], gg[19];
+    T f[19], j[3];
+    Node3<T> m;
+    node_state_r<P, BIG>(v, ph, mf, R, L, k, f, m, j);
+    const uint32_t row = R.rb[1][1], vo = L.xo[1];
+    pf.st(0, row, vo, m.p);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) jf[a].st(0, row, vo, j[a]);
+    const T dp0[3] = {T(0), T(0), T(0)};
+    T gd[19];
+#pragma unroll
+    for (int i = 0; i < 19; ++i) gd[i] = T(0);
+    if constexpr (TRT) collide3_trt<T>(f, gd, m, dp0, k.c);
+    else collide3<T>(f, gd, m, dp0, k.c);
+#pragma unroll
+    for (int i = 0; i < 19; ++i) w.f.st(i, row, vo, f[i]);
+  });
+}
+
+template <int P, bool BIG, bool TRT = false>
+__global__ __launch_bounds__(256) void k3_g(Pop3<P> in, Pop3<P> out,
+                                            const typename PrecT<P>::T* __restrict__ phi,
+                                            const typename PrecT<P>::T* __restrict__ mu,
+                                            const typename PrecT<P>::T* __restrict__ p,
+                                            const typename PrecT<P>::T* __restrict__ jx,
+                                            const typename PrecT<P>::T* __restrict__ jy,
+                                            const typename PrecT<P>::T* __restrict__ jz,
+                                            Coef3<typename PrecT<P>::T> k, Geom3 g, uint32_t nxc) {
+  using T = typename PrecT<P>::T;
+  const PopView<P, BIG> v(in), w(out);
+  const Planes<T, false> ph(phi, g.Ns, 1), mf(mu, g.Ns, 1), pf(p, g.Ns, 1);
+  const Planes<T, false> jf[3] = {{jx, g.Ns, 1}, {jy, g.Ns, 1}, {jz, g.Ns, 1}};
+  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
+    T gg[19];
     int32_t q = 0;
 #pragma unroll
     for (int i = 0; i < 19; ++i) {
@@ -731,15 +779,20 @@ __global__ __launch_bounds__(256) void k3_collide(Pop3<P> in, Pop3<P> out,
         gg[i] = v.g.ld(s.plane, s.row, s.vo);
       }
     }
+    const uint32_t row = R.rb[1][1], vo = L.xo[1];
+    const T j[3] = {jf[0].ld(0, row, vo), jf[1].ld(0, row, vo), jf[2].ld(0, row, vo)};
+    T phi, mu, gph[3], gmu[3], lphi, lmu;
+    stencil_r<T>(ph, R, L, phi, gph[0], gph[1], gph[2], lphi);
+    stencil_r<T>(mf, R, L, mu, gmu[0], gmu[1], gmu[2], lmu);
     Node3<T> m;
-    node_state_r<P, BIG>(v, ph, mf, R, L, k, f, m);
+    macro3<T>(phi, mu, gph, gmu, lmu, T(0), j, k, m);
     T p0, dp[3], lapp;
     stencil_r<T>(pf, R, L, p0, dp[0], dp[1], dp[2], lapp);
-    if constexpr (TRT) collide3_trt<T>(f, gg, m, dp, k.c);
-    else collide3<T>(f, gg, m, dp, k.c);
-    const uint32_t row = R.rb[1][1], vo = L.xo[1];
+    T fd[19];
 #pragma unroll
-    for (int i = 0; i < 19; ++i) w.f.st(i, row, vo, f[i]);
+    for (int i = 0; i < 19; ++i) fd[i] = T(0);
+    if constexpr (TRT) collide3_trt<T>(fd, gg, m, dp, k.c);
+    else collide3<T>(fd, gg, m, dp, k.c);
     if constexpr (FixedG<P>::value) {
       // g_0 closes the node's Q2.29 sum at the pulled total q
       int32_t rest = 0;
@@ -790,6 +843,7 @@ __global__ __launch_bounds__(256) void k3_phiq(Pop3<P_F32> in, int32_t* __restri
 // the 3 planes of warm-up at each segment end are
 // recomputed by the neighbouring workgroups. Results equal those of the
 // four-kernel path up to the rounding order of contracted multiply-adds.
+// (The four kernels split the two collisions the same way.)
 // Used for FP32 only, with stage A reading phi from the Q2.29 words that the
 // previous step scattered (PHIQ below): pulling g there over the halo made
 // the kernel read 453 B per node (those re-reads miss L2), against 252 with
@@ -1364,7 +1418,7 @@ struct lbm3_ctx {
   hipStream_t stream;
   char* pop[2];
   int cur;
-  char* fields;      // phi, mu, p (compute type, Ns each)
+  char* fields;      // phi, mu, p, jx, jy, jz (compute type, 8 bytes a node each)
   double* part;      // 5 per reduction block
   int nred;
   double* red_out;
@@ -1424,7 +1478,7 @@ Layout3 layout3(const lbm3_params* p) {
   L.pop0 = 0;
   L.pop1 = pb;
   L.fields = 2 * pb;
-  L.part = L.fields + up(3 * (size_t)g.Ns * 8);
+  L.part = L.fields + up(6 * (size_t)g.Ns * 8);   // phi, mu, p, j
   L.red = L.part + up((size_t)L.nred * 5 * 8);
   L.phiq = L.red + up(8 * 8);
   L.total = L.phiq + 2 * up((size_t)g.Ns * 4);
@@ -1512,15 +1566,26 @@ void launch_collide(lbm3_ctx* c) {
   using T = typename PrecT<P>::T;
   const Geom3& g = c->geom;
   Pop3<P> in{c->pop[c->cur], g.Ns}, out{c->pop[c->cur ^ 1], g.Ns};
-  const T* phi = (const T*)c->fields;
-  const T* mu = (const T*)(c->fields + g.Ns * 8);
-  const T* p = (const T*)(c->fields + 2 * g.Ns * 8);
-  if (c->prm.trt_magic > 0.0)
-    hipLaunchKernelGGL((k3_collide<P, BIG, true>), dim3(row_grid(g)), dim3(256), 0, c->stream,
-                       in, out, phi, mu, p, coef3<T>(c), g, chunks_x(g));
-  else
-    hipLaunchKernelGGL((k3_collide<P, BIG, false>), dim3(row_grid(g)), dim3(256), 0, c->stream,
-                       in, out, phi, mu, p, coef3<T>(c), g, chunks_x(g));
+  T* phi = (T*)c->fields;
+  T* mu = (T*)(c->fields + g.Ns * 8);
+  T* p = (T*)(c->fields + 2 * g.Ns * 8);
+  T* jx = (T*)(c->fields + 3 * g.Ns * 8);
+  T* jy = (T*)(c->fields + 4 * g.Ns * 8);
+  T* jz = (T*)(c->fields + 5 * g.Ns * 8);
+  if (c->prm.trt_magic > 0.0) {
+    hipLaunchKernelGGL((k3_pf<P, BIG, true>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, out,
+                       (const T*)phi, (const T*)mu, p, jx, jy, jz, coef3<T>(c), g, chunks_x(g));
+    hipLaunchKernelGGL((k3_g<P, BIG, true>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, out,
+                       (const T*)phi, (const T*)mu, (const T*)p, (const T*)jx, (const T*)jy,
+                       (const T*)jz, coef3<T>(c), g, chunks_x(g));
+  } else {
+    hipLaunchKernelGGL((k3_pf<P, BIG, false>), dim3(row_grid(g)), dim3(256), 0, c->stream, in,
+                       out, (const T*)phi, (const T*)mu, p, jx, jy, jz, coef3<T>(c), g,
+                       chunks_x(g));
+    hipLaunchKernelGGL((k3_g<P, BIG, false>), dim3(row_grid(g)), dim3(256), 0, c->stream, in,
+                       out, (const T*)phi, (const T*)mu, (const T*)p, (const T*)jx,
+                       (const T*)jy, (const T*)jz, coef3<T>(c), g, chunks_x(g));
+  }
 }
 
 // workgroups of the kernel that will run resident on the whole GPU at once
@@ -1605,17 +1670,13 @@ lbm_status step_p(lbm3_ctx* c, int64_t n) {
   if constexpr (P == P_F32)
     if (!(c->prm.flags & LBM_FLAG_UNFUSED)) return step_fused_p<P>(c, n);
   c->phiq_ok = false;
-  T* p = (T*)(c->fields + 2 * g.Ns * 8);
   const bool big = big3<P>(g);
   for (int64_t s = 0; s < n; ++s) {
     if (fields_p<P>(c) != hipSuccess) return LBM_EDEVICE;
-    if (big) {
-      launch_macro<P, true>(c, p, MomentOut3{});
+    if (big)
       launch_collide<P, true>(c);
-    } else {
-      launch_macro<P, false>(c, p, MomentOut3{});
+    else
       launch_collide<P, false>(c);
-    }
     if (hipGetLastError() != hipSuccess) return LBM_EDEVICE;
     c->cur ^= 1;
     c->t += 1;
