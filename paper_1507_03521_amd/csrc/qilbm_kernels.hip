@@ -1414,7 +1414,7 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
 }
 
 // Resident workgroups per CU (waves per SIMD with 4-wave workgroups): two
-// for FP32 and FP16 storage (LDS 78 KB / 53 KB, 242 / 181 VGPRs), one for
+// for FP32 and FP16 storage (LDS 78 KB / 53 KB, 245 / 216 VGPRs), one for
 // FP64 (LDS 156 KB: the ring of 18 binary64 words per node is 108 KB).
 template <int P> struct Fused2Waves { static constexpr int value = 2; };
 template <> struct Fused2Waves<P_F64> { static constexpr int value = 1; };
