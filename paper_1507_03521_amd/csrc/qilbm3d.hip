@@ -851,9 +851,11 @@ __global__ __launch_bounds__(256) void k3_phiq(Pop3<P_F32> in, int32_t* __restri
 // workgroup per CU, barrier-bound) the fused form was a quarter slower than
 // the four kernels.
 namespace fz {
-// 64 x 8 columns: 48 KB of LDS, so three workgroups per CU (at most 168
-// VGPRs); 64 x 16 (81 KB, two per CU) measured 4 % slower, 32 x 16 11 %
-constexpr int TX = 64, TY = 8;
+// 64 x 16 columns on 512 lanes (two core nodes per lane): 79 KB of LDS,
+// one workgroup (eight waves) per CU, 3 % faster than 64 x 8 columns on 256
+// lanes (48 KB, three per CU): the ring of the pressure stage is 16 % of
+// the tile instead of 29 %; 128 x 8 on 512 lanes 5 % slower
+constexpr int TX = 64, TY = 16;
 template <int H>
 struct Reg {
   static constexpr int W = TX + 2 * H, HT = TY + 2 * H, A = W * HT;
@@ -863,7 +865,7 @@ constexpr int RPHI = 5, RMU = 4, RP = 3;
 
 template <int P>
 struct FzThreads {
-  static constexpr int value = 256;
+  static constexpr int value = 512;
 };
 
 // node rounds of stages C and D unrolled together (loads of several nodes
