@@ -24,12 +24,13 @@
  *     lattice total of phi is an exact integer invariant); LBM_FP16_STORE is
  *     not offered in 3-D.
  *   Kernels: the populations in a pull layout. FP32 runs one fused kernel
- *     per step (a workgroup sweeps a 64 x 8 column tile along z, phi, mu and
- *     p in LDS plane rings; the collision scatters each g word to the node
- *     it streams to, accumulating the next step's phi as an exact Q2.29 sum
- *     in a workspace buffer); FP64, and FP32 with LBM_FLAG_UNFUSED, run four
- *     kernels per step (phi; mu; pressure; collision with streaming), one
- *     wave per 64-node run of a row. The two FP32 paths agree to rounding
+ *     per step (a workgroup sweeps a 64 x 16 column tile along z, phi, mu
+ *     and p in LDS plane rings; f collides where the pressure is formed, g
+ *     a plane later, and the g collision scatters each g word to the node it
+ *     streams to, accumulating the next step's phi as an exact Q2.29 sum in
+ *     a workspace buffer); FP64, and FP32 with LBM_FLAG_UNFUSED, run four
+ *     kernels per step (phi; mu; pressure with the collision of f; the
+ *     collision of g), one wave per 64-node run of a row. The two FP32 paths agree to rounding
  *     order and hold the same exact phi total.
  *   Memory, streams, errors: as in qilbm.h (caller-owned device workspace,
  *     asynchronous calls on the context's stream except lbm3_mass).
@@ -66,8 +67,9 @@ typedef struct {
 typedef struct lbm3_ctx lbm3_ctx;
 
 /* Device workspace bytes for these parameters (0 when invalid): two
- * population buffers, the phi/mu/p fields, reduction partials and two int32
- * buffers of the Q2.29 phi sums of the fused FP32 step. */
+ * population buffers, the phi/mu/p fields and the momentum j between the two
+ * collision kernels of the four-kernel form, reduction partials and two
+ * int32 buffers of the Q2.29 phi sums of the fused FP32 step. */
 size_t lbm3_workspace_bytes(const lbm3_params* params);
 
 /* Context at t = 0 from phi0_dev (FP64 [nz][ny][nx], device): f = 0 and
