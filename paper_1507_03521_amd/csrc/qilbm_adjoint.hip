@@ -938,6 +938,14 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     L.gpy[a & 3][lc] = nbr[J & 1].dpy;
     if (k.owns(a)) acc[AP_ALPHA] += double(nbr[J & 1].alpha);
   }
+  // The loads for the next iteration go out as soon as their registers are
+  // free: a wait on the memory counter also waits for every store issued
+  // before the load it needs, so a load issued behind the stores of D'
+  // would wait for them. hf and hg are free once A' has kept what it needs.
+  if (k.in(r, 1)) {
+    gather_post<T>(k, r, 0, hf);
+    gather_post<T>(k, r, 9, hg);
+  }
   __syncthreads();
   // B': pressure cotangent and the macroscopic transposes of row b
   if (k.in(b, 2)) {
@@ -984,6 +992,12 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   T he[9];
   if constexpr (!KeepGd<T>::value)
     if (k.owns(e)) gather_post<T>(k, e, 9, he);
+  // the next record row (rrec is free once stage 0 has put it in the rings)
+  if (k.in(r + d, 0)) {
+    const uint32_t ro = (uint32_t)(k.prow(r + d) * g.nx);
+#pragma unroll
+    for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
+  }
   // C': mu cotangent of row cm, then mu(phi)
   if (k.in(cm, 3)) {
     const T b_mu = m1[(J + 1) & 1] + stencil_Tl<T, true, true>(L.gmx, L.gmy, L.lmu, cm, lc, k.wall(cm));
@@ -1000,8 +1014,7 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     }
   }
   __syncthreads();
-  // D': phi cotangent of row e, g cotangents out; then the next iteration's
-  // gathers
+  // D': phi cotangent of row e, g cotangents out
   if (k.owns(e)) {
     const T b_phi = p3[(J + 1) & 1] + stencil_Tl<T, true, true>(L.grx, L.gry, L.lph, e, lc, k.wall(e));
     const uint32_t ro = (uint32_t)(e * g.nx);
@@ -1009,15 +1022,6 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     for (int i = 0; i < 9; ++i)
       k.hout.st(9 + i, ro, (uint32_t)k.x,
                 (KeepGd<T>::value ? gdr[(J + 1) & 3][i] : he[i] * (T(1) - c.inv_tau_g)) + b_phi);
-  }
-  if (k.in(r, 1)) {
-    gather_post<T>(k, r, 0, hf);
-    gather_post<T>(k, r, 9, hg);
-  }
-  if (k.in(r + d, 0)) {
-    const uint32_t ro = (uint32_t)(k.prow(r + d) * g.nx);
-#pragma unroll
-    for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
   }
 }
 
