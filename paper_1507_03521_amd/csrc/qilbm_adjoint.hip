@@ -757,6 +757,35 @@ struct PlaneArr {
   __device__ __forceinline__ void st(int plane, uint32_t elem_row, uint32_t col, T v) const {
     buf_st<T>(v, rs(plane), col * (uint32_t)sizeof(T), so(plane, elem_row));
   }
+  // Element col of row elem_row / nx of plane, written only by lanes with
+  // ok set. Every lane issues the store; the other lanes' offset lies 2 GiB
+  // beyond the range of the descriptor, where the hardware drops a store.
+  // No branch then separates the lanes that write from those that do not, so
+  // the compiler's count of memory operations in flight stays exact across
+  // the stores (with a branch it takes the path without them, and the next
+  // wait for a load waits for the stores as well). The descriptors: not BIG,
+  // one per group of 9 planes (the f and the g cotangents; under 2 GiB each
+  // as the 18 planes span less than 4 GiB); BIG, one per plane and row.
+  __device__ __forceinline__ void init_halves() {
+    if constexpr (!BIG)
+      for (int h = 0; h < 2; ++h)
+        half[h] = __builtin_amdgcn_make_buffer_rsrc(base + (int64_t)(9 * h) * ps, 0,
+                                                    (int)(9 * ps), BUF_WORD3);
+  }
+  __device__ __forceinline__ void st_if(bool ok, int plane, uint32_t elem_row, uint32_t col,
+                                        uint32_t nx, T v) const {
+    const uint32_t vo = col * (uint32_t)sizeof(T) + (ok ? 0u : 0x80000000u);
+    if constexpr (!BIG) {
+      buf_st<T>(v, half[plane >= 9], vo,
+                (uint32_t)(plane % 9) * ps + elem_row * (uint32_t)sizeof(T));
+    } else {
+      const __amdgpu_buffer_rsrc_t rr = __builtin_amdgcn_make_buffer_rsrc(
+          base + (int64_t)plane * ps + (int64_t)elem_row * sizeof(T), 0, (int)(nx * sizeof(T)),
+          BUF_WORD3);
+      buf_st<T>(v, rr, vo, 0u);
+    }
+  }
+  __amdgpu_buffer_rsrc_t half[2];
 };
 
 template <typename T, bool BIG>
@@ -774,6 +803,9 @@ struct AdjCtx {
   __device__ __forceinline__ bool owns(int v) const {
     return act && lc >= AH && lc < wi + AH && v >= y0 && v < y1;
   }
+  // v if the tile owns row v, else its first row (a row of the lattice for
+  // the descriptor of a store that no lane makes)
+  __device__ __forceinline__ int own_row(int v) const { return v >= y0 && v < y1 ? v : y0; }
   // physical row of virtual row v (the halo reaches a few rows beyond the
   // lattice: a short uniform loop instead of a division)
   __device__ __forceinline__ int prow(int v) const {
@@ -948,6 +980,7 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   }
   __syncthreads();
   // B': pressure cotangent and the macroscopic transposes of row b
+  T o_S = T(0), o_jx = T(0), o_jy = T(0);
   if (k.in(b, 2)) {
     const NodeBar<T>& nb = nbr[(J + 1) & 1];
     const T b_p = nb.p + stencil_Tl<T, true, false>(L.gpx, L.gpy, nullptr, b, lc, k.wall(b));
@@ -981,15 +1014,20 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
     L.gry[b & 3][lc] = c.drho * b_dry;
     p2[J & 1] = b_phi + c.drho * b_rho;
     m1[J & 1] = nb.mu;
-    if (k.owns(b)) {
-      const uint32_t ro = (uint32_t)(b * g.nx);
-      fbar_out([&](int i, T v) { k.hout.st(i, ro, (uint32_t)k.x, v); }, fdr[(J + 1) & 1], b_S,
-               b_jx, b_jy);
-      acc[AP_LAMBDA] += double(b_D) * double(lapmu);
-    }
+    o_S = b_S;
+    o_jx = b_jx;
+    o_jy = b_jy;
+    if (k.owns(b)) acc[AP_LAMBDA] += double(b_D) * double(lapmu);
+  }
+  {
+    // the f cotangents of row b out, from every lane (st_if)
+    const uint32_t ro = (uint32_t)(k.own_row(b) * g.nx);
+    const bool ok = k.owns(b);
+    fbar_out([&](int i, T v) { k.hout.st_if(ok, i, ro, (uint32_t)k.x, (uint32_t)g.nx, v); },
+             fdr[(J + 1) & 1], o_S, o_jx, o_jy);
   }
   __syncthreads();
-  T he[9];
+  T he[9] = {};
   if constexpr (!KeepGd<T>::value)
     if (k.owns(e)) gather_post<T>(k, e, 9, he);
   // the next record row (rrec is free once stage 0 has put it in the rings)
@@ -1015,13 +1053,17 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   }
   __syncthreads();
   // D': phi cotangent of row e, g cotangents out
-  if (k.owns(e)) {
-    const T b_phi = p3[(J + 1) & 1] + stencil_Tl<T, true, true>(L.grx, L.gry, L.lph, e, lc, k.wall(e));
-    const uint32_t ro = (uint32_t)(e * g.nx);
+  {
+    const bool ok = k.owns(e);
+    T b_phi = T(0);
+    if (ok)
+      b_phi = p3[(J + 1) & 1] + stencil_Tl<T, true, true>(L.grx, L.gry, L.lph, e, lc, k.wall(e));
+    const uint32_t ro = (uint32_t)(k.own_row(e) * g.nx);
 #pragma unroll
     for (int i = 0; i < 9; ++i)
-      k.hout.st(9 + i, ro, (uint32_t)k.x,
-                (KeepGd<T>::value ? gdr[(J + 1) & 3][i] : he[i] * (T(1) - c.inv_tau_g)) + b_phi);
+      k.hout.st_if(ok, 9 + i, ro, (uint32_t)k.x, (uint32_t)g.nx,
+                    (KeepGd<T>::value ? gdr[(J + 1) & 3][i] : he[i] * (T(1) - c.inv_tau_g)) +
+                        b_phi);
   }
 }
 
@@ -1038,6 +1080,7 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
   k.rec.init(rec, g.Ns, 6);
   k.hin.init(hin, g.Ns, 18);
   k.hout.init(hout, g.Ns, 18);
+  k.hout.init_halves();
   k.c = c;
   k.g = g;
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
