@@ -930,6 +930,21 @@ struct FwdState {
 // full; the values are the same).
 template <typename T> struct KeepGd { static constexpr bool value = sizeof(T) == 4; };
 
+// Record row v (loaded into rrec) into the LDS rings.
+template <typename T, bool BIG>
+__device__ __forceinline__ void put_record(const AdjCtx<T, BIG>& k, int v, AdjLds<T>& L,
+                                           const T (&rrec)[6]) {
+  if (k.in(v, 0)) {
+    const int lc = k.lc;
+    L.phi[v & 7][lc] = rrec[R_PHI];
+    L.mu[v & 3][lc] = rrec[R_MU];
+    L.p[v & 3][lc] = rrec[R_P];
+    L.sj[v & 3][0][lc] = rrec[R_S];
+    L.sj[v & 3][1][lc] = rrec[R_JX];
+    L.sj[v & 3][2][lc] = rrec[R_JY];
+  }
+}
+
 template <typename T, bool BIG, int J>
 __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<T>& L, T (&rrec)[6],
                                          T (&hf)[9], T (&hg)[9], NodeBar<T> (&nbr)[2],
@@ -940,15 +955,8 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   const Coef<T>& c = k.c;
   const int lc = k.lc, d = k.d;
   const int a = r - d, b = r - 2 * d, cm = r - 3 * d, e = r - 4 * d;
-  // 0: record row r into the rings
-  if (k.in(r, 0)) {
-    L.phi[r & 7][lc] = rrec[R_PHI];
-    L.mu[r & 3][lc] = rrec[R_MU];
-    L.p[r & 3][lc] = rrec[R_P];
-    L.sj[r & 3][0][lc] = rrec[R_S];
-    L.sj[r & 3][1][lc] = rrec[R_JX];
-    L.sj[r & 3][2][lc] = rrec[R_JY];
-  }
+  // (row r of the record is in the rings: put there at the end of the
+  // previous iteration, or before the first)
   __syncthreads();
   // A': collision transpose of row a
   if (k.in(a, 1)) {
@@ -1030,7 +1038,7 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
   T he[9] = {};
   if constexpr (!KeepGd<T>::value)
     if (k.owns(e)) gather_post<T>(k, e, 9, he);
-  // the next record row (rrec is free once stage 0 has put it in the rings)
+  // the next record row (rrec is free: row r is in the rings)
   if (k.in(r + d, 0)) {
     const uint32_t ro = (uint32_t)(k.prow(r + d) * g.nx);
 #pragma unroll
@@ -1065,6 +1073,10 @@ __device__ __forceinline__ void adj_iter(const AdjCtx<T, BIG>& k, int r, AdjLds<
                     (KeepGd<T>::value ? gdr[(J + 1) & 3][i] : he[i] * (T(1) - c.inv_tau_g)) +
                         b_phi);
   }
+  // record row r + d into the rings for the next iteration (here rather than
+  // at the top of the next one, so that its wait for the record loads is
+  // counted in straight-line code and leaves D''s stores in flight)
+  put_record(k, r + d, L, rrec);
 }
 
 template <typename T>
@@ -1111,6 +1123,7 @@ __global__ __launch_bounds__(ANT, AdjWaves<T>::value) void k_adj_fused(
 #pragma unroll
       for (int q = 0; q < 6; ++q) rrec[q] = k.rec.ld(q, ro, (uint32_t)k.x);
     }
+    put_record(k, r0, L, rrec);
     for (int it = 0; it < nit; it += 4) {
       adj_iter<T, BIG, 0>(k, r0 + k.d * (it + 0), L, rrec, hf, hg, nbr, fst, fdr, gdr, p2, m1,
                             p3, acc);
