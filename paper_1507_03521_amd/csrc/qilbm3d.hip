@@ -638,17 +638,6 @@ __global__ __launch_bounds__(256) void k3_phi(Pop3<P> in, typename PrecT<P>::T* 
   });
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k3_mu(const T* __restrict__ phi, T* __restrict__ mu,
-                                             Coef3<T> k, Geom3 g, uint32_t nxc) {
-  const Planes<T, false> ph(phi, g.Ns, 1), out(mu, g.Ns, 1);
-  for_rows<sizeof(T)>(g, nxc, [&](const RowCtx& R, const Lane& L) {
-    T c0, gx, gy, gz, lp;
-    stencil_r<T>(ph, R, L, c0, gx, gy, gz, lp);
-    out.st(0, R.rb[1][1], L.xo[1], mu_bulk(c0, k.c) - k.c.kappa * lp);
-  });
-}
-
 // Pulled f of the lane's node and the node state from it and the phi, mu
 // fields.
 template <int P, bool BIG>
@@ -983,6 +972,60 @@ __device__ __forceinline__ void lds_stencil(const T* pm, const T* p0, const T* p
   gy *= T(3);
   gz *= T(3);
   lp *= T(6);
+}
+
+// mu = mu_bulk(phi) - kappa lap(phi) (Sec. II, the chemical potential) of a
+// 64 x 4 column tile over a segment of MZ_ZS planes: the phi planes of the
+// tile and the ring of nodes around it go through a ring of four LDS planes,
+// so each phi value is read from memory about once instead of once per
+// stencil neighbour. Beyond a wall the mirrored ghost plane is the wall plane
+// itself; x, y and (without walls) z are periodic.
+constexpr int MZ_TX = 64, MZ_TY = 4, MZ_W = MZ_TX + 2, MZ_A = MZ_W * (MZ_TY + 2), MZ_ZS = 32;
+
+__host__ __device__ inline int mu_tiles_xy(const Geom3& g) {
+  return ((g.nx + MZ_TX - 1) / MZ_TX) * ((g.ny + MZ_TY - 1) / MZ_TY);
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k3_mu(const T* __restrict__ phi, T* __restrict__ mu,
+                                             Coef3<T> k, Geom3 g) {
+  __shared__ T ring[4][MZ_A];
+  const int ntx = (g.nx + MZ_TX - 1) / MZ_TX, nxy = mu_tiles_xy(g);
+  const int b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+  const int seg = b / nxy, txy = b - seg * nxy;
+  const int ty = txy / ntx, tx = txy - ty * ntx;
+  const int x0 = tx * MZ_TX, y0 = ty * MZ_TY;
+  const int z0 = seg * MZ_ZS, z1 = min(g.nz, z0 + MZ_ZS);
+  const int t = threadIdx.x, lx = t & 63, ly = t >> 6;
+  const int x = x0 + lx, y = y0 + ly;
+  const uint32_t nx = (uint32_t)g.nx, ny = (uint32_t)g.ny;
+  // plane zz of the sweep (z0 - 1 .. z1) into its ring slot
+  auto load_plane = [&](int zz) {
+    int zp = zz;
+    if (zp < 0) zp = g.walls ? 0 : zp + g.nz;
+    else if (zp >= g.nz) zp = g.walls ? g.nz - 1 : zp - g.nz;
+    T* dst = ring[zz & 3];
+    for (int e = t; e < MZ_A; e += 256) {
+      const int ey = e / MZ_W, ex = e - ey * MZ_W;
+      // the halo can reach more than one period on narrow lattices
+      const int gx = (x0 - 1 + ex + g.nx) % g.nx, gy = (y0 - 1 + ey + g.ny) % g.ny;
+      dst[e] = phi[((uint32_t)zp * ny + (uint32_t)gy) * nx + (uint32_t)gx];
+    }
+  };
+  load_plane(z0 - 1);
+  load_plane(z0);
+  // plane z + 1 goes into the slot of z - 3, which no lane reads after the
+  // barrier of the iteration before: one barrier per plane
+  for (int z = z0; z < z1; ++z) {
+    load_plane(z + 1);
+    __syncthreads();
+    if (x < g.nx && y < g.ny) {
+      T c0, gx, gy, gz, lp;
+      lds_stencil<T, MZ_W>(ring[(z - 1) & 3], ring[z & 3], ring[(z + 1) & 3],
+                           (ly + 1) * MZ_W + lx + 1, c0, gx, gy, gz, lp);
+      mu[((uint32_t)z * ny + (uint32_t)y) * nx + (uint32_t)x] = mu_bulk(c0, k.c) - k.c.kappa * lp;
+    }
+  }
 }
 
 // PHIQ (FP32 only): stage A reads phi as the Q2.29 sum phiq_in of the
@@ -1548,8 +1591,9 @@ hipError_t fields_p(lbm3_ctx* c) {
   else
     hipLaunchKernelGGL((k3_phi<P, false>), dim3(row_grid(g)), dim3(256), 0, c->stream, in, phi, g,
                        nxc);
-  hipLaunchKernelGGL(k3_mu<T>, dim3(row_grid(g)), dim3(256), 0, c->stream, (const T*)phi, mu,
-                     coef3<T>(c), g, nxc);
+  const int64_t mu_blocks = (int64_t)mu_tiles_xy(g) * ((g.nz + MZ_ZS - 1) / MZ_ZS);
+  hipLaunchKernelGGL(k3_mu<T>, dim3((unsigned)mu_blocks), dim3(256), 0, c->stream,
+                     (const T*)phi, mu, coef3<T>(c), g);
   return hipGetLastError();
 }
 
