@@ -91,6 +91,15 @@ constexpr double GQ_D = 536870912.0;
 __host__ __device__ constexpr float HQ(int i) {
   return i == 0 ? 16384.0f : (i <= 4 ? 4096.0f : 1024.0f);
 }
+// The Q2.29 word of a stored binary16 g_i: the half times HQ(i), exact in
+// binary32, truncated toward zero (a fraction remains only for halves below
+// 1 / HQ(i), i.e. g below one Q2.29 step). Every kernel, and the host-side
+// total of the tests, maps a half this one way, so g_0 = phi_q - sum of the
+// other words keeps the lattice total an exact integer invariant; truncation
+// is one conversion where rounding to nearest takes two.
+__device__ __forceinline__ int32_t q_half(__half h, int i) {
+  return (int32_t)(__half2float(h) * HQ(i));
+}
 
 // Bytes of one population buffer (18 planes).
 __host__ __device__ inline int64_t pop_bytes(int P, int64_t Ns) {
@@ -176,7 +185,7 @@ struct Pop {
       return *reinterpret_cast<const int32_t*>(word_at(k, idx));
     } else {
       if (k == 9) return at<int32_t>(base + 2 * Ns, idx);
-      return __float2int_rn(__half2float(half_ld(half_at(k, idx))) * HQ(dir(k)));
+      return q_half(half_ld(half_at(k, idx)), dir(k));
     }
   }
   // stores v into plane k; for g planes in the fixed-point modes returns the
@@ -201,7 +210,7 @@ struct Pop {
       }
       const __half h = __float2half_rn(v * H_SCALE(dir(k)));
       *reinterpret_cast<__half*>(half_at(k, idx)) = h;
-      return k < 9 ? 0 : __float2int_rn(__half2float(h) * HQ(dir(k)));
+      return k < 9 ? 0 : q_half(h, dir(k));
     }
   }
   // stores the binary64 value v into plane k with a single rounding to the

@@ -487,7 +487,7 @@ struct BufPop {
   __device__ __forceinline__ static int32_t q_g(R w) {
     if constexpr (P == P_F32) return (int32_t)(uint32_t)(w >> 32);
     else if constexpr (I == 0) return (int32_t)w;
-    else return __float2int_rn(__half2float(__builtin_bit_cast(__half, (uint16_t)(w >> 16))) * HQ(I));
+    else return q_half(__builtin_bit_cast(__half, (uint16_t)(w >> 16)), I);
   }
   template <int I>
   __device__ __forceinline__ void st_f(T v, uint32_t elem_row, uint32_t col) const {
@@ -510,7 +510,7 @@ struct BufPop {
     } else {
       const __half h = __float2half_rn(v * H_SCALE(I));
       buf_st<GR>(h, g_rsrc<I>(), col * (uint32_t)sizeof(GR), so);
-      return __float2int_rn(__half2float(h) * HQ(I));
+      return q_half(h, I);
     }
   }
   // paired layouts: stores f_I and g_I as one word; returns the Q2.29
@@ -527,7 +527,7 @@ struct BufPop {
     const uint32_t w = (uint32_t)__builtin_bit_cast(uint16_t, hf) |
                        ((uint32_t)__builtin_bit_cast(uint16_t, hg) << 16);
     buf_st<GR>(w, g_rsrc<I>(), col * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
-    return __float2int_rn(__half2float(hg) * HQ(I));
+    return q_half(hg, I);
   }
   // FP32: stores f_I and the Q2.29 word q of g_I as one 64-bit word
   template <int I>
@@ -1058,7 +1058,7 @@ __device__ __forceinline__ void pack_row(const typename PrecT<P>::T f[9],
     for (int i = 1; i < 9; ++i) {
       const __half hf = __float2half_rn(f[i] * H_SCALE(i));
       const __half hg = __float2half_rn(gg[i] * H_SCALE(i));
-      rest += __float2int_rn(__half2float(hg) * HQ(i));
+      rest += q_half(hg, i);
       w[i] = (uint32_t)__builtin_bit_cast(uint16_t, hf) |
              ((uint32_t)__builtin_bit_cast(uint16_t, hg) << 16);
     }

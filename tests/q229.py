@@ -23,5 +23,6 @@ def q229_total(raw, precision, nx, ny):
     halves = raw[6 * Ns:38 * Ns].view(torch.float16).view(8, Ns, 2)[:, :N, 1].float()
     for i in range(8):
         scale = 4096.0 if i < 4 else 1024.0
-        tot += int(torch.round(halves[i] * scale).to(torch.int64).sum())
+        # the kernels' mapping: the half times 2^29 / scale, truncated
+        tot += int(torch.trunc(halves[i] * scale).to(torch.int64).sum())
     return tot
