@@ -382,7 +382,8 @@ template <> struct BufT<P_F32> { using F = float; using G0 = int32_t; using GR =
 template <> struct BufT<P_F16> { using F = __half; using G0 = int32_t; using GR = uint32_t; using R = uint32_t; };
 
 // BIG: a group of population planes (f_0..8 or g_1..8) spans 4 GiB or more,
-// beyond the 32-bit range of one descriptor; every access then builds a
+// beyond the 32-bit range of one descriptor (FP64: more than 2 GiB, see
+// fused_big); every access then builds a
 // descriptor for its own plane (scalar work only) and the scalar offset
 // holds the row alone.
 template <int P, bool BIG = false>
@@ -489,19 +490,23 @@ struct BufPop {
     else if constexpr (I == 0) return (int32_t)w;
     else return q_half(__builtin_bit_cast(__half, (uint16_t)(w >> 16)), I);
   }
+  // vb (stores): added to the lane's vector offset; 0x80000000 puts the
+  // store beyond a descriptor of at most 2 GiB, where the hardware drops it
   template <int I>
-  __device__ __forceinline__ void st_f(T v, uint32_t elem_row, uint32_t col) const {
+  __device__ __forceinline__ void st_f(T v, uint32_t elem_row, uint32_t col,
+                                       uint32_t vb = 0) const {
     F w;
     if constexpr (P == P_F16) w = __float2half_rn(v * H_SCALE(I));
     else w = v;
-    buf_st<F>(w, f_rsrc<I>(), col * (uint32_t)sizeof(F), f_soff<I>(elem_row));
+    buf_st<F>(w, f_rsrc<I>(), col * (uint32_t)sizeof(F) + vb, f_soff<I>(elem_row));
   }
   // stores g_I (I >= 1); returns its Q2.29 contribution in the fixed-point modes
   template <int I>
-  __device__ __forceinline__ int32_t st_g(T v, uint32_t elem_row, uint32_t col) const {
+  __device__ __forceinline__ int32_t st_g(T v, uint32_t elem_row, uint32_t col,
+                                          uint32_t vb = 0) const {
     const uint32_t so = g_soff<I>(elem_row);
     if constexpr (P == P_F64) {
-      buf_st<GR>(v, g_rsrc<I>(), col * (uint32_t)sizeof(GR), so);
+      buf_st<GR>(v, g_rsrc<I>(), col * (uint32_t)sizeof(GR) + vb, so);
       return 0;
     } else if constexpr (P == P_F32) {
       const int32_t q = __float2int_rn(v * GQ);
@@ -535,8 +540,9 @@ struct BufPop {
     const uint64_t w = (uint64_t)__builtin_bit_cast(uint32_t, fv) | ((uint64_t)(uint32_t)q << 32);
     buf_st<GR>(w, g_rsrc<I>(), col * (uint32_t)sizeof(GR), g_soff<I>(elem_row));
   }
-  __device__ __forceinline__ void st_g0(T v, int32_t q, uint32_t elem_row, uint32_t col) const {
-    if constexpr (P == P_F64) buf_st<G0>(v, rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
+  __device__ __forceinline__ void st_g0(T v, int32_t q, uint32_t elem_row, uint32_t col,
+                                        uint32_t vb = 0) const {
+    if constexpr (P == P_F64) buf_st<G0>(v, rg0, col * (uint32_t)sizeof(G0) + vb, elem_row * (uint32_t)sizeof(G0));
     else buf_st<G0>(q, rg0, col * (uint32_t)sizeof(G0), elem_row * (uint32_t)sizeof(G0));
   }
 };
@@ -624,10 +630,11 @@ __device__ __forceinline__ int32_t store_pairs(const FusedCtx<P, BIG>& k, uint32
 
 template <int P, bool BIG, int I = 1>
 __device__ __forceinline__ int32_t store_g_rest(const FusedCtx<P, BIG>& k, uint32_t row,
-                                              const typename PrecT<P>::T gg[9]) {
+                                              const typename PrecT<P>::T gg[9],
+                                              uint32_t vb = 0) {
   if constexpr (I < 9) {
-    const int32_t q = k.out.template st_g<I>(gg[I], row, k.col[1]);
-    return q + store_g_rest<P, BIG, I + 1>(k, row, gg);
+    const int32_t q = k.out.template st_g<I>(gg[I], row, k.col[1], vb);
+    return q + store_g_rest<P, BIG, I + 1>(k, row, gg, vb);
   } else {
     return 0;
   }
@@ -635,10 +642,10 @@ __device__ __forceinline__ int32_t store_g_rest(const FusedCtx<P, BIG>& k, uint3
 
 template <int P, bool BIG, int I = 0>
 __device__ __forceinline__ void store_f(const FusedCtx<P, BIG>& k, uint32_t row,
-                                        const typename PrecT<P>::T f[9]) {
+                                        const typename PrecT<P>::T f[9], uint32_t vb = 0) {
   if constexpr (I < 9) {
-    k.out.template st_f<I>(f[I], row, k.col[1]);
-    store_f<P, BIG, I + 1>(k, row, f);
+    k.out.template st_f<I>(f[I], row, k.col[1], vb);
+    store_f<P, BIG, I + 1>(k, row, f, vb);
   }
 }
 
@@ -647,7 +654,8 @@ __device__ __forceinline__ void store_f(const FusedCtx<P, BIG>& k, uint32_t row,
 template <int P, bool BIG>
 __device__ __forceinline__ void store_row(const FusedCtx<P, BIG>& k, uint32_t row,
                                           const typename PrecT<P>::T f[9],
-                                          const typename PrecT<P>::T gg[9], int32_t phi_q) {
+                                          const typename PrecT<P>::T gg[9], int32_t phi_q,
+                                          uint32_t vb = 0) {
   if constexpr (P == P_F16) {
     k.out.template st_f<0>(f[0], row, k.col[1]);
     const int32_t rest = store_pairs<P, BIG>(k, row, f, gg);
@@ -656,9 +664,9 @@ __device__ __forceinline__ void store_row(const FusedCtx<P, BIG>& k, uint32_t ro
     const int32_t rest = store_pairs<P, BIG>(k, row, f, gg);
     k.out.template st_pair_q<0>(f[0], phi_q - rest, row, k.col[1]);
   } else {
-    store_f<P, BIG>(k, row, f);
-    const int32_t rest = store_g_rest<P, BIG>(k, row, gg);
-    k.out.st_g0(gg[0], phi_q - rest, row, k.col[1]);
+    store_f<P, BIG>(k, row, f, vb);
+    const int32_t rest = store_g_rest<P, BIG>(k, row, gg, vb);
+    k.out.st_g0(gg[0], phi_q - rest, row, k.col[1], vb);
   }
 }
 
@@ -1145,9 +1153,10 @@ __device__ __forceinline__ void row_pack(const typename PrecT<P>::T f[9],
 template <int P, bool BIG>
 __device__ __forceinline__ void store_node2(const FusedCtx<P, BIG>& k, uint32_t rowoff,
                                             const typename PrecT<P>::T f[9],
-                                            const typename PrecT<P>::T g[9], int32_t phi_q) {
+                                            const typename PrecT<P>::T g[9], int32_t phi_q,
+                                            uint32_t vb = 0) {
   if constexpr (P == P_F64) {
-    store_row<P, BIG>(k, rowoff, f, g, 0);
+    store_row<P, BIG>(k, rowoff, f, g, 0, vb);
   } else {
     Row<P> o;
     pack_row<P>(f, g, phi_q, o.w, o.f0);
@@ -1401,7 +1410,25 @@ __device__ __forceinline__ void fused2_iter(const FusedCtx<P, BIG>& k, int r, in
   // D2: row r - 8d to memory
   {
     const int cr = r2 - 3 * d;
-    if (in_stage(k, cr, 7)) {
+    if constexpr (P == P_F64 && !BIG) {
+      // Every lane issues the 18 stores; lanes and rows outside the stage
+      // offset theirs 2 GiB beyond the descriptors (each spans at most
+      // 2 GiB here, fused_big), where the hardware drops them. With the
+      // stores under a branch the compiler's count of memory operations in
+      // flight is merged from the path without them, and the next
+      // iteration's wait for the loads of row r + d would also wait for
+      // these stores (one wave per SIMD: nothing else covers it).
+      const bool ok = in_stage(k, cr, 7);
+      T f[9], gg[9];
+      int32_t phi_q = 0;
+      if (ok) {
+        row_phi<P2>(rb2[(J + 1) & 3], phi_q);
+        row_unpack<P2>(rb2[(J + 1) & 3], f, gg);
+        stage_collide<T, NT, TRT>(L.s2, cr, g, lc, k.c, nd2[(J + 1) & 1], f, gg);
+      }
+      const int crs = cr >= 0 && cr < g.ny ? cr : 0;
+      store_node2<P, BIG>(k, (uint32_t)(crs * g.nx), f, gg, phi_q, ok ? 0u : 0x80000000u);
+    } else if (in_stage(k, cr, 7)) {
       T f[9], gg[9];
       int32_t phi_q;
       row_phi<P2>(rb2[(J + 1) & 3], phi_q);
@@ -1581,11 +1608,15 @@ FusedShape fused_shape(const Geom& g, int seg_rows, int resident) {
   return sh;
 }
 
+// FP64: also where a group spans more than 2 GiB, so that the two-step
+// kernel's stores beyond the range of a group descriptor (2 GiB past the
+// lane's offset) are dropped (the g_0 plane's descriptor is smaller still).
 template <int P>
 bool fused_big(const Geom& g) {
   const int64_t f_group = (P == P_F16 ? 1 : 9) * g.Ns * (int64_t)sizeof(typename BufT<P>::F);
   const int64_t g_group = (P == P_F32 ? 9 : 8) * g.Ns * (int64_t)sizeof(typename BufT<P>::GR);
-  return f_group > (int64_t)UINT32_MAX || g_group > (int64_t)UINT32_MAX;
+  const int64_t lim = P == P_F64 ? ((int64_t)1 << 31) : (int64_t)UINT32_MAX;
+  return f_group > lim || g_group > lim;
 }
 
 template <int P>
