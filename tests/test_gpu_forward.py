@@ -461,13 +461,17 @@ def test_reduced_precision_conserves_mass_exactly(precision, bc):
 
 # Lattices whose population plane groups exceed the 4 GiB range of one
 # buffer descriptor (the fused kernel then addresses every plane with its own
-# descriptor): nodes just above the threshold for each storage precision.
+# descriptor): nodes just above the threshold for each storage precision. FP64
+# takes that path from 2 GiB on (its two-step kernel drops the stores of lanes
+# outside the stage 2 GiB beyond a group descriptor), so it also has a case
+# between the two limits.
 # The two paths evaluate the same arithmetic in different orders, so they
 # agree to rounding, not bitwise. Tolerances (f, g) relative to the largest
 # magnitude: FP64 as the one-step oracle parity; FP32 and FP16 storage as the
 # full-size tests that start from the equilibrium initial state, where f is
 # small and formed by cancellation (an addressing error would be O(1)).
-BIG_SHAPES = [("fp64", 4000, 15000, (1e-12, 1e-12)), ("fp32", 8000, 15000, (2e-3, 1e-6)),
+BIG_SHAPES = [("fp64", 4000, 15000, (1e-12, 1e-12)), ("fp64", 4000, 7500, (1e-12, 1e-12)),
+              ("fp32", 8000, 15000, (2e-3, 1e-6)),
               ("fp16", 10000, 14000, (4e-3, 1e-5)),
               ("fp64", 300, 41, (1e-12, 1e-12)), ("fp32", 300, 41, (2e-3, 1e-6)),
               ("fp16", 300, 41, (4e-3, 1e-5))]
@@ -476,8 +480,9 @@ BIG_SHAPES = [("fp64", 4000, 15000, (1e-12, 1e-12)), ("fp32", 8000, 15000, (2e-3
 @pytest.mark.parametrize("per_pass", [1, 2])
 @pytest.mark.parametrize("precision,nx,ny,tol", BIG_SHAPES)
 def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol, per_pass):
-    """At sizes where nine planes of populations span more than 4 GiB (and,
-    for comparison, at a small size), two fused steps (walls and gravity on;
+    """At sizes where a group of population planes spans more than one
+    descriptor's range (4 GiB; FP64 2 GiB), and, for comparison, at a small
+    size, two fused steps (walls and gravity on;
     two one-step launches or one two-step launch) agree with two steps of
     the unfused kernels, which address memory with 64-bit pointers; in the
     fixed-point modes both conserve the exact integer total of g."""
@@ -501,7 +506,8 @@ def test_fused_large_lattice_matches_unfused(precision, nx, ny, tol, per_pass):
         # word planes (FP32) or the eight 32-bit ones (FP16 storage)
         group = {"fp64": 9 * 8, "fp32": 9 * 8, "fp16": 8 * 4}[precision] * Ns
         # the per-plane addressing is in use at the large sizes only
-        assert (group > 2**32 - 1) == (nx * ny > 10**7)
+        limit = 2**31 if precision == "fp64" else 2**32 - 1
+        assert (group > limit) == (nx * ny > 10**7)
         if precision != "fp64":
             q0 = _q229_total(lat.save_raw(), precision, nx, ny)
         lat.step(2)
